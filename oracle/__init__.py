@@ -1,0 +1,268 @@
+"""FP64 CPU oracle for GMP features (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  It wraps ``gmp_oracle.c`` (plain C,
+built with gcc, no FMA contraction, no fast-math) through ctypes and shares
+nothing with the HIP library.
+
+Every function here follows the definitions written at the top of
+``gmp_oracle.c``: the closed-form Gaussian-product overlap of a solid
+Maxwell-Cartesian harmonic probe with Gaussian density primitives, the
+per-width cutoff inferred from the overlap threshold, the brute-force
+neighbour set over periodic images, and the weighted root-sum-square
+feature (GMP-Featurizer, arXiv 2303.12980, section "Examples").
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gmp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CFLAGS = ["-O3", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (x86-64 baseline ISA, portable across hosts)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            L = ctypes.CDLL(_LIB)
+            dp = ctypes.POINTER(ctypes.c_double)
+            ip = ctypes.POINTER(ctypes.c_int32)
+            lp = ctypes.POINTER(ctypes.c_int64)
+            c_int, c_dbl, c_i64 = ctypes.c_int, ctypes.c_double, ctypes.c_int64
+            L.oracle_cutoffs.argtypes = [c_int, dp, c_int, ip, dp, dp, c_dbl, dp]
+            L.oracle_cutoffs.restype = c_int
+            L.oracle_wrap.argtypes = [c_int, dp, dp, c_int, dp, ip]
+            L.oracle_wrap.restype = c_int
+            L.oracle_neighbors.argtypes = [c_int, dp, ip, dp, c_int, c_int, dp, c_int, c_i64,
+                                           ip, ip, dp, ip, ip]
+            L.oracle_neighbors.restype = c_i64
+            probe_args = [c_int, ip, c_int, dp, c_int, ip, dp, dp, c_dbl]
+            L.oracle_features.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp]
+            L.oracle_features.restype = c_int
+            L.oracle_grad.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, dp, dp, dp, dp]
+            L.oracle_grad.restype = c_int
+            L.oracle_loss_frozen.argtypes = [c_int, dp, ip, dp, *probe_args, lp, ip, ip, dp, dp, dp]
+            L.oracle_loss_frozen.restype = c_int
+            L.oracle_solid_harmonic.argtypes = [c_int, c_int, c_int, c_int, dp, dp, dp]
+            L.oracle_solid_harmonic.restype = None
+            L.oracle_radial.argtypes = [c_int, c_dbl, c_int, dp, dp, c_int, dp, dp]
+            L.oracle_radial.restype = None
+            _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _l(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _check(st):
+    if st != 0:
+        raise OracleError(f"oracle status {st}")
+
+
+def _probe_args(probes):
+    keep = []
+    o, op = _i(probes.orders); keep.append(o)
+    s, sp = _d(probes.sigmas); keep.append(s)
+    po, pop = _i(probes.prim_offsets); keep.append(po)
+    B, Bp = _d(probes.B); keep.append(B)
+    be, bep = _d(probes.beta); keep.append(be)
+    args = [len(o), op, len(s), sp, len(po) - 1, pop, Bp, bep, float(probes.tau)]
+    return keep, args
+
+
+def n_components(orders: Sequence[int]) -> int:
+    return int(sum((l + 1) * (l + 2) // 2 for l in orders))
+
+
+def cutoffs(probes) -> np.ndarray:
+    """rc(sigma)^2 for every sigma."""
+    keep, a = _probe_args(probes)
+    rc2 = np.zeros(len(probes.sigmas))
+    _, rp = _d(rc2)
+    _check(lib().oracle_cutoffs(a[2], a[3], a[4], a[5], a[6], a[7], a[8],
+                                rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return rc2
+
+
+def wrap(pos, cell, pbc):
+    pos, pp = _d(pos)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    n = len(pos)
+    rw = np.zeros((n, 3))
+    m = np.zeros((n, 3), dtype=np.int32)
+    _check(lib().oracle_wrap(n, pp, cp, int(pbc), rw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return rw, m
+
+
+def neighbors(struct, rc2, centre: int):
+    """Canonical neighbour list of one centre: dict with j, n [k,3], q, shell."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    rc2, rp = _d(rc2)
+    st = ctypes.c_int32(0)
+    cap = 1024
+    while True:
+        j = np.zeros(cap, np.int32); n = np.zeros((cap, 3), np.int32)
+        q = np.zeros(cap); sh = np.zeros(cap, np.int32)
+        cnt = lib().oracle_neighbors(len(pos), pp, sp, cp, int(pbc), len(rc2), rp, int(centre), cap,
+                                     j.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     ctypes.byref(st))
+        _check(st.value)
+        if cnt <= cap:
+            return dict(j=j[:cnt], n=n[:cnt], q=q[:cnt], shell=sh[:cnt],
+                        e=np.asarray(spec)[j[:cnt]])
+        cap = int(cnt)
+
+
+def features(struct, probes, centres: Optional[Sequence[int]] = None, with_mu: bool = False):
+    """F [n_centres, n_orders*n_sigmas] (order-major) and optionally mu
+    [n_centres, sum_o ncomp(l_o)*n_sigmas] laid out (order, sigma, component)."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    keep, a = _probe_args(probes)
+    if centres is None:
+        nc, cptr, carr = -1, None, None
+        ncent = len(pos)
+    else:
+        carr, cptr = _i(np.asarray(centres))
+        nc = ncent = len(carr)
+    nf = len(probes.orders) * len(probes.sigmas)
+    F = np.zeros((ncent, nf))
+    ncomp = n_components(probes.orders) * len(probes.sigmas)
+    mu = np.zeros((ncent, ncomp)) if with_mu else None
+    _check(lib().oracle_features(len(pos), pp, sp, cp, int(pbc), *a, nc, cptr,
+                                 F.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if with_mu else None))
+    return (F, mu) if with_mu else F
+
+
+def features_batch(batch, probes, with_mu=False):
+    Fs, mus = [], []
+    for s in range(batch.n_structs):
+        r = features(batch.structure(s), probes, with_mu=with_mu)
+        if with_mu:
+            Fs.append(r[0]); mus.append(r[1])
+        else:
+            Fs.append(r)
+    F = np.concatenate(Fs, axis=0)
+    return (F, np.concatenate(mus, axis=0)) if with_mu else F
+
+
+def grad(struct, probes, G):
+    """Analytic dL/dR [n,3] and dL/dcell [3,3] of L = sum G*F, plus F."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    keep, a = _probe_args(probes)
+    G, gp = _d(G)
+    n = len(pos)
+    gpos = np.zeros((n, 3)); gcell = np.zeros((3, 3))
+    F = np.zeros((n, len(probes.orders) * len(probes.sigmas)))
+    _check(lib().oracle_grad(n, pp, sp, cp, int(pbc), *a, gp,
+                             gpos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             gcell.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             F.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return gpos, gcell, F
+
+
+def frozen_pairs(struct, probes):
+    """Pair list of the current configuration in raw-position form (j, n~, q),
+    for finite differences with the pair set held fixed."""
+    pos, spec, cell, pbc = struct
+    rc2 = cutoffs(probes)
+    _, m = wrap(pos, cell, pbc)
+    po = [0]; pj = []; pn = []; pq = []
+    for i in range(len(pos)):
+        nb = neighbors(struct, rc2, i)
+        pj.append(nb["j"])
+        pn.append(nb["n"] - m[nb["j"]] + m[i])
+        pq.append(nb["q"])
+        po.append(po[-1] + len(nb["j"]))
+    return (np.asarray(po, np.int64), np.concatenate(pj).astype(np.int32),
+            np.concatenate(pn).astype(np.int32), np.concatenate(pq))
+
+
+def loss_frozen(struct, probes, G, pairs):
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    keep, a = _probe_args(probes)
+    po, pop = _l(pairs[0]); pj, pjp = _i(pairs[1]); pn, pnp = _i(pairs[2]); pq, pqp = _d(pairs[3])
+    G, gp = _d(G)
+    out = ctypes.c_double(0.0)
+    _check(lib().oracle_loss_frozen(len(pos), pp, sp, cp, *a, pop, pjp, pnp, pqp, gp, ctypes.byref(out)))
+    return out.value
+
+
+def solid_harmonic(a: int, b: int, c: int, pts):
+    pts, p = _d(np.asarray(pts).reshape(-1, 3))
+    v = np.zeros(len(pts)); g = np.zeros((len(pts), 3))
+    lib().oracle_solid_harmonic(a, b, c, len(pts), p, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return v, g
+
+
+def radial(l: int, sigma: float, B, beta, q):
+    B, Bp = _d(B); beta, bp = _d(beta); q, qp = _d(np.atleast_1d(q))
+    out = np.zeros(len(q))
+    lib().oracle_radial(int(l), float(sigma), len(B), Bp, bp, len(q), qp,
+                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def components(l: int):
+    """(a, b, c) of order l in the oracle's component order."""
+    out = []
+    for a in range(l, -1, -1):
+        for b in range(l - a, -1, -1):
+            out.append((a, b, l - a - b))
+    return out

@@ -1,0 +1,667 @@
+/*
+ * Plain FP64 CPU oracle for Gaussian Multipole (GMP) features.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or helper
+ * with the HIP library.
+ *
+ * What it computes (the method of GMP-Featurizer, arXiv 2303.12980, section
+ * "Examples": features are the Cartesian product of MCSH angular orders and
+ * Gaussian radial widths, order-major; the cutoff is inferred from the
+ * overlap threshold; derivatives are taken with respect to atom positions):
+ *
+ *   probe        G_s(u) = (2 pi s^2)^(-3/2) exp(-|u|^2 / (2 s^2)),  alpha = 1/(2 s^2)
+ *   angular      P_abc(u) = (-1)^l |u|^(2l+1) d^a_x d^b_y d^c_z (1/|u|),  a+b+c = l
+ *   density      rho_i(r) = sum_{(j,n)} sum_k B_{e_j,k} exp(-beta_{e_j,k} |r - R_j - n.cell|^2)
+ *   component    mu_{i,l,s,abc} = int rho_i(r) P_abc(r - R_i) G_s(r - R_i) d^3r
+ *              = sum_{(j,n)} c_{l,s,e_j}(|d|^2) P_abc(d),   d = R_j + n.cell - R_i
+ *   radial       c_{l,s,e}(q) = sum_k B (alpha/lam)^(3/2) (beta/lam)^l exp(-gam q),
+ *                lam = alpha + beta, gam = alpha beta / lam
+ *   feature      F_{i,l,s} = sqrt( sum_{a+b+c=l} l!/(a!b!c!) mu_{i,l,s,abc}^2 )
+ *   cutoff       rc(s)^2 = max over elements, primitives of ln(|A0|/tau)/gam,
+ *                A0 = B (alpha/lam)^(3/2); 0 when |A0| <= tau
+ *
+ * The closed form follows from the Gaussian product theorem and the mean
+ * value property of harmonic polynomials; the test suite pins it against
+ * brute-force quadrature of the integral.
+ *
+ * Neighbour set and its floating-point operation order (no FMA contraction:
+ * build with -ffp-contract=off):
+ *   reciprocal rows b1 = (a2 x a3)/V, b2 = (a3 x a1)/V, b3 = (a1 x a2)/V, V = a1.(a2 x a3)
+ *   f_k  = (x b_k.x + y b_k.y) + z b_k.z ;  m_k = floor(f_k) on periodic axes, else 0
+ *   Rw   = R - ((m1 a1 + m2 a2) + m3 a3)
+ *   s(n) = (n1 a1 + n2 a2) + n3 a3
+ *   d    = (Rw_j - Rw_i) + s(n) ;  q = (d.x^2 + d.y^2) + d.z^2
+ *   (j, n) is a neighbour of i when q <= max_s rc(s)^2, n ranging over Z^3 on
+ *   periodic axes (the centre itself and its own images included).
+ *   shell(q) = number of sigmas with rc(s)^2 < q; sigma s uses the pairs with
+ *   q <= rc(s)^2.
+ *   Canonical order: ascending (species of j, shell, j, n1, n2, n3).
+ *
+ * Gradient of L = sum G_{i,l,s} F_{i,l,s} with the pair set held fixed:
+ *   W = G w_abc mu / F (0 when F = 0);  v_{ijn} = sum W grad_d[c(q) P(d)]
+ *   dL/dR_j += v, dL/dR_i -= v, dL/da_m += (n_m - m_j,m + m_i,m) v.
+ * The derivative of c(q) P(d) is taken with forward-mode dual numbers.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_INVALID 1
+#define OR_E_CELL 3
+#define OR_E_CAPACITY 4
+
+/* ------------------------------------------------------------------ */
+/* dual numbers: value and gradient with respect to d = (x, y, z)      */
+/* ------------------------------------------------------------------ */
+typedef struct { double v, g[3]; } dual;
+
+static dual dconst(double c) { dual r = {c, {0.0, 0.0, 0.0}}; return r; }
+static dual dvar(double v, int k) { dual r = dconst(v); r.g[k] = 1.0; return r; }
+static dual dadd(dual a, dual b) {
+  dual r; r.v = a.v + b.v;
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] + b.g[k];
+  return r;
+}
+static dual dsub(dual a, dual b) {
+  dual r; r.v = a.v - b.v;
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] - b.g[k];
+  return r;
+}
+static dual dmul(dual a, dual b) {
+  dual r; r.v = a.v * b.v;
+  for (int k = 0; k < 3; ++k) r.g[k] = a.g[k] * b.v + a.v * b.g[k];
+  return r;
+}
+static dual dscale(double c, dual a) {
+  dual r; r.v = c * a.v;
+  for (int k = 0; k < 3; ++k) r.g[k] = c * a.g[k];
+  return r;
+}
+static dual dexp(dual a) {
+  dual r; r.v = exp(a.v);
+  for (int k = 0; k < 3; ++k) r.g[k] = r.v * a.g[k];
+  return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* Solid Maxwell-Cartesian harmonics P_abc, written out per exponent    */
+/* pattern.  u, s, t are the coordinates sorted by descending exponent. */
+/* ------------------------------------------------------------------ */
+static dual solid_harmonic(int a, int b, int c, dual x, dual y, dual z) {
+  int e[3] = {a, b, c};
+  dual v[3] = {x, y, z};
+  /* stable sort of the three (exponent, variable) pairs, descending */
+  for (int i = 1; i < 3; ++i)
+    for (int k = i; k > 0 && e[k] > e[k - 1]; --k) {
+      int te = e[k]; e[k] = e[k - 1]; e[k - 1] = te;
+      dual tv = v[k]; v[k] = v[k - 1]; v[k - 1] = tv;
+    }
+  dual u = v[0], s = v[1], t = v[2];
+  dual r2 = dadd(dadd(dmul(x, x), dmul(y, y)), dmul(z, z));
+  dual u2 = dmul(u, u);
+  int p = e[0] * 100 + e[1] * 10 + e[2];
+  switch (p) {
+    case 0:   return dconst(1.0);
+    case 100: return u;
+    case 200: return dsub(dscale(3.0, u2), r2);                     /* 3u^2 - r^2 */
+    case 110: return dscale(3.0, dmul(u, s));                       /* 3us */
+    case 300: return dsub(dscale(15.0, dmul(u2, u)),                /* 15u^3 - 9u r^2 */
+                          dscale(9.0, dmul(u, r2)));
+    case 210: return dsub(dscale(15.0, dmul(u2, s)),                /* 15u^2 s - 3 s r^2 */
+                          dscale(3.0, dmul(s, r2)));
+    case 111: return dscale(15.0, dmul(dmul(u, s), t));             /* 15ust */
+    case 400: {                                                     /* 105u^4 - 90u^2 r^2 + 9r^4 */
+      dual a4 = dscale(105.0, dmul(u2, u2));
+      dual b4 = dscale(90.0, dmul(u2, r2));
+      dual c4 = dscale(9.0, dmul(r2, r2));
+      return dadd(dsub(a4, b4), c4);
+    }
+    case 310:                                                       /* 105u^3 s - 45 u s r^2 */
+      return dsub(dscale(105.0, dmul(dmul(u2, u), s)), dscale(45.0, dmul(dmul(u, s), r2)));
+    case 220: {                                                     /* 105u^2s^2 - 15u^2r^2 - 15s^2r^2 + 3r^4 */
+      dual s2 = dmul(s, s);
+      dual a4 = dscale(105.0, dmul(u2, s2));
+      dual b4 = dscale(15.0, dmul(u2, r2));
+      dual c4 = dscale(15.0, dmul(s2, r2));
+      dual d4 = dscale(3.0, dmul(r2, r2));
+      return dadd(dsub(dsub(a4, b4), c4), d4);
+    }
+    case 211:                                                       /* 105u^2 s t - 15 s t r^2 */
+      return dsub(dscale(105.0, dmul(u2, dmul(s, t))), dscale(15.0, dmul(dmul(s, t), r2)));
+    default:  return dconst(NAN);
+  }
+}
+
+static int ncomp(int l) { return (l + 1) * (l + 2) / 2; }
+
+/* components of order l in the order (a desc, then b desc) */
+static void comp_abc(int l, int idx, int *a, int *b, int *c) {
+  int k = 0;
+  for (int aa = l; aa >= 0; --aa)
+    for (int bb = l - aa; bb >= 0; --bb) {
+      if (k == idx) { *a = aa; *b = bb; *c = l - aa - bb; return; }
+      ++k;
+    }
+}
+
+static double factorial(int n) { double f = 1.0; for (int i = 2; i <= n; ++i) f *= i; return f; }
+
+static double comp_weight(int a, int b, int c) {
+  return factorial(a + b + c) / (factorial(a) * factorial(b) * factorial(c));
+}
+
+/* ------------------------------------------------------------------ */
+/* probes and cutoffs                                                  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int n_orders; const int32_t *orders;
+  int n_sigmas; const double *sigmas;
+  int n_elements; const int32_t *prim_offsets;
+  const double *B, *beta;
+  double tau;
+} probes_t;
+
+int oracle_cutoffs(int n_sigmas, const double *sigmas, int n_elements,
+                   const int32_t *prim_offsets, const double *B, const double *beta,
+                   double tau, double *rc2) {
+  if (!(tau > 0.0)) return OR_E_INVALID;
+  for (int s = 0; s < n_sigmas; ++s) {
+    double sg = sigmas[s];
+    if (!(sg > 0.0)) return OR_E_INVALID;
+    double alpha = 1.0 / (2.0 * sg * sg);
+    double best = 0.0;
+    for (int e = 0; e < n_elements; ++e)
+      for (int k = prim_offsets[e]; k < prim_offsets[e + 1]; ++k) {
+        if (!(beta[k] > 0.0)) return OR_E_INVALID;
+        double lam = alpha + beta[k];
+        double gam = alpha * beta[k] / lam;
+        double A0 = fabs(B[k]) * pow(alpha / lam, 1.5);
+        if (A0 <= tau) continue;
+        double r2 = log(A0 / tau) / gam;
+        if (r2 > best) best = r2;
+      }
+    rc2[s] = best;
+  }
+  return OR_OK;
+}
+
+/* radial factor c_{l,s,e}(q) as a dual number in d */
+static dual radial(const probes_t *P, int l, int s, int e, dual q) {
+  double sg = P->sigmas[s];
+  double alpha = 1.0 / (2.0 * sg * sg);
+  dual acc = dconst(0.0);
+  for (int k = P->prim_offsets[e]; k < P->prim_offsets[e + 1]; ++k) {
+    double lam = alpha + P->beta[k];
+    double gam = alpha * P->beta[k] / lam;
+    double A = P->B[k] * pow(alpha / lam, 1.5) * pow(P->beta[k] / lam, (double)l);
+    acc = dadd(acc, dscale(A, dexp(dscale(-gam, q))));
+  }
+  return acc;
+}
+
+/* ------------------------------------------------------------------ */
+/* lattice                                                             */
+/* ------------------------------------------------------------------ */
+static void cross3(const double *a, const double *b, double *c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double *a, const double *b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+/* reciprocal rows; returns 0 on success, OR_E_CELL for a singular cell */
+static int reciprocal(const double *cell, double *b /* 9 */) {
+  const double *a1 = cell, *a2 = cell + 3, *a3 = cell + 6;
+  double c23[3], c31[3], c12[3];
+  cross3(a2, a3, c23); cross3(a3, a1, c31); cross3(a1, a2, c12);
+  double V = dot3(a1, c23);
+  if (!(fabs(V) > 0.0) || !isfinite(V)) return OR_E_CELL;
+  for (int k = 0; k < 3; ++k) { b[k] = c23[k] / V; b[3 + k] = c31[k] / V; b[6 + k] = c12[k] / V; }
+  return OR_OK;
+}
+
+/* Wrap every atom into the home cell along periodic axes. */
+int oracle_wrap(int n_atoms, const double *pos, const double *cell, int pbc,
+                double *rw, int32_t *m) {
+  double b[9];
+  if (pbc) { int st = reciprocal(cell, b); if (st) return st; }
+  for (int i = 0; i < n_atoms; ++i) {
+    const double *R = pos + 3 * i;
+    int mi[3] = {0, 0, 0};
+    if (pbc)
+      for (int k = 0; k < 3; ++k)
+        if (pbc & (1 << k)) {
+          double f = dot3(R, b + 3 * k);
+          if (!isfinite(f)) return OR_E_INVALID;
+          mi[k] = (int)floor(f);
+        }
+    for (int c = 0; c < 3; ++c) {
+      double t = (double)mi[0] * cell[c] + (double)mi[1] * cell[3 + c];
+      t = t + (double)mi[2] * cell[6 + c];
+      rw[3 * i + c] = R[c] - (pbc ? t : 0.0);
+    }
+    m[3 * i + 0] = mi[0]; m[3 * i + 1] = mi[1]; m[3 * i + 2] = mi[2];
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* neighbours of one centre, by brute force over atoms and images      */
+/* ------------------------------------------------------------------ */
+typedef struct { int32_t e, shell, j, n[3]; double q, d[3]; } pair_t;
+
+static int pair_cmp(const void *pa, const void *pb) {
+  const pair_t *x = (const pair_t *)pa, *y = (const pair_t *)pb;
+  if (x->e != y->e) return x->e < y->e ? -1 : 1;
+  if (x->shell != y->shell) return x->shell < y->shell ? -1 : 1;
+  if (x->j != y->j) return x->j < y->j ? -1 : 1;
+  for (int k = 0; k < 3; ++k)
+    if (x->n[k] != y->n[k]) return x->n[k] < y->n[k] ? -1 : 1;
+  return 0;
+}
+
+typedef struct {
+  int n_atoms; const double *rw; const int32_t *species; const double *cell; int pbc;
+  int nimg[3];
+} sys_t;
+
+static int image_reach(const double *cell, int pbc, double rcmax, int nimg[3]) {
+  nimg[0] = nimg[1] = nimg[2] = 0;
+  if (!pbc) return OR_OK;
+  double b[9];
+  int st = reciprocal(cell, b);
+  if (st) return st;
+  for (int k = 0; k < 3; ++k)
+    if (pbc & (1 << k)) {
+      double inv_h = sqrt(dot3(b + 3 * k, b + 3 * k));
+      double r = floor(rcmax * inv_h) + 2.0;
+      if (!(r < 1.0e6)) return OR_E_INVALID;
+      nimg[k] = (int)r;
+    }
+  return OR_OK;
+}
+
+/* collect the sorted neighbour list of centre i into a malloc'd array */
+static int64_t collect(const sys_t *S, int i, int n_sigmas, const double *rc2, pair_t **out) {
+  double rcmax2 = 0.0;
+  for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  int64_t cap = 256, n = 0;
+  pair_t *buf = (pair_t *)malloc(sizeof(pair_t) * cap);
+  const double *Ri = S->rw + 3 * i;
+  const double *a1 = S->cell, *a2 = S->cell + 3, *a3 = S->cell + 6;
+  for (int n1 = -S->nimg[0]; n1 <= S->nimg[0]; ++n1)
+    for (int n2 = -S->nimg[1]; n2 <= S->nimg[1]; ++n2)
+      for (int n3 = -S->nimg[2]; n3 <= S->nimg[2]; ++n3) {
+        double sh[3];
+        for (int c = 0; c < 3; ++c) {
+          if (S->pbc) {
+            double t = (double)n1 * a1[c] + (double)n2 * a2[c];
+            sh[c] = t + (double)n3 * a3[c];
+          } else {
+            sh[c] = 0.0;
+          }
+        }
+        for (int j = 0; j < S->n_atoms; ++j) {
+          const double *Rj = S->rw + 3 * j;
+          double d[3];
+          for (int c = 0; c < 3; ++c) d[c] = (Rj[c] - Ri[c]) + sh[c];
+          double q = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+          if (!(q <= rcmax2)) continue;
+          if (n == cap) { cap *= 2; buf = (pair_t *)realloc(buf, sizeof(pair_t) * cap); }
+          pair_t *p = buf + n++;
+          p->e = S->species[j]; p->j = j;
+          p->n[0] = n1; p->n[1] = n2; p->n[2] = n3;
+          p->q = q; p->d[0] = d[0]; p->d[1] = d[1]; p->d[2] = d[2];
+          int sh_ = 0;
+          for (int s = 0; s < n_sigmas; ++s) if (rc2[s] < q) ++sh_;
+          p->shell = sh_;
+        }
+      }
+  qsort(buf, (size_t)n, sizeof(pair_t), pair_cmp);
+  *out = buf;
+  return n;
+}
+
+static int make_sys(sys_t *S, int n_atoms, const double *pos, const int32_t *species,
+                    const double *cell, int pbc, double rcmax2, double **rw_out, int32_t **m_out) {
+  double *rw = (double *)malloc(sizeof(double) * 3 * (n_atoms > 0 ? n_atoms : 1));
+  int32_t *m = (int32_t *)malloc(sizeof(int32_t) * 3 * (n_atoms > 0 ? n_atoms : 1));
+  int st = oracle_wrap(n_atoms, pos, cell, pbc, rw, m);
+  if (!st) st = image_reach(cell, pbc, sqrt(rcmax2), S->nimg);
+  if (st) { free(rw); free(m); return st; }
+  S->n_atoms = n_atoms; S->rw = rw; S->species = species; S->cell = cell; S->pbc = pbc;
+  *rw_out = rw; *m_out = m;
+  return OR_OK;
+}
+
+/*
+ * Canonical neighbour list of one centre.  Writes up to `cap` entries and
+ * returns the full count (a count larger than `cap` means truncated).
+ * out_n is [cap*3], shifts relative to the wrapped positions.
+ */
+int64_t oracle_neighbors(int n_atoms, const double *pos, const int32_t *species,
+                         const double *cell, int pbc, int n_sigmas, const double *rc2,
+                         int centre, int64_t cap, int32_t *out_j, int32_t *out_n,
+                         double *out_q, int32_t *out_shell, int32_t *status) {
+  double rcmax2 = 0.0;
+  for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw; int32_t *m;
+  *status = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (*status) return 0;
+  pair_t *P;
+  int64_t n = collect(&S, centre, n_sigmas, rc2, &P);
+  for (int64_t k = 0; k < n && k < cap; ++k) {
+    out_j[k] = P[k].j;
+    out_n[3 * k] = P[k].n[0]; out_n[3 * k + 1] = P[k].n[1]; out_n[3 * k + 2] = P[k].n[2];
+    out_q[k] = P[k].q; out_shell[k] = P[k].shell;
+  }
+  free(P); free(rw); free(m);
+  return n;
+}
+
+/* ------------------------------------------------------------------ */
+/* features                                                            */
+/* ------------------------------------------------------------------ */
+static int total_comps(const probes_t *P) {
+  int t = 0;
+  for (int o = 0; o < P->n_orders; ++o) t += ncomp(P->orders[o]);
+  return t;
+}
+
+static int check_probes(const probes_t *P) {
+  if (P->n_orders < 1 || P->n_sigmas < 1 || P->n_elements < 1) return OR_E_INVALID;
+  for (int o = 0; o < P->n_orders; ++o)
+    if (P->orders[o] < 0 || P->orders[o] > 4) return OR_E_INVALID;
+  return OR_OK;
+}
+
+/* mu and F for centre i from its pair list; mu layout [order][sigma][comp] */
+static void centre_features(const probes_t *P, const pair_t *pairs, int64_t np,
+                            const double *rc2, double *mu, double *F) {
+  int nc = total_comps(P);
+  memset(mu, 0, sizeof(double) * (size_t)nc * P->n_sigmas);
+  for (int64_t p = 0; p < np; ++p) {
+    const pair_t *pp = pairs + p;
+    dual x = dconst(pp->d[0]), y = dconst(pp->d[1]), z = dconst(pp->d[2]);
+    dual q = dconst(pp->q);
+    int off = 0;
+    for (int o = 0; o < P->n_orders; ++o) {
+      int l = P->orders[o];
+      for (int s = 0; s < P->n_sigmas; ++s) {
+        if (!(pp->q <= rc2[s])) continue;
+        double c = radial(P, l, s, pp->e, q).v;
+        for (int k = 0; k < ncomp(l); ++k) {
+          int a, b, cc; comp_abc(l, k, &a, &b, &cc);
+          mu[(size_t)(off + s * ncomp(l) + k)] += c * solid_harmonic(a, b, cc, x, y, z).v;
+        }
+      }
+      off += P->n_sigmas * ncomp(l);
+    }
+  }
+  int off = 0;
+  for (int o = 0; o < P->n_orders; ++o) {
+    int l = P->orders[o];
+    for (int s = 0; s < P->n_sigmas; ++s) {
+      double acc = 0.0;
+      for (int k = 0; k < ncomp(l); ++k) {
+        int a, b, cc; comp_abc(l, k, &a, &b, &cc);
+        double v = mu[off + s * ncomp(l) + k];
+        acc += comp_weight(a, b, cc) * v * v;
+      }
+      F[o * P->n_sigmas + s] = sqrt(acc);
+    }
+    off += P->n_sigmas * ncomp(l);
+  }
+}
+
+/*
+ * Features of the listed centres of one structure (all centres when
+ * n_centres < 0).  F is [n_centres][n_orders*n_sigmas]; mu (optional) is
+ * [n_centres][sum_o ncomp(l_o) * n_sigmas] in (order, sigma, component) order.
+ */
+int oracle_features(int n_atoms, const double *pos, const int32_t *species,
+                    const double *cell, int pbc,
+                    int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                    int n_elements, const int32_t *prim_offsets, const double *B,
+                    const double *beta, double tau,
+                    int n_centres, const int32_t *centres, double *F, double *mu) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  int st = check_probes(&P);
+  if (st) return st;
+  for (int i = 0; i < n_atoms; ++i)
+    if (species[i] < 0 || species[i] >= n_elements) return OR_E_INVALID;
+  double *rc2 = (double *)malloc(sizeof(double) * n_sigmas);
+  st = oracle_cutoffs(n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, rc2);
+  double rcmax2 = 0.0;
+  for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw = NULL; int32_t *m = NULL;
+  if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (st) { free(rc2); return st; }
+  int nc = total_comps(&P);
+  int ncent = n_centres < 0 ? n_atoms : n_centres;
+  int nf = n_orders * n_sigmas;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < ncent; ++t) {
+    int i = n_centres < 0 ? t : centres[t];
+    pair_t *pairs;
+    int64_t np = collect(&S, i, n_sigmas, rc2, &pairs);
+    double *mu_i = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
+    centre_features(&P, pairs, np, rc2, mu_i, F + (size_t)t * nf);
+    if (mu) memcpy(mu + (size_t)t * nc * n_sigmas, mu_i, sizeof(double) * (size_t)nc * n_sigmas);
+    free(mu_i); free(pairs);
+  }
+  free(rc2); free(rw); free(m);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* gradient of L = sum G F                                             */
+/* ------------------------------------------------------------------ */
+/* v = sum_{o,s,c} W grad_d[c_{l,s}(q) P_c(d)] for one pair */
+static void pair_v(const probes_t *P, const pair_t *pp, const double *rc2, const double *W,
+                   double v[3]) {
+  dual x = dvar(pp->d[0], 0), y = dvar(pp->d[1], 1), z = dvar(pp->d[2], 2);
+  dual q = dadd(dadd(dmul(x, x), dmul(y, y)), dmul(z, z));
+  v[0] = v[1] = v[2] = 0.0;
+  int off = 0;
+  for (int o = 0; o < P->n_orders; ++o) {
+    int l = P->orders[o];
+    for (int s = 0; s < P->n_sigmas; ++s) {
+      if (!(pp->q <= rc2[s])) continue;
+      dual c = radial(P, l, s, pp->e, q);
+      for (int k = 0; k < ncomp(l); ++k) {
+        int a, b, cc; comp_abc(l, k, &a, &b, &cc);
+        double w = W[off + s * ncomp(l) + k];
+        if (w == 0.0) continue;
+        dual t = dmul(c, solid_harmonic(a, b, cc, x, y, z));
+        v[0] += w * t.g[0]; v[1] += w * t.g[1]; v[2] += w * t.g[2];
+      }
+    }
+    off += P->n_sigmas * ncomp(l);
+  }
+}
+
+static void make_W(const probes_t *P, const double *mu, const double *F, const double *G, double *W) {
+  int off = 0;
+  for (int o = 0; o < P->n_orders; ++o) {
+    int l = P->orders[o];
+    for (int s = 0; s < P->n_sigmas; ++s) {
+      double f = F[o * P->n_sigmas + s];
+      double g = G[o * P->n_sigmas + s];
+      for (int k = 0; k < ncomp(l); ++k) {
+        int a, b, cc; comp_abc(l, k, &a, &b, &cc);
+        int idx = off + s * ncomp(l) + k;
+        W[idx] = f > 0.0 ? g * comp_weight(a, b, cc) * mu[idx] / f : 0.0;
+      }
+    }
+    off += P->n_sigmas * ncomp(l);
+  }
+}
+
+/*
+ * Analytic gradient of L = sum_{i,o,s} G[i][o*S+s] F[i][o*S+s] for one
+ * structure.  grad_pos [n_atoms*3], grad_cell [9] (row m = d/d a_m).
+ * Also returns F [n_atoms*nf] when F_out is not NULL.
+ */
+int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
+                const double *cell, int pbc,
+                int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                int n_elements, const int32_t *prim_offsets, const double *B,
+                const double *beta, double tau,
+                const double *G, double *grad_pos, double *grad_cell, double *F_out) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  int st = check_probes(&P);
+  if (st) return st;
+  for (int i = 0; i < n_atoms; ++i)
+    if (species[i] < 0 || species[i] >= n_elements) return OR_E_INVALID;
+  double *rc2 = (double *)malloc(sizeof(double) * n_sigmas);
+  st = oracle_cutoffs(n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, rc2);
+  double rcmax2 = 0.0;
+  for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw = NULL; int32_t *m = NULL;
+  if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (st) { free(rc2); return st; }
+  int nc = total_comps(&P);
+  int nf = n_orders * n_sigmas;
+  memset(grad_pos, 0, sizeof(double) * 3 * n_atoms);
+  memset(grad_cell, 0, sizeof(double) * 9);
+  double *mu = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
+  double *W = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
+  double *Fi = (double *)malloc(sizeof(double) * nf);
+  for (int i = 0; i < n_atoms; ++i) {
+    pair_t *pairs;
+    int64_t np = collect(&S, i, n_sigmas, rc2, &pairs);
+    centre_features(&P, pairs, np, rc2, mu, Fi);
+    if (F_out) memcpy(F_out + (size_t)i * nf, Fi, sizeof(double) * nf);
+    make_W(&P, mu, Fi, G + (size_t)i * nf, W);
+    for (int64_t p = 0; p < np; ++p) {
+      double v[3];
+      pair_v(&P, pairs + p, rc2, W, v);
+      int j = pairs[p].j;
+      for (int k = 0; k < 3; ++k) { grad_pos[3 * j + k] += v[k]; grad_pos[3 * i + k] -= v[k]; }
+      for (int a = 0; a < 3; ++a) {
+        double nt = (double)(pairs[p].n[a] - m[3 * j + a] + m[3 * i + a]);
+        for (int k = 0; k < 3; ++k) grad_cell[3 * a + k] += nt * v[k];
+      }
+    }
+    free(pairs);
+  }
+  free(mu); free(W); free(Fi); free(rc2); free(rw); free(m);
+  return OR_OK;
+}
+
+/*
+ * L = sum G F evaluated over a FROZEN pair set, for finite differences that
+ * do not see cutoff crossings.  Pairs of centre i are
+ * pj[po[i]..po[i+1]), with raw-position image shifts pn (3 ints each,
+ * d = R_j - R_i + pn.cell) and base squared distances pq deciding which
+ * sigmas use each pair (q_base <= rc2[s]).
+ */
+int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
+                       const double *cell,
+                       int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                       int n_elements, const int32_t *prim_offsets, const double *B,
+                       const double *beta, double tau,
+                       const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
+                       const double *G, double *L_out) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  int st = check_probes(&P);
+  if (st) return st;
+  double *rc2 = (double *)malloc(sizeof(double) * n_sigmas);
+  st = oracle_cutoffs(n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, rc2);
+  if (st) { free(rc2); return st; }
+  int nc = total_comps(&P);
+  int nf = n_orders * n_sigmas;
+  double L = 0.0;
+  double *mu = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
+  double *Fi = (double *)malloc(sizeof(double) * nf);
+  for (int i = 0; i < n_atoms; ++i) {
+    int64_t np = po[i + 1] - po[i];
+    pair_t *pairs = (pair_t *)malloc(sizeof(pair_t) * (np > 0 ? np : 1));
+    for (int64_t p = 0; p < np; ++p) {
+      int64_t g = po[i] + p;
+      int j = pj[g];
+      pair_t *pp = pairs + p;
+      pp->j = j; pp->e = species[j];
+      for (int c = 0; c < 3; ++c) {
+        double sh = (double)pn[3 * g] * cell[c] + (double)pn[3 * g + 1] * cell[3 + c] +
+                    (double)pn[3 * g + 2] * cell[6 + c];
+        pp->d[c] = (pos[3 * j + c] - pos[3 * i + c]) + sh;
+      }
+      double qq = (pp->d[0] * pp->d[0] + pp->d[1] * pp->d[1]) + pp->d[2] * pp->d[2];
+      /* membership from the base configuration: rc2 test on pq, value from qq */
+      pp->q = qq;
+      pp->shell = 0;
+      for (int s = 0; s < n_sigmas; ++s) if (rc2[s] < pq[g]) ++pp->shell;
+    }
+    /* evaluate with the frozen membership: a sigma uses the pair when pq <= rc2 */
+    memset(mu, 0, sizeof(double) * (size_t)nc * n_sigmas);
+    for (int64_t p = 0; p < np; ++p) {
+      const pair_t *pp = pairs + p;
+      double qb = pq[po[i] + p];
+      dual x = dconst(pp->d[0]), y = dconst(pp->d[1]), z = dconst(pp->d[2]);
+      dual q = dconst(pp->q);
+      int off = 0;
+      for (int o = 0; o < n_orders; ++o) {
+        int l = orders[o];
+        for (int s = 0; s < n_sigmas; ++s) {
+          if (!(qb <= rc2[s])) continue;
+          double c = radial(&P, l, s, pp->e, q).v;
+          for (int k = 0; k < ncomp(l); ++k) {
+            int a, b, cc; comp_abc(l, k, &a, &b, &cc);
+            mu[off + s * ncomp(l) + k] += c * solid_harmonic(a, b, cc, x, y, z).v;
+          }
+        }
+        off += n_sigmas * ncomp(l);
+      }
+    }
+    int off = 0;
+    for (int o = 0; o < n_orders; ++o) {
+      int l = orders[o];
+      for (int s = 0; s < n_sigmas; ++s) {
+        double acc = 0.0;
+        for (int k = 0; k < ncomp(l); ++k) {
+          int a, b, cc; comp_abc(l, k, &a, &b, &cc);
+          double v = mu[off + s * ncomp(l) + k];
+          acc += comp_weight(a, b, cc) * v * v;
+        }
+        L += G[(size_t)i * nf + o * n_sigmas + s] * sqrt(acc);
+      }
+      off += n_sigmas * ncomp(l);
+    }
+    free(pairs);
+  }
+  free(mu); free(Fi); free(rc2);
+  *L_out = L;
+  return OR_OK;
+}
+
+/* P_abc and its gradient at npts points (pts [npts*3]); out_g [npts*3] */
+void oracle_solid_harmonic(int a, int b, int c, int npts, const double *pts,
+                           double *out_v, double *out_g) {
+  for (int p = 0; p < npts; ++p) {
+    dual x = dvar(pts[3 * p], 0), y = dvar(pts[3 * p + 1], 1), z = dvar(pts[3 * p + 2], 2);
+    dual r = solid_harmonic(a, b, c, x, y, z);
+    out_v[p] = r.v;
+    if (out_g) { out_g[3 * p] = r.g[0]; out_g[3 * p + 1] = r.g[1]; out_g[3 * p + 2] = r.g[2]; }
+  }
+}
+
+/* c_{l,s,e}(q) at npts values of q (plain value) */
+void oracle_radial(int l, double sigma, int n_prims, const double *B, const double *beta,
+                   int npts, const double *q, double *out) {
+  double alpha = 1.0 / (2.0 * sigma * sigma);
+  for (int p = 0; p < npts; ++p) {
+    double acc = 0.0;
+    for (int k = 0; k < n_prims; ++k) {
+      double lam = alpha + beta[k];
+      double gam = alpha * beta[k] / lam;
+      acc += B[k] * pow(alpha / lam, 1.5) * pow(beta[k] / lam, (double)l) * exp(-gam * q[p]);
+    }
+    out[p] = acc;
+  }
+}
