@@ -1,0 +1,202 @@
+/*
+ * gmp.h -- C ABI of the MI355X (gfx950) Gaussian Multipole feature library.
+ *
+ * The method is the one GMP-Featurizer computes (arXiv 2303.12980): for every
+ * centre atom i, every probe (angular order l of a solid Maxwell-Cartesian
+ * spherical harmonic, Gaussian radial width sigma) and every neighbour j
+ * within the sigma-dependent cutoff (periodic images included), the
+ * closed-form overlap of the probe with each Gaussian primitive
+ * B_k exp(-beta_k |r - R_j|^2) of the neighbour's density is accumulated into
+ * multipole components mu_{i,l,sigma,abc}; the feature is the weighted
+ * root-sum-square F_{i,l,sigma} = sqrt(sum_abc l!/(a!b!c!) mu^2)
+ * ("Examples": probe set = Cartesian product of orders and sigmas, order-major;
+ * cutoff inferred from the overlap threshold; derivatives with respect to the
+ * atom positions on request).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers owned by the caller unless marked [host].
+ *  - Nothing is allocated on the device by any entry point; scratch memory
+ *    is the caller's workspace `ws` of `ws_bytes` bytes (see
+ *    gmp_workspace_size).  The plan owns small constant tables that it
+ *    allocates once in gmp_plan_create.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *    Entry points return after enqueueing, except where a host-visible
+ *    result is requested (n_pairs of gmp_build_neighbors).
+ *  - Errors are reported by status codes only; nothing aborts or prints.
+ *    gmp_last_error() returns a thread-local message for the last non-OK
+ *    status.  Device-side conditions (non-finite coordinates, image shifts
+ *    out of range, list overflow in no-sync mode) are recorded in a status
+ *    word inside `ws` and reported by gmp_build_neighbors when it syncs, or
+ *    by gmp_check_status.
+ */
+#ifndef GMP_H
+#define GMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GMP_OK = 0,
+  GMP_E_INVALID = 1,      /* bad argument: null pointer, order outside 0..4, sigma <= 0, beta <= 0, ... */
+  GMP_E_UNSUPPORTED = 2,  /* valid but outside what the kernels handle (documented limits) */
+  GMP_E_CELL = 3,         /* singular lattice for a structure with a periodic axis */
+  GMP_E_CAPACITY = 4,     /* neighbour capacity too small; required count returned */
+  GMP_E_NONFINITE = 5,    /* non-finite coordinate or lattice entry */
+  GMP_E_HIP = 6,          /* a HIP runtime call failed */
+  GMP_E_NOMEM = 7,        /* host allocation or workspace too small */
+} gmp_status;
+
+/* Arithmetic of the overlap kernels.
+ *  GMP_FP64:              every step in FP64 (exp in FP64).
+ *  GMP_FP32_COMPENSATED:  pair terms (displacement, monomials, exponentials,
+ *                         radial sums, products) in FP32; per-lane component
+ *                         accumulation as an FP32 (hi, lo) pair updated with
+ *                         an error-free two-sum; cross-lane reduction, the
+ *                         moment-to-component map and the norm in FP64.
+ *                         Lattice wrap, image shifts and distances stay FP64. */
+typedef enum { GMP_FP64 = 0, GMP_FP32_COMPENSATED = 1 } gmp_precision;
+
+typedef struct gmp_plan gmp_plan; /* opaque, immutable after creation */
+
+/* [host] probe set and density primitives; mirrors the featurizer's
+ * hyper-parameter dictionary ("Examples": orders, sigmas, pseudopotential
+ * primitives, overlap_threshold).  Copied by gmp_plan_create. */
+typedef struct {
+  int32_t n_orders;              /* 1..5 */
+  const int32_t *orders;         /* distinct, each in 0..4; output order as given */
+  int32_t n_sigmas;              /* 1..16 */
+  const double *sigmas;          /* Angstrom, > 0; output order as given */
+  int32_t n_elements;            /* 1..64 */
+  const int32_t *prim_offsets;   /* [n_elements+1], ascending, prim_offsets[0] = 0 */
+  const double *B;               /* [prim_offsets[n_elements]] primitive weights (any sign) */
+  const double *beta;            /* [prim_offsets[n_elements]] exponents, > 0 (1/Angstrom^2) */
+  double overlap_threshold;      /* tau > 0: rc(sigma)^2 = max_{e,k} ln(|A0|/tau)/gamma */
+} gmp_probe_desc;
+
+/* A packed batch of structures (CSR over atoms); mirrors the featurizer's
+ * native structure dictionary (lattice vectors, positions, atom types). */
+typedef struct {
+  int32_t n_structs;
+  int64_t n_atoms;
+  const int64_t *atom_offsets;   /* [n_structs+1]; structure s owns atoms [off[s], off[s+1]) */
+  const double *x, *y, *z;       /* [n_atoms] Cartesian coordinates, Angstrom (SoA) */
+  const int32_t *species;        /* [n_atoms] element index 0..n_elements-1 */
+  const double *cell;            /* [n_structs*9]; row m (entries 3m..3m+2) is lattice vector a_m */
+  const uint8_t *pbc;            /* [n_structs]; bit k set = periodic along a_k; 0 = isolated
+                                    (then the cell is ignored and may be zero) */
+} gmp_batch;
+
+/* Neighbour lists in canonical order.  For centre i, entries
+ * [offsets[i], offsets[i+1]) are sorted by (species of j, shell, j, n1, n2, n3)
+ * where shell(q) = number of sigmas with rc(sigma)^2 < q; every sigma's
+ * neighbour set is then a prefix of each species segment. */
+typedef struct {
+  int64_t capacity;              /* [host] entries allocated in j, shift, reverse */
+  int64_t n_pairs;               /* [host] set by gmp_build_neighbors (sync mode) */
+  int64_t *offsets;              /* [n_atoms+1] */
+  int32_t *j;                    /* [capacity] neighbour atom (global index) */
+  int32_t *shift;                /* [capacity] bytes (n1, n2, n3, species_j), n_k signed, little endian;
+                                    d = (Rw_j - Rw_i) + n1 a1 + n2 a2 + n3 a3 with wrapped positions */
+  int32_t *elem_start;           /* [n_atoms*(n_elements+1)] species segment starts, local to offsets[i] */
+  int32_t *sigma_end;            /* [n_atoms*n_elements*n_sigmas] end of sigma s's prefix in segment e, local */
+  int32_t *wrap;                 /* [n_atoms*3] m_i: Rw_i = R_i - (m1 a1 + m2 a2 + m3 a3) */
+  double *rw;                    /* [3*n_atoms] wrapped positions, SoA (x block, y block, z block) */
+  int32_t *reverse;              /* [capacity] or NULL: local index of (j, i, -n) in j's list;
+                                    required by gmp_features_backward */
+} gmp_neighbors;
+
+/* Plan: validates the probe set, infers rc(sigma)^2 from the overlap
+ * threshold ("Examples": the local cutoff is inferred from
+ * overlap_threshold), and uploads the per (sigma, element, primitive)
+ * coefficient tables.  Allocates a few KB of device memory once. */
+gmp_status gmp_plan_create(const gmp_probe_desc *desc, gmp_precision precision, gmp_plan **out);
+void gmp_plan_destroy(gmp_plan *plan);
+
+/* [host] rc(sigma)^2 for every sigma of a probe set, without creating a
+ * plan (host only, no device needed): the squared distance beyond which
+ * every primitive's l = 0 overlap |B| (alpha/lambda)^(3/2) exp(-gamma q)
+ * falls below overlap_threshold ("Examples": the cutoff is inferred from the
+ * threshold).  rc2: [n_sigmas]. */
+gmp_status gmp_probe_cutoffs(const gmp_probe_desc *desc, double *rc2);
+
+/* [host] outputs: n_features = n_orders*n_sigmas; n_components =
+ * n_sigmas * sum_o (l_o+1)(l_o+2)/2; rc2 [n_sigmas] (may be NULL). */
+gmp_status gmp_plan_info(const gmp_plan *plan, int32_t *n_features, int32_t *n_components,
+                         double *rc2);
+
+/* Tuning knobs of the overlap and adjoint kernels (autotuned by the caller
+ * or left at defaults).  sigma_group: sigmas per wavefront (1, 2, 4);
+ * chunk_pairs: a centre's list is processed in pieces of this many pairs
+ * (0 = never split); the piece boundaries depend only on that centre's own
+ * list, so features of a structure are bitwise the same whether it is
+ * featurized alone or inside a batch, for a given tuning; persistent: 1 =
+ * persistent grid pulling work items; bin_divisor: cell-list bin edge is
+ * about rc_max / bin_divisor.  The workspace size depends on the tuning.
+ * Changing the tuning is not thread-safe with concurrent calls on the plan. */
+typedef struct {
+  int32_t sigma_group;
+  int32_t chunk_pairs;
+  int32_t persistent;
+  int32_t bin_divisor;           /* 1..4 */
+} gmp_tuning;
+gmp_status gmp_plan_get_tuning(const gmp_plan *plan, gmp_tuning *out);
+gmp_status gmp_plan_set_tuning(gmp_plan *plan, const gmp_tuning *t);
+
+/* [host] bytes of workspace needed by every entry point for a batch of this
+ * size and a neighbour capacity. */
+gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n_atoms,
+                              int64_t capacity, size_t *bytes);
+
+/* Lattice wrap, cell-list binning, neighbour count, fill and canonical
+ * sort; also the reverse-pair index when nbrs->reverse is not NULL.
+ * Sync mode (n_pairs != NULL): syncs `stream` once after counting; if the
+ * count exceeds nbrs->capacity it returns GMP_E_CAPACITY with *n_pairs set
+ * to the required count (offsets are valid; call again with a larger
+ * capacity).  No-sync mode (n_pairs == NULL, usable under graph capture):
+ * never syncs; an overflow is flagged in the workspace status word and the
+ * lists are left incomplete (see gmp_check_status). */
+gmp_status gmp_build_neighbors(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs,
+                               int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream);
+
+/* Features [n_atoms * n_features] (float for GMP_FP32_COMPENSATED, double
+ * for GMP_FP64), order-major: features[i*n_features + o*n_sigmas + s].
+ * components (optional, FP64) [n_atoms * n_components] laid out
+ * (order, sigma, component) with components of order l in the order
+ * (a descending, then b descending); required later by the backward. */
+gmp_status gmp_features(const gmp_plan *plan, const gmp_batch *batch, const gmp_neighbors *nbrs,
+                        void *features, double *components, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Adjoint: given G = dL/dF [n_atoms * n_features] (same type as features),
+ * writes grad_pos [3 * n_atoms] (FP64, SoA: x block, y block, z block) and,
+ * when grad_cell is not NULL, grad_cell [n_structs * 9] (FP64, row m = dL/da_m),
+ * with Cartesian input positions held fixed and the pair set held fixed.
+ * Needs the components and features of the forward and nbrs->reverse. */
+gmp_status gmp_features_backward(const gmp_plan *plan, const gmp_batch *batch,
+                                 const gmp_neighbors *nbrs, const double *components,
+                                 const void *features, const void *grad_features,
+                                 double *grad_pos, double *grad_cell, void *ws, size_t ws_bytes,
+                                 void *stream);
+
+/* Syncs `stream` and reports (and clears) the device status word in ws. */
+gmp_status gmp_check_status(void *ws, size_t ws_bytes, void *stream);
+
+/* Per-kernel timing with HIP events on the launch stream.  Between
+ * gmp_profile_begin and gmp_profile_end every kernel the library launches is
+ * bracketed by events; gmp_profile_end syncs and returns, per kernel name,
+ * the number of launches and the summed milliseconds.  names: [host]
+ * buffer of max_kernels*64 chars. */
+gmp_status gmp_profile_begin(void);
+gmp_status gmp_profile_end(int32_t max_kernels, int32_t *n_kernels, char *names,
+                           int32_t *launches, double *ms);
+
+const char *gmp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMP_H */

@@ -1,0 +1,333 @@
+// Adjoint of the features: dL/dR and dL/dcell for L = sum G F (the paper's
+// feature derivatives with respect to atom positions, contracted with an
+// upstream gradient).
+//
+//   W_{i,l,s,abc} = G_{i,l,s} w_abc mu_abc / F_{i,l,s}   (0 when F = 0)
+//   For centre i and sigma s the polynomial Q_{i,s,l}(d) = sum_abc W P_abc(d)
+//   is stored in monomial form (coefficients M) together with the monomial
+//   coefficients of its gradient (Dx, Dy, Dz), so per pair
+//   v_{ijn} = grad_d sum_{s,l} c_{l,s}(q) Q_{i,s,l}(d)
+//          = sum_{s,l} [ 2 c'_{l,s}(q) Q_{i,s,l}(d) d + c_{l,s}(q) grad Q_{i,s,l}(d) ].
+//   dL/dR_j += v, dL/dR_i -= v, dL/da_m += (n_m - m_{j,m} + m_{i,m}) v.
+//
+// Determinism without atomics: every centre writes the v of its own pairs
+// (pair-owner scatter into a per-pair buffer); each atom then gathers, in
+// list order, -v of its own pairs plus v of the reverse pairs (j, i, -n);
+// the cell gradient is a fixed-order per-structure reduction of per-atom
+// partials.
+#include "gmp_internal.h"
+
+namespace gmp {
+namespace {
+
+constexpr MonoTable kMT = make_mono_table();
+
+template <bool F64> struct Real;
+template <> struct Real<false> { using T = float; };
+template <> struct Real<true> { using T = double; };
+
+__device__ inline float exp_scaled(float a, float q) { return __builtin_amdgcn_exp2f(a * q); }
+__device__ inline double exp_scaled(double a, double q) { return exp(a * q); }
+__device__ inline float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fma_(double a, double b, double c) { return fma(a, b, c); }
+
+template <bool F64> __device__ inline const typename Real<F64>::T *coef_ptr(const PlanDev &P, int s, int e);
+template <> __device__ inline const float *coef_ptr<false>(const PlanDev &P, int s, int e) {
+  return P.coef32 + ((size_t)(s * P.E + e) * P.kmax) * kCoefStride;
+}
+template <> __device__ inline const double *coef_ptr<true>(const PlanDev &P, int s, int e) {
+  return P.coef64 + ((size_t)(s * P.E + e) * P.kmax) * kCoefStride;
+}
+
+// coefficient block per (centre, sigma): M [nmono(L)], then Dx, Dy, Dz [nmono(L-1)] each
+__host__ __device__ inline int coef_block(int lmax) { return nmono(lmax) + 3 * nmono(lmax - 1); }
+
+// One wavefront per centre.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, int64_t N, const double *components,
+                                                  const void *grad_features, void *bcoef) {
+  using T = typename Real<F64>::T;
+  extern __shared__ double lds_b[];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
+  const int S = P.S, NM = nmono(P.lmax), NM1 = nmono(P.lmax - 1), NB = coef_block(P.lmax);
+  double *scale = lds_b + (size_t)w * (P.nf + S * NM);  // [nf]
+  double *M = scale + P.nf;                               // [S][NM]
+  const bool live = i < N;
+  const double *mu = components + (size_t)i * P.ncomp_total;
+  if (live) {
+    for (int t = lane; t < P.nf; t += kWave) {
+      const int o = t / S, s = t - o * S;
+      const int l = P.orders[o], nc = ncomp(l);
+      const double *mv = mu + P.comp_off[o] + s * nc;
+      double a = 0.0;
+      for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
+      const double F = sqrt(a);
+      const double G = (double)((const T *)grad_features)[(size_t)i * P.nf + t];
+      scale[t] = F > 0.0 ? G / F : 0.0;
+    }
+  }
+  wave_lds_sync();
+  if (live) {
+    // M_{s,m} = sum_abc W_abc T_l[abc][m],  W_abc = scale w_abc mu_abc
+    for (int t = lane; t < S * NM; t += kWave) {
+      const int s = t / NM, m = t - s * NM;
+      const int l = kMT.deg[m];
+      double v = 0.0;
+      int o = -1;
+      for (int oo = 0; oo < P.n_orders; ++oo) if (P.orders[oo] == l) o = oo;
+      if (o >= 0) {
+        const int nc = ncomp(l), mm = m - doff(l);
+        const double *mv = mu + P.comp_off[o] + s * nc;
+        for (int cc = 0; cc < nc; ++cc) v += P.weight[doff(l) + cc] * mv[cc] * P.T[P.toff[l] + cc * nc + mm];
+        v *= scale[o * S + s];
+      }
+      M[t] = v;
+    }
+  }
+  wave_lds_sync();
+  if (live) {
+    T *out = (T *)bcoef + (size_t)i * S * NB;
+    for (int t = lane; t < S * NB; t += kWave) {
+      const int s = t / NB, r = t - s * NB;
+      double v;
+      if (r < NM) {
+        v = M[s * NM + r];
+      } else {
+        const int ax = (r - NM) / NM1, m1 = (r - NM) - ax * NM1;  // derivative axis and lower monomial
+        const int d1 = kMT.deg[m1];
+        int a = kMT.ea[m1], b = kMT.eb[m1], c = kMT.ec[m1];
+        double f;
+        if (ax == 0) { f = a + 1; ++a; } else if (ax == 1) { f = b + 1; ++b; } else { f = c + 1; ++c; }
+        v = f * M[s * NM + doff(d1 + 1) + midx(d1 + 1, a, b)];
+      }
+      out[t] = (T)v;
+    }
+  }
+}
+
+template <int LMAX, bool F64>
+__global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDev nb, const void *bcoef_,
+                                                   void *vbuf_, int C, int64_t n_items) {
+  using T = typename Real<F64>::T;
+  constexpr int NM = nmono(LMAX), NM1 = nmono(LMAX - 1);
+  constexpr int NB = NM + 3 * NM1;
+  const int lane = lane_id();
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (item >= n_items) return;
+  const int64_t i = item / C;
+  const int c = (int)(item - i * C);
+  const int64_t N = bt.n_atoms;
+  const int S = P.S, E = P.E;
+  const T *bcoef = (const T *)bcoef_ + (size_t)i * S * NB;
+  T *vbuf = (T *)vbuf_;
+  const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  const double *cell = bt.cell + 9 * (int64_t)st;
+  const int pbc = bt.pbc[st] & 7;
+  const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+  const int64_t base = nb.offsets[i];
+  const int cnt = (int)(nb.offsets[i + 1] - base);
+  const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
+
+  for (int e = 0; e < E; ++e) {
+    const int es = nb.elem_start[i * (E + 1) + e], ee = nb.elem_start[i * (E + 1) + e + 1];
+    const int lo = es > clo ? es : clo;
+    const int hi = ee < chi ? ee : chi;
+    if (hi <= lo) continue;
+    const int32_t *se = nb.sigma_end + (i * E + e) * S;
+    const int K = P.kcount[e];
+    for (int p0 = lo; p0 < hi; p0 += kWave) {
+      const int p = p0 + lane;
+      const bool act = p < hi;
+      int32_t j = (int32_t)i, w = 0;
+      if (act) { j = nb.j[base + p]; w = nb.shift[base + p]; }
+      double shx = 0.0, shy = 0.0, shz = 0.0;
+      if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
+      const double dx = (nb.rw[j] - rix) + shx;
+      const double dy = (nb.rw[N + j] - riy) + shy;
+      const double dz = (nb.rw[2 * N + j] - riz) + shz;
+      const double q = (dx * dx + dy * dy) + dz * dz;
+      const T xv = (T)dx, yv = (T)dy, zv = (T)dz, qv = (T)q;
+      T mono[NM];
+      mono[0] = (T)1;
+#pragma unroll
+      for (int m = 1; m < NM; ++m) {
+        const T v = kMT.var[m] == 0 ? xv : (kMT.var[m] == 1 ? yv : zv);
+        mono[m] = v * mono[kMT.parent[m]];
+      }
+      double vx = 0.0, vy = 0.0, vz = 0.0;
+      for (int s = 0; s < S; ++s) {
+        if (!(act && p < se[s])) continue;
+        const T *cf = coef_ptr<F64>(P, s, e);
+        const T *bc = bcoef + (size_t)s * NB;
+        T cl[LMAX + 1], cp[LMAX + 1];
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) { cl[l] = (T)0; cp[l] = (T)0; }
+        for (int k = 0; k < K; ++k) {
+          const T *ck = cf + k * kCoefStride;
+          const T ek = exp_scaled(ck[0], qv);
+#pragma unroll
+          for (int l = 0; l <= LMAX; ++l) {
+            const T t = ck[1 + l] * ek;
+            cl[l] += t;
+            cp[l] = fma_(ck[6], t, cp[l]);
+          }
+        }
+        T A = (T)0, Bx = (T)0, By = (T)0, Bz = (T)0;
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) {
+          if (!((P.order_mask >> l) & 1)) continue;
+          T Q = (T)0;
+#pragma unroll
+          for (int mm = 0; mm < ncomp(l); ++mm) Q = fma_(bc[doff(l) + mm], mono[doff(l) + mm], Q);
+          A = fma_(cp[l], Q, A);
+          if (l >= 1) {
+            T gx = (T)0, gy = (T)0, gz = (T)0;
+#pragma unroll
+            for (int mm = 0; mm < ncomp(l - 1); ++mm) {
+              const T mv = mono[doff(l - 1) + mm];
+              gx = fma_(bc[NM + doff(l - 1) + mm], mv, gx);
+              gy = fma_(bc[NM + NM1 + doff(l - 1) + mm], mv, gy);
+              gz = fma_(bc[NM + 2 * NM1 + doff(l - 1) + mm], mv, gz);
+            }
+            Bx = fma_(cl[l], gx, Bx);
+            By = fma_(cl[l], gy, By);
+            Bz = fma_(cl[l], gz, Bz);
+          }
+        }
+        const T A2 = A + A;
+        vx += (double)fma_(A2, xv, Bx);
+        vy += (double)fma_(A2, yv, By);
+        vz += (double)fma_(A2, zv, Bz);
+      }
+      if (act) {
+        T *dst = vbuf + (size_t)(base + p) * 4;
+        dst[0] = (T)vx;
+        dst[1] = (T)vy;
+        dst[2] = (T)vz;
+        dst[3] = (T)0;
+      }
+    }
+  }
+}
+
+// One wavefront per atom: grad_pos in list order and the atom's cell partial.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_bwd_gather(BatchDev bt, NbrDev nb, const void *vbuf_, double *grad_pos,
+                                                    double *cellpart) {
+  using T = typename Real<F64>::T;
+  const T *vbuf = (const T *)vbuf_;
+  const int lane = lane_id();
+  const int64_t a = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int64_t N = bt.n_atoms;
+  if (a >= N) return;
+  const int64_t base = nb.offsets[a], end = nb.offsets[a + 1];
+  const int ma0 = nb.wrap[3 * a], ma1 = nb.wrap[3 * a + 1], ma2 = nb.wrap[3 * a + 2];
+  double g[3] = {0.0, 0.0, 0.0};
+  double cp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t p = base + lane; p < end; p += kWave) {
+    const int32_t j = nb.j[p];
+    const int32_t w = nb.shift[p];
+    const int32_t rv = nb.reverse[p];
+    if (rv < 0) continue;  // flagged by the neighbour build; never for a consistent list
+    const T *va = vbuf + (size_t)p * 4;
+    const T *vr = vbuf + (size_t)(nb.offsets[j] + rv) * 4;
+    const double v0 = (double)va[0], v1 = (double)va[1], v2 = (double)va[2];
+    g[0] += (double)vr[0] - v0;
+    g[1] += (double)vr[1] - v1;
+    g[2] += (double)vr[2] - v2;
+    const double nt[3] = {(double)(shift_n(w, 0) - nb.wrap[3 * j] + ma0),
+                          (double)(shift_n(w, 1) - nb.wrap[3 * j + 1] + ma1),
+                          (double)(shift_n(w, 2) - nb.wrap[3 * j + 2] + ma2)};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      cp[3 * m] += nt[m] * v0;
+      cp[3 * m + 1] += nt[m] * v1;
+      cp[3 * m + 2] += nt[m] * v2;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[k] = wave_sum(g[k]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cp[k] = wave_sum(cp[k]);
+  if (lane == 0) {
+    grad_pos[a] = g[0];
+    grad_pos[N + a] = g[1];
+    grad_pos[2 * N + a] = g[2];
+  }
+  if (lane < 9) {
+    double v = cp[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) v = lane == k ? cp[k] : v;
+    cellpart[(size_t)a * 9 + lane] = v;
+  }
+}
+
+// One wavefront per structure: fixed-order sum of per-atom cell partials.
+__global__ __launch_bounds__(256) void k_cell_reduce(BatchDev bt, const double *cellpart, double *grad_cell) {
+  const int lane = lane_id();
+  const int64_t s = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (s >= bt.n_structs) return;
+  const int64_t a0 = bt.atom_offsets[s], a1 = bt.atom_offsets[s + 1];
+  double cp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t a = a0 + lane; a < a1; a += kWave)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) cp[k] += cellpart[(size_t)a * 9 + k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cp[k] = wave_sum(cp[k]);
+  if (lane < 9) {
+    double v = cp[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) v = lane == k ? cp[k] : v;
+    grad_cell[s * 9 + lane] = v;
+  }
+}
+
+using PairsFn = void (*)(PlanDev, BatchDev, NbrDev, const void *, void *, int, int64_t);
+template <bool F64> PairsFn pick_pairs(int lmax) {
+  switch (lmax) {
+    case 0: return k_bwd_pairs<0, F64>;
+    case 1: return k_bwd_pairs<1, F64>;
+    case 2: return k_bwd_pairs<2, F64>;
+    case 3: return k_bwd_pairs<3, F64>;
+    default: return k_bwd_pairs<4, F64>;
+  }
+}
+
+}  // namespace
+
+size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms) {
+  return (size_t)n_atoms * p->dev.S * coef_block(p->dev.lmax);
+}
+
+void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
+                     const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
+                     double *grad_cell, int C, hipStream_t s) {
+  const int64_t N = bt.n_atoms;
+  if (N == 0) return;
+  const bool f64 = p->prec == GMP_FP64;
+  const int64_t blocks = (N + 3) / 4;
+  size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
+  if (f64)
+    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N, components,
+               grad_features, bcoef);
+  else
+    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N, components,
+               grad_features, bcoef);
+  const int64_t n_items = N * (int64_t)C;
+  PairsFn fn = f64 ? pick_pairs<true>(p->dev.lmax) : pick_pairs<false>(p->dev.lmax);
+  GMP_LAUNCH("adj_pairs", fn, dim3((unsigned)((n_items + 3) / 4)), dim3(256), 0, s, p->dev, bt, nb, bcoef, vbuf, C,
+             n_items);
+  if (f64)
+    GMP_LAUNCH("adj_gather", k_bwd_gather<true>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
+               cellpart);
+  else
+    GMP_LAUNCH("adj_gather", k_bwd_gather<false>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
+               cellpart);
+  if (grad_cell) {
+    const int64_t sb = (bt.n_structs + 3) / 4;
+    GMP_LAUNCH("adj_cell", k_cell_reduce, dim3((unsigned)sb), dim3(256), 0, s, bt, cellpart, grad_cell);
+  }
+}
+
+}  // namespace gmp

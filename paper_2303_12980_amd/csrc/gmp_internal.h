@@ -1,0 +1,233 @@
+// Internal declarations of the gfx950 GMP feature library.
+//
+// Every translation unit is compiled with -ffp-contract=off: the lattice
+// wrap, image shifts and squared distances must round identically wherever
+// they are evaluated (neighbour build, overlap, adjoint), and the two-sum of
+// the compensated accumulation must not be fused.  Multiply-adds that may
+// round once are written as explicit fma()/fmaf().
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/gmp.h"
+
+namespace gmp {
+
+constexpr int kMaxOrders = 5;
+constexpr int kMaxSigmas = 16;
+constexpr int kMaxElements = 64;
+constexpr int kMaxL = 4;
+constexpr int kCoefStride = 8;    // per (sigma, element, primitive): -g', A0..A4, -gamma, pad
+constexpr int kSortMax = 8192;    // largest per-centre list sorted in LDS
+constexpr int kWave = 64;
+
+// status-word bits (device side)
+enum : uint32_t {
+  ST_NONFINITE = 1u,
+  ST_CELL = 2u,
+  ST_SHIFT_RANGE = 4u,
+  ST_OVERFLOW = 8u,
+  ST_SORT_SIZE = 16u,
+  ST_INTERNAL = 32u,
+  ST_BIN_RANGE = 64u,
+  ST_SPECIES = 128u,
+};
+
+__host__ __device__ constexpr int ncomp(int l) { return (l + 1) * (l + 2) / 2; }
+// number of monomials of degree <= d
+__host__ __device__ constexpr int nmono(int d) { return d < 0 ? 0 : (d + 1) * (d + 2) * (d + 3) / 6; }
+// offset of degree d's block in the monomial array
+__host__ __device__ constexpr int doff(int d) { return nmono(d - 1); }
+// index of (a, b, c=d-a-b) inside degree d, components ordered a desc then b desc
+__host__ __device__ constexpr int midx(int d, int a, int b) { return (d - a) * (d - a + 1) / 2 + (d - a - b); }
+
+// Monomial recursion table: monomial t (global index, degree >= 1) equals
+// variable var[t] (0=x, 1=y, 2=z) times monomial parent[t].
+struct MonoTable {
+  int parent[35];
+  int var[35];
+  int deg[35];
+  int ea[35], eb[35], ec[35];
+};
+
+__host__ __device__ constexpr MonoTable make_mono_table() {
+  MonoTable t{};
+  for (int d = 0; d <= 4; ++d)
+    for (int a = d; a >= 0; --a)
+      for (int b = d - a; b >= 0; --b) {
+        int c = d - a - b;
+        int g = doff(d) + midx(d, a, b);
+        t.deg[g] = d; t.ea[g] = a; t.eb[g] = b; t.ec[g] = c;
+        if (d == 0) { t.parent[g] = -1; t.var[g] = -1; continue; }
+        if (a > 0) { t.parent[g] = doff(d - 1) + midx(d - 1, a - 1, b); t.var[g] = 0; }
+        else if (b > 0) { t.parent[g] = doff(d - 1) + midx(d - 1, 0, b - 1); t.var[g] = 1; }
+        else { t.parent[g] = doff(d - 1) + midx(d - 1, 0, 0); t.var[g] = 2; }
+      }
+  return t;
+}
+
+struct StructInfo {
+  double b[9];        // reciprocal rows
+  double reach[3];    // fractional reach rc_max/h_k (periodic axes)
+  int nb[3];          // bins per axis
+  int pbc;
+  int64_t bin_base;   // first bin slot of this structure
+};
+
+// Device view of a plan (passed by value to kernels).
+struct PlanDev {
+  int S, E, n_orders, lmax, order_mask, kmax, nf, ncomp_total;
+  int orders[kMaxOrders];
+  int comp_off[kMaxOrders];       // offset of order o's (sigma, component) block in one centre's components
+  int sig_order[kMaxSigmas];      // sigmas sorted by rc^2 ascending (stable)
+  int rank_lt[kMaxSigmas];        // #{s': rc2[s'] < rc2[s]}
+  int shell_end_sig[kMaxSigmas];  // for shell h: a sigma with rank_lt == h, else -1
+  int shell_prev_sig[kMaxSigmas]; // for shell h: a sigma with the largest rank_lt < h, else -1
+  double rc2[kMaxSigmas];
+  double rcmax2;
+  const float *coef32;            // [S][E][kmax][kCoefStride]
+  const double *coef64;           // [S][E][kmax][kCoefStride]
+  const int *kcount;              // [E]
+  const double *T;                // moment->component maps, per order l: ncomp(l)^2 at toff[l]
+  int toff[kMaxL + 1];
+  double weight[35];              // l!/(a!b!c!) by global monomial index (same (a,b,c) ordering)
+};
+
+struct BatchDev {
+  int n_structs;
+  int64_t n_atoms;
+  const int64_t *atom_offsets;
+  const double *x, *y, *z;
+  const int32_t *species;
+  const double *cell;
+  const uint8_t *pbc;
+};
+
+struct NbrDev {
+  int64_t capacity;
+  int64_t *offsets;
+  int32_t *j;
+  int32_t *shift;
+  int32_t *elem_start;
+  int32_t *sigma_end;
+  int32_t *wrap;
+  double *rw;
+  int32_t *reverse;
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// LDS writes of one wavefront become visible to its other lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ inline int struct_of_atom(const int64_t *off, int n_structs, int64_t i) {
+  int lo = 0, hi = n_structs;  // find s with off[s] <= i < off[s+1]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Image shift s(n) = (n1 a1 + n2 a2) + n3 a3, FP64, fixed operation order.
+__device__ inline void image_shift(const double *cell, int n1, int n2, int n3, double &sx, double &sy,
+                                   double &sz) {
+  double t;
+  t = (double)n1 * cell[0] + (double)n2 * cell[3]; sx = t + (double)n3 * cell[6];
+  t = (double)n1 * cell[1] + (double)n2 * cell[4]; sy = t + (double)n3 * cell[7];
+  t = (double)n1 * cell[2] + (double)n2 * cell[5]; sz = t + (double)n3 * cell[8];
+}
+
+__device__ inline int shift_n(int32_t w, int k) { return (int)(int8_t)((uint32_t)w >> (8 * k)); }
+__device__ inline int shift_species(int32_t w) { return (int)((uint32_t)w >> 24); }
+
+}  // namespace gmp
+
+// ---------------------------------------------------------------- host side
+struct gmp_plan {
+  gmp_precision prec;
+  gmp::PlanDev dev;
+  int S, E, n_orders;
+  int orders[gmp::kMaxOrders];
+  double sigmas[gmp::kMaxSigmas];
+  double rc2[gmp::kMaxSigmas];
+  gmp_tuning tuning;
+  void *dmem;  // single device allocation holding the tables
+};
+
+namespace gmp {
+gmp_status set_error(gmp_status st, const std::string &msg);
+gmp_status hip_error(hipError_t e, const char *where);
+
+// kernel launch bookkeeping for the optional per-kernel event timing
+void prof_before(const char *name, hipStream_t s);
+void prof_after(hipStream_t s);
+
+// workspace carving
+struct Carver {
+  char *base;
+  size_t off, cap;
+  bool dry;
+  explicit Carver(void *p, size_t c) : base((char *)p), off(0), cap(c), dry(p == nullptr) {}
+  template <typename T> T *take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T *p = dry ? nullptr : (T *)(base + off);
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+struct WsLayout {
+  uint32_t *status;       // [64] words: [0] flags, [2..3] total pairs, [4] max count
+  StructInfo *sinfo;
+  int32_t *bin_of;
+  int32_t *bin_count;
+  int64_t *bin_start;
+  int32_t *bin_fill;
+  double *fw;             // [3][N]
+  double *sx, *sy, *sz;   // bin-sorted wrapped positions
+  int32_t *sid, *ssp;     // bin-sorted atom index and species
+  int32_t *cnt;           // [N][E][S]
+  int64_t *ptotal;        // [N]
+  int64_t *scan_aux;      // scan block sums
+  double *partial;        // overlap partial moments [chunk][sigma][monomial]
+  int64_t *nch;           // [N] chunks per centre
+  int64_t *chunk_off;     // [N+1] first chunk of each centre
+  void *bcoef;            // adjoint per-centre polynomial coefficients
+  void *vbuf;             // adjoint per-pair vectors [capacity][4]
+  double *cellpart;       // [N][9]
+  size_t bytes;
+};
+WsLayout carve(const gmp_plan *p, int n_structs, int64_t n_atoms, int64_t capacity, void *ws,
+               size_t ws_bytes);
+int64_t partial_slots(const gmp_plan *p, int64_t n_atoms, int64_t capacity);
+
+// device scans (exclusive, writes n+1 outputs)
+void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *aux, hipStream_t s);
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *aux, hipStream_t s);
+int64_t scan_aux_size(int64_t n);
+void fill_zero(void *p, size_t bytes, hipStream_t s);
+}  // namespace gmp
+
+// Launch with optional event timing.  `label` names the kernel in the
+// per-kernel timing report; `kernel` may be a function-pointer variable.
+#define GMP_LAUNCH(label, kernel, grid, block, smem, stream, ...)              \
+  do {                                                                         \
+    gmp::prof_before(label, stream);                                           \
+    hipLaunchKernelGGL(kernel, grid, block, smem, stream, __VA_ARGS__);        \
+    gmp::prof_after(stream);                                                   \
+  } while (0)

@@ -1,0 +1,286 @@
+"""Python front end of the gfx950 GMP feature library.
+
+Thin marshalling over the C ABI (include/gmp.h): PyTorch provides device
+memory and the current stream; every step of the path (wrap, cell list,
+neighbour lists, overlaps, norms, adjoint) runs in libgmp.so.
+
+Feature layout follows the featurizer's enumeration (paper, "Examples"):
+the probe set is the Cartesian product orders x sigmas, order-major, so
+feature o*n_sigmas + s is (orders[o], sigmas[s]).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GMPError, check
+
+__all__ = ["GMPPlan", "DeviceBatch", "Neighbors", "Workspace", "build_neighbors", "features",
+           "features_backward", "GMPFunction", "feature_labels", "profile", "GMPError"]
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def feature_labels(orders: Sequence[int], sigmas: Sequence[float]):
+    """(order, sigma) of every feature in output order.  Order -1 (the local
+    density) carries no sigma and contributes one feature, listed first where
+    it appears in the orders."""
+    out = []
+    for l in orders:
+        if l == -1:
+            out.append((-1, 0))
+            continue
+        for s in sigmas:
+            out.append((int(l), float(s)))
+    return out
+
+
+class GMPPlan:
+    """Probe set + density primitives + precision (wraps gmp_plan)."""
+
+    def __init__(self, orders, sigmas, prim_offsets, B, beta, overlap_threshold, precision="fp32c"):
+        L = _lib.load()
+        self._orders = np.ascontiguousarray(orders, dtype=np.int32)
+        self._sigmas = np.ascontiguousarray(sigmas, dtype=np.float64)
+        self._poff = np.ascontiguousarray(prim_offsets, dtype=np.int32)
+        self._B = np.ascontiguousarray(B, dtype=np.float64)
+        self._beta = np.ascontiguousarray(beta, dtype=np.float64)
+        self.tau = float(overlap_threshold)
+        prec = {"fp64": _lib.GMP_FP64, "fp32c": _lib.GMP_FP32_COMPENSATED}[precision]
+        self.precision = precision
+        d = _lib.ProbeDesc(len(self._orders), self._orders.ctypes.data_as(_lib.P_i32),
+                           len(self._sigmas), self._sigmas.ctypes.data_as(_lib.P_dbl),
+                           len(self._poff) - 1, self._poff.ctypes.data_as(_lib.P_i32),
+                           self._B.ctypes.data_as(_lib.P_dbl), self._beta.ctypes.data_as(_lib.P_dbl),
+                           self.tau)
+        h = ctypes.c_void_p(0)
+        check(L.gmp_plan_create(ctypes.byref(d), prec, ctypes.byref(h)))
+        self._h = h
+        nf, nc = _lib.c_i32(0), _lib.c_i32(0)
+        rc2 = np.zeros(len(self._sigmas))
+        check(L.gmp_plan_info(h, ctypes.byref(nf), ctypes.byref(nc), rc2.ctypes.data_as(_lib.P_dbl)))
+        self.n_features, self.n_components, self.rc2 = nf.value, nc.value, rc2
+        self.n_elements = len(self._poff) - 1
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+
+    @classmethod
+    def from_probes(cls, probes, precision="fp32c"):
+        return cls(probes.orders, probes.sigmas, probes.prim_offsets, probes.B, probes.beta, probes.tau,
+                   precision)
+
+    @property
+    def orders(self):
+        return self._orders.copy()
+
+    @property
+    def sigmas(self):
+        return self._sigmas.copy()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def labels(self):
+        return feature_labels(self._orders, self._sigmas)
+
+    def get_tuning(self) -> dict:
+        t = _lib.Tuning()
+        check(_lib.load().gmp_plan_get_tuning(self._h, ctypes.byref(t)))
+        return dict(sigma_group=t.sigma_group, chunk_pairs=t.chunk_pairs, persistent=t.persistent,
+                    bin_divisor=t.bin_divisor)
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _lib.Tuning(cur["sigma_group"], cur["chunk_pairs"], cur["persistent"], cur["bin_divisor"])
+        check(_lib.load().gmp_plan_set_tuning(self._h, ctypes.byref(t)))
+
+    def workspace_bytes(self, n_structs, n_atoms, capacity) -> int:
+        b = ctypes.c_size_t(0)
+        check(_lib.load().gmp_workspace_size(self._h, int(n_structs), int(n_atoms), int(capacity), ctypes.byref(b)))
+        return int(b.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.gmp_plan_destroy(h)
+            self._h = None
+
+
+class DeviceBatch:
+    """Packed CSR batch resident on the GPU (wraps gmp_batch)."""
+
+    def __init__(self, atom_offsets, pos, species, cell, pbc, device="cuda"):
+        self.atom_offsets = torch.as_tensor(np.asarray(atom_offsets, np.int64), device=device)
+        pos = torch.as_tensor(np.asarray(pos, np.float64), device=device)
+        self.xyz = pos.t().contiguous()  # [3, N] SoA
+        self.species = torch.as_tensor(np.asarray(species, np.int32), device=device)
+        self.cell = torch.as_tensor(np.asarray(cell, np.float64).reshape(-1, 9), device=device).contiguous()
+        self.pbc = torch.as_tensor(np.asarray(pbc, np.uint8), device=device)
+        self.n_structs = int(self.atom_offsets.numel() - 1)
+        self.n_atoms = int(self.species.numel())
+
+    @classmethod
+    def from_batch(cls, b, device="cuda"):
+        return cls(b.atom_offsets, b.pos, b.species, b.cell, b.pbc, device)
+
+    def desc(self, xyz: Optional[torch.Tensor] = None, cell: Optional[torch.Tensor] = None):
+        xyz = self.xyz if xyz is None else xyz
+        cell = self.cell if cell is None else cell
+        return _lib.BatchDesc(self.n_structs, self.n_atoms, self.atom_offsets.data_ptr(), xyz[0].data_ptr(),
+                              xyz[1].data_ptr(), xyz[2].data_ptr(), self.species.data_ptr(), cell.data_ptr(),
+                              self.pbc.data_ptr())
+
+
+class Workspace:
+    """Grow-only device scratch buffer."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes * 1.1) + 4096, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+class Neighbors:
+    """Canonical neighbour lists (wraps gmp_neighbors)."""
+
+    def __init__(self, plan: GMPPlan, batch: DeviceBatch, capacity: int, reverse: bool = True):
+        dev = batch.species.device
+        N = batch.n_atoms
+        E, S = plan.n_elements, len(plan.sigmas)
+        self.capacity = int(capacity)
+        self.n_pairs = 0
+        self.offsets = torch.zeros(N + 1, dtype=torch.int64, device=dev)
+        self.j = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.shift = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.elem_start = torch.empty(N * (E + 1), dtype=torch.int32, device=dev)
+        self.sigma_end = torch.empty(N * E * S, dtype=torch.int32, device=dev)
+        self.wrap = torch.empty(N * 3, dtype=torch.int32, device=dev)
+        self.rw = torch.empty(3 * N, dtype=torch.float64, device=dev)
+        self.reverse = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev) if reverse else None
+
+    def desc(self):
+        return _lib.NbrDesc(self.capacity, self.n_pairs, self.offsets.data_ptr(), self.j.data_ptr(),
+                            self.shift.data_ptr(), self.elem_start.data_ptr(), self.sigma_end.data_ptr(),
+                            self.wrap.data_ptr(), self.rw.data_ptr(),
+                            self.reverse.data_ptr() if self.reverse is not None else 0)
+
+    # host-side views for tests
+    def shifts_numpy(self):
+        w = self.shift[: self.n_pairs].cpu().numpy().view(np.uint8).reshape(-1, 4)
+        return w[:, :3].view(np.int8).astype(np.int32), w[:, 3].astype(np.int32)
+
+
+def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: Optional[int] = None,
+                    reverse: bool = True, stream=None) -> Neighbors:
+    """Neighbour lists with the two-call capacity pattern."""
+    L = _lib.load()
+    if capacity is None:
+        capacity = max(1024, batch.n_atoms * 64)
+    for _ in range(2):
+        nb = Neighbors(plan, batch, capacity, reverse)
+        nbytes = plan.workspace_bytes(batch.n_structs, batch.n_atoms, nb.capacity)
+        buf = ws.get(nbytes)
+        bd, nd = batch.desc(), nb.desc()
+        npairs = ctypes.c_int64(0)
+        st = L.gmp_build_neighbors(plan.handle, ctypes.byref(bd), ctypes.byref(nd), ctypes.byref(npairs),
+                                   _ptr(buf), buf.numel(), _stream_ptr(stream))
+        if st == _lib.GMP_E_CAPACITY:
+            capacity = int(npairs.value)
+            continue
+        check(st)
+        nb.n_pairs = int(npairs.value)
+        return nb
+    raise GMPError(_lib.GMP_E_CAPACITY, "capacity retry failed")
+
+
+def features(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Workspace, with_components=True,
+             xyz=None, cell=None, out=None, comp_out=None, stream=None):
+    L = _lib.load()
+    N = batch.n_atoms
+    dev = batch.species.device
+    F = out if out is not None else torch.empty((N, plan.n_features), dtype=plan.dtype, device=dev)
+    mu = None
+    if with_components:
+        mu = comp_out if comp_out is not None else torch.empty((N, plan.n_components), dtype=torch.float64,
+                                                               device=dev)
+    nbytes = plan.workspace_bytes(batch.n_structs, N, nb.capacity)
+    buf = ws.get(nbytes)
+    bd, nd = batch.desc(xyz, cell), nb.desc()
+    check(L.gmp_features(plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(F), _ptr(mu), _ptr(buf),
+                         buf.numel(), _stream_ptr(stream)))
+    return F, mu
+
+
+def features_backward(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Workspace, mu, F, G,
+                      want_cell=True, xyz=None, cell=None, stream=None):
+    L = _lib.load()
+    N = batch.n_atoms
+    dev = batch.species.device
+    G = G.to(dtype=plan.dtype).contiguous()
+    gpos = torch.empty(3 * N, dtype=torch.float64, device=dev)
+    gcell = torch.empty(batch.n_structs * 9, dtype=torch.float64, device=dev) if want_cell else None
+    nbytes = plan.workspace_bytes(batch.n_structs, N, nb.capacity)
+    buf = ws.get(nbytes)
+    bd, nd = batch.desc(xyz, cell), nb.desc()
+    check(L.gmp_features_backward(plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(mu), _ptr(F), _ptr(G),
+                                  _ptr(gpos), _ptr(gcell), _ptr(buf), buf.numel(), _stream_ptr(stream)))
+    gp = gpos.view(3, N).t()
+    return gp, (gcell.view(-1, 3, 3) if want_cell else None)
+
+
+class GMPFunction(torch.autograd.Function):
+    """features = GMPFunction.apply(xyz [3,N] fp64, cell [n_s,9] fp64, plan, batch, nbrs, ws).
+
+    The neighbour lists (pair set) are held fixed: the gradient is that of
+    the features over the given pairs, dL/dxyz and dL/dcell with Cartesian
+    positions held fixed when the cell moves."""
+
+    @staticmethod
+    def forward(ctx, xyz, cell, plan, batch, nb, ws):
+        F, mu = features(plan, batch, nb, ws, True, xyz=xyz.contiguous(), cell=cell.contiguous())
+        ctx.save_for_backward(xyz, cell, F, mu)
+        ctx.plan, ctx.batch, ctx.nb, ctx.ws = plan, batch, nb, ws
+        return F
+
+    @staticmethod
+    def backward(ctx, gF):
+        xyz, cell, F, mu = ctx.saved_tensors
+        gp, gc = features_backward(ctx.plan, ctx.batch, ctx.nb, ctx.ws, mu, F, gF.contiguous(), True,
+                                   xyz=xyz.contiguous(), cell=cell.contiguous())
+        return gp.t().contiguous(), gc.reshape(-1, 9), None, None, None, None
+
+
+class profile:
+    """Context manager: per-kernel HIP-event timings of library launches."""
+
+    def __enter__(self):
+        check(_lib.load().gmp_profile_begin())
+        self.result = {}
+        return self
+
+    def __exit__(self, *exc):
+        n = _lib.c_i32(0)
+        names = ctypes.create_string_buffer(64 * 64)
+        launches = (_lib.c_i32 * 64)()
+        ms = (_lib.c_dbl * 64)()
+        check(_lib.load().gmp_profile_end(64, ctypes.byref(n), names, launches, ms))
+        for k in range(n.value):
+            nm = names.raw[64 * k: 64 * k + 64].split(b"\0", 1)[0].decode()
+            self.result[nm] = (int(launches[k]), float(ms[k]))
+        return False
