@@ -1,0 +1,209 @@
+"""Throughput of the GMP feature path on one MI355X.
+
+Workload: the single-structure "plain method at scale" case -- a periodic
+40 x 40 x 40 A cell with 4096 atoms of 5 elements (Dirichlet proportions,
+minimum pair distance 1.6 A), 5 Gaussian primitives per element
+(B log-uniform [0.01, 10], beta log-uniform [0.1, 30] 1/A^2), probes
+l = 0..4 x 8 sigmas log-spaced 0.1..1.6 A (40 features per atom),
+overlap threshold 1e-11; synthetic, seeded.
+
+One step = the whole hot path on that batch: lattice wrap + cell list +
+neighbour lists (with reverse index), forward features (overlap + norm),
+and the adjoint with a seeded N(0,1) upstream gradient (dL/dR, dL/dcell).
+The reported value is atoms*features/s of that step in the FP32
+compensated path; the FP64 path and forward-only rates are reported beside
+it.  Per-kernel durations come from HIP events recorded by the library on
+the launch stream (torch's current stream) during the timed steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed issue)
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
+PEAK_HBM_GBS = 8000.0
+# v_exp_f32 is a quarter-rate transcendental: 256 CU x 4 SIMD x 16 lanes / 4 x 2.4 GHz
+PEAK_EXP_PER_S = 256 * 4 * 16 / 4 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--sample-centres", type=int, default=48)
+    return ap.parse_args()
+
+
+def algorithmic_counts(nb, probes):
+    """Per-launch algorithmic work of the overlap kernel, from the lists:
+    per pair, the monomials of degree >= 2 up to l_max (one multiply each)
+    and q (5 flops); per (pair, active sigma), per primitive one multiply,
+    one exp and one multiply-add per order for the radial sums, and one
+    multiply-add per requested component for the accumulation."""
+    E, S = probes.n_elements, len(probes.sigmas)
+    offs = nb.offsets.cpu().numpy()
+    es = nb.elem_start.cpu().numpy().reshape(-1, E + 1).astype(np.int64)
+    se = nb.sigma_end.cpu().numpy().reshape(-1, E, S).astype(np.int64)
+    active = se - es[:, :E, None]                      # [N, E, S] pairs used by each sigma
+    K = np.diff(probes.prim_offsets).astype(np.int64)  # primitives per element
+    L = np.asarray(probes.orders)
+    lmax = int(L.max())
+    ncomp = int(sum((l + 1) * (l + 2) // 2 for l in L))
+    nmono_hi = (lmax + 1) * (lmax + 2) * (lmax + 3) // 6 - 4 if lmax >= 2 else 0
+    pairs = int(offs[-1])
+    pair_sigma = int(active.sum())
+    exps = int((active.sum(axis=(0, 2)) * K).sum())
+    flops = pairs * (5 + nmono_hi) + exps * (2 + 2 * len(L)) + pair_sigma * 2 * ncomp
+    return dict(pairs=pairs, pair_sigma=pair_sigma, exps=exps, flops=flops)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is described "
+                                   "in DESIGN.md and not executed", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import gmp_synth as gs
+    import paper_2303_12980_amd as g
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    batch, probes = gs.config(args.workload)
+    N, nf = batch.n_atoms, probes.n_features
+    print(f"[bench] workload {args.workload}: {N} atoms, {nf} features, generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    db = g.DeviceBatch.from_batch(batch, dev)
+    G = torch.as_tensor(np.random.default_rng(7).standard_normal((N, nf)), device=dev)
+    ws = g.Workspace(dev)
+
+    def make(prec):
+        plan = g.GMPPlan.from_probes(probes, prec)
+        nb = g.build_neighbors(plan, db, ws)
+        return plan, nb
+
+    def step(plan, nb, backward=True):
+        nb2 = g.build_neighbors(plan, db, ws, out=nb)
+        F, mu = g.features(plan, db, nb2, ws)
+        if backward:
+            gp, gc = g.features_backward(plan, db, nb2, ws, mu, F, G)
+            return F, mu, gp, gc
+        return F, mu, None, None
+
+    def timed(plan, nb, steps, warmup, backward=True, profile=False):
+        for _ in range(warmup):
+            step(plan, nb, backward)
+        torch.cuda.synchronize()
+        prof = None
+        if profile:
+            pctx = g.profile().__enter__()
+        t = time.perf_counter()
+        for _ in range(steps):
+            out = step(plan, nb, backward)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        if profile:
+            pctx.__exit__(None, None, None)
+            prof = pctx.result
+        return dt, out, prof
+
+    results = {}
+    plan32, nb32 = make("fp32c")
+    dt_fb, out32, prof = timed(plan32, nb32, args.steps, args.warmup, True, True)
+    print(f"[bench] fp32c fwd+bwd {dt_fb * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    dt_f, _, prof_f = timed(plan32, nb32, args.steps, 1, False, True)
+    results["fp32c"] = dict(fwd_bwd_ms=dt_fb * 1e3, fwd_ms=dt_f * 1e3)
+    if not args.no_fp64:
+        plan64, nb64 = make("fp64")
+        dt64_fb, out64, prof64 = timed(plan64, nb64, max(3, args.steps // 4), 1, True, True)
+        dt64_f, _, _ = timed(plan64, nb64, max(3, args.steps // 4), 1, False, False)
+        results["fp64"] = dict(fwd_bwd_ms=dt64_fb * 1e3, fwd_ms=dt64_f * 1e3)
+        print(f"[bench] fp64 fwd+bwd {dt64_fb * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel averages over the timed fp32c steps
+    kern = {k: dict(launches=v[0], avg_ms=v[1] / v[0], ms_per_step=v[1] / args.steps) for k, v in prof.items()}
+    kern_f = {k: dict(launches=v[0], avg_ms=v[1] / v[0]) for k, v in prof_f.items()}
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    counts = algorithmic_counts(nb32, probes)
+    ov = kern["overlap"]
+    achieved = counts["flops"] / (ov["avg_ms"] * 1e-3) / 1e12
+    roofline = {"kernel": "overlap", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "exp_rate_per_s": counts["exps"] / (ov["avg_ms"] * 1e-3),
+                "exp_frac": counts["exps"] / (ov["avg_ms"] * 1e-3) / PEAK_EXP_PER_S,
+                "algorithmic_flops_per_launch": counts["flops"], "avg_launch_ms": ov["avg_ms"],
+                "dominant_kernel_of_step": dom}
+
+    # accuracy on sampled centres vs the FP64 oracle
+    import oracle
+    rng = np.random.default_rng(11)
+    cs = np.sort(rng.choice(N, size=min(args.sample_centres, N), replace=False))
+    Fref = oracle.features(batch.structure(0), probes, centres=cs)
+    F32 = out32[0].cpu().numpy()[cs]
+    big = Fref > probes.tau
+    acc = {"sampled_centres": int(len(cs)),
+           "fp32c_max_rel_err": float(np.max(np.abs(F32[big] - Fref[big]) / Fref[big]))}
+    if not args.no_fp64:
+        F64 = out64[0].cpu().numpy()[cs]
+        acc["fp64_max_rel_err"] = float(np.max(np.abs(F64[big] - Fref[big]) / Fref[big]))
+
+    # CPU baseline: the oracle (forward) on a bounded sample of centres
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+        threads = min(threads, len(os.sched_getaffinity(0)))
+        n_s = min(N, 64 * threads)
+        cs2 = np.arange(n_s, dtype=np.int32)
+        t = time.perf_counter()
+        oracle.features(batch.structure(0), probes, centres=cs2)
+        dt = time.perf_counter() - t
+        cpu = {"value": n_s * nf / dt, "unit": "atoms*features/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 oracle forward (brute-force neighbours + closed-form overlaps) for the first "
+                         f"{n_s} of {N} centres, {dt:.1f} s wall on {threads} OpenMP threads; forward only"}
+
+    atoms_feat = N * nf
+    value = atoms_feat / dt_fb
+    out = {
+        "metric": "atoms*features/s (fwd+bwd, FP32 compensated, incl. neighbour build)",
+        "value": value, "unit": "atoms*features/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt_fb * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: periodic 40x40x40 A cell, {N} atoms, 5 elements, "
+                               f"5 primitives/element, l=0..4 x 8 sigma (0.1-1.6 A), tau 1e-11",
+                   "atoms": N, "features_per_atom": nf, "pairs": counts["pairs"], "precision": "fp32c"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rates": {
+            "fp32c_fwd_bwd": atoms_feat / dt_fb,
+            "fp32c_fwd": atoms_feat / dt_f,
+            **({"fp64_fwd_bwd": atoms_feat / (results["fp64"]["fwd_bwd_ms"] * 1e-3),
+                "fp64_fwd": atoms_feat / (results["fp64"]["fwd_ms"] * 1e-3)} if "fp64" in results else {}),
+            "fp32c_fwd_kernels_only": atoms_feat / (1e-3 * (kern_f["overlap"]["avg_ms"] + kern_f["norm"]["avg_ms"])),
+        },
+        "accuracy": acc,
+        "kernels_fp32c_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in kern.items()},
+    }
+    if not args.no_fp64:
+        out["kernels_fp64_ms_per_step"] = {k: round(v[1] / max(3, args.steps // 4), 5) for k, v in prof64.items()}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

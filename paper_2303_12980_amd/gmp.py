@@ -187,13 +187,18 @@ class Neighbors:
 
 
 def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: Optional[int] = None,
-                    reverse: bool = True, stream=None) -> Neighbors:
-    """Neighbour lists with the two-call capacity pattern."""
+                    reverse: bool = True, stream=None, out: Optional[Neighbors] = None) -> Neighbors:
+    """Neighbour lists with the two-call capacity pattern.  ``out`` reuses
+    the buffers of an earlier result for the same batch shape when its
+    capacity suffices."""
     L = _lib.load()
     if capacity is None:
-        capacity = max(1024, batch.n_atoms * 64)
+        capacity = out.capacity if out is not None else max(1024, batch.n_atoms * 64)
     for _ in range(2):
-        nb = Neighbors(plan, batch, capacity, reverse)
+        if out is not None and out.capacity >= capacity and (out.reverse is not None) == reverse:
+            nb = out
+        else:
+            nb = Neighbors(plan, batch, capacity, reverse)
         nbytes = plan.workspace_bytes(batch.n_structs, batch.n_atoms, nb.capacity)
         buf = ws.get(nbytes)
         bd, nd = batch.desc(), nb.desc()
