@@ -36,8 +36,9 @@
  *   (j, n) is a neighbour of i when q <= max_s rc(s)^2, n ranging over Z^3 on
  *   periodic axes (the centre itself and its own images included).
  *   shell(q) = number of sigmas with rc(s)^2 < q; sigma s uses the pairs with
- *   q <= rc(s)^2.
- *   Canonical order: ascending (species of j, shell, j, n1, n2, n3).
+ *   q <= rc(s)^2, i.e. shell(q) <= #{s' : rc(s')^2 < rc(s)^2}.
+ *   Canonical order: ascending (shell, species of j, j, n1, n2, n3), so the
+ *   pairs every sigma uses form a prefix of the list.
  *
  * Gradient of L = sum G_{i,l,s} F_{i,l,s} with the pair set held fixed:
  *   W = G w_abc mu / F (0 when F = 0);  v_{ijn} = sum W grad_d[c(q) P(d)]
@@ -256,8 +257,8 @@ typedef struct { int32_t e, shell, j, n[3]; double q, d[3]; } pair_t;
 
 static int pair_cmp(const void *pa, const void *pb) {
   const pair_t *x = (const pair_t *)pa, *y = (const pair_t *)pb;
-  if (x->e != y->e) return x->e < y->e ? -1 : 1;
   if (x->shell != y->shell) return x->shell < y->shell ? -1 : 1;
+  if (x->e != y->e) return x->e < y->e ? -1 : 1;
   if (x->j != y->j) return x->j < y->j ? -1 : 1;
   for (int k = 0; k < 3; ++k)
     if (x->n[k] != y->n[k]) return x->n[k] < y->n[k] ? -1 : 1;

@@ -46,7 +46,7 @@ def _np_neighbors(struct, rc2, centre, box=None):
                 q = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
                 for j in np.flatnonzero(q <= rcmax2):
                     shell = int(np.sum(rc2 < q[j]))
-                    out.append((int(spec[j]), shell, int(j), int(n1), int(n2), int(n3), q[j]))
+                    out.append((shell, int(spec[j]), int(j), int(n1), int(n2), int(n3), q[j]))
     out.sort(key=lambda t: t[:6])
     return out
 
@@ -70,7 +70,7 @@ def test_neighbors_bit_exact_vs_numpy(case):
         got = oracle.neighbors(struct, rc2, i)
         assert len(got["j"]) == len(ref)
         for k, t in enumerate(ref):
-            assert (int(got["e"][k]), int(got["shell"][k]), int(got["j"][k]), *map(int, got["n"][k])) == t[:6]
+            assert (int(got["shell"][k]), int(got["e"][k]), int(got["j"][k]), *map(int, got["n"][k])) == t[:6]
             assert got["q"][k].tobytes() == np.float64(t[6]).tobytes()
 
 
@@ -112,6 +112,20 @@ def test_membership_matches_plain_distance():
                     for j in np.flatnonzero(np.abs(r - rc) <= 1e-9):
                         pytest.skip("pair on the cutoff surface")
         assert got == ref
+
+
+def test_every_sigma_uses_a_prefix():
+    """In canonical order the pairs a sigma uses (q <= rc(sigma)^2) come first."""
+    rng = np.random.default_rng(51)
+    struct = gs.small_periodic(rng, n_atoms=9, n_elements=3, density=0.06, dmin=1.3)
+    probes = gs.small_probes(rng, n_sigmas=4, n_elements=3, tau=1e-7)
+    rc2 = oracle.cutoffs(probes)
+    for i in range(len(struct[0])):
+        nb = oracle.neighbors(struct, rc2, i)
+        for s in range(len(rc2)):
+            used = nb["q"] <= rc2[s]
+            k = int(used.sum())
+            assert used[:k].all() and not used[k:].any()
 
 
 def test_self_images_present_when_cutoff_exceeds_cell():
