@@ -49,7 +49,7 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_counts(nb, probes):
+def algorithmic_counts(nb, probes, rc2):
     """Per-launch algorithmic work of the overlap kernel, from the lists:
     per pair, the monomials of degree >= 2 up to l_max (one multiply each)
     and q (5 flops); per (pair, active sigma), per primitive one multiply,
@@ -57,17 +57,18 @@ def algorithmic_counts(nb, probes):
     multiply-add per requested component for the accumulation."""
     E, S = probes.n_elements, len(probes.sigmas)
     offs = nb.offsets.cpu().numpy()
-    es = nb.elem_start.cpu().numpy().reshape(-1, E + 1).astype(np.int64)
-    se = nb.sigma_end.cpu().numpy().reshape(-1, E, S).astype(np.int64)
-    active = se - es[:, :E, None]                      # [N, E, S] pairs used by each sigma
-    K = np.diff(probes.prim_offsets).astype(np.int64)  # primitives per element
+    bs = nb.bucket_start.cpu().numpy().reshape(-1, S * E + 1).astype(np.int64)
+    sizes = np.diff(bs, axis=1).reshape(-1, S, E)          # [N, shell, species]
+    rank = np.array([int(np.sum(rc2 < rc2[s])) for s in range(S)])
+    active = np.cumsum(sizes, axis=1)[:, rank, :]          # [N, sigma, species] pairs each sigma uses
+    K = np.diff(probes.prim_offsets).astype(np.int64)      # primitives per element
     L = np.asarray(probes.orders)
     lmax = int(L.max())
     ncomp = int(sum((l + 1) * (l + 2) // 2 for l in L))
     nmono_hi = (lmax + 1) * (lmax + 2) * (lmax + 3) // 6 - 4 if lmax >= 2 else 0
     pairs = int(offs[-1])
     pair_sigma = int(active.sum())
-    exps = int((active.sum(axis=(0, 2)) * K).sum())
+    exps = int((active.sum(axis=(0, 1)) * K).sum())
     flops = pairs * (5 + nmono_hi) + exps * (2 + 2 * len(L)) + pair_sigma * 2 * ncomp
     return dict(pairs=pairs, pair_sigma=pair_sigma, exps=exps, flops=flops)
 
@@ -141,7 +142,7 @@ def main():
     kern = {k: dict(launches=v[0], avg_ms=v[1] / v[0], ms_per_step=v[1] / args.steps) for k, v in prof.items()}
     kern_f = {k: dict(launches=v[0], avg_ms=v[1] / v[0]) for k, v in prof_f.items()}
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    counts = algorithmic_counts(nb32, probes)
+    counts = algorithmic_counts(nb32, probes, plan32.rc2)
     ov = kern["overlap"]
     achieved = counts["flops"] / (ov["avg_ms"] * 1e-3) / 1e12
     roofline = {"kernel": "overlap", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,

@@ -57,8 +57,15 @@ typedef enum {
  *                         accumulation as an FP32 (hi, lo) pair updated with
  *                         an error-free two-sum; cross-lane reduction, the
  *                         moment-to-component map and the norm in FP64.
- *                         Lattice wrap, image shifts and distances stay FP64. */
-typedef enum { GMP_FP64 = 0, GMP_FP32_COMPENSATED = 1 } gmp_precision;
+ *  GMP_FP32_WIDE:         exponentials and radial sums in FP32; monomials of
+ *                         the FP64 displacement and the per-lane accumulation
+ *                         in FP64 (one FP64 fma per term: on gfx950 FP64 FMA
+ *                         issues at the non-packed FP32 rate, so widening is
+ *                         cheaper than a two-sum and loses nothing).
+ * In every mode the lattice wrap, image shifts and distances are FP64.
+ * Features are float for both FP32 modes and double for GMP_FP64; the
+ * adjoint of both FP32 modes evaluates its pair terms in FP32. */
+typedef enum { GMP_FP64 = 0, GMP_FP32_COMPENSATED = 1, GMP_FP32_WIDE = 2 } gmp_precision;
 
 typedef struct gmp_plan gmp_plan; /* opaque, immutable after creation */
 
@@ -71,7 +78,7 @@ typedef struct {
   int32_t n_sigmas;              /* 1..16 */
   const double *sigmas;          /* Angstrom, > 0; output order as given */
   int32_t n_elements;            /* 1..64 */
-  const int32_t *prim_offsets;   /* [n_elements+1], ascending, prim_offsets[0] = 0 */
+  const int32_t *prim_offsets;   /* [n_elements+1], ascending, prim_offsets[0] = 0; <= 16 per element */
   const double *B;               /* [prim_offsets[n_elements]] primitive weights (any sign) */
   const double *beta;            /* [prim_offsets[n_elements]] exponents, > 0 (1/Angstrom^2) */
   double overlap_threshold;      /* tau > 0: rc(sigma)^2 = max_{e,k} ln(|A0|/tau)/gamma */
@@ -91,9 +98,10 @@ typedef struct {
 } gmp_batch;
 
 /* Neighbour lists in canonical order.  For centre i, entries
- * [offsets[i], offsets[i+1]) are sorted by (species of j, shell, j, n1, n2, n3)
- * where shell(q) = number of sigmas with rc(sigma)^2 < q; every sigma's
- * neighbour set is then a prefix of each species segment. */
+ * [offsets[i], offsets[i+1]) are sorted by (shell, species of j, j, n1, n2, n3)
+ * where shell(q) = number of sigmas with rc(sigma)^2 < q, so the pairs each
+ * sigma uses (q <= rc(sigma)^2) are a prefix of the list.  Bucket
+ * b = shell * n_elements + species holds the entries of one (shell, species). */
 typedef struct {
   int64_t capacity;              /* [host] entries allocated in j, shift, reverse */
   int64_t n_pairs;               /* [host] set by gmp_build_neighbors (sync mode) */
@@ -101,8 +109,9 @@ typedef struct {
   int32_t *j;                    /* [capacity] neighbour atom (global index) */
   int32_t *shift;                /* [capacity] bytes (n1, n2, n3, species_j), n_k signed, little endian;
                                     d = (Rw_j - Rw_i) + n1 a1 + n2 a2 + n3 a3 with wrapped positions */
-  int32_t *elem_start;           /* [n_atoms*(n_elements+1)] species segment starts, local to offsets[i] */
-  int32_t *sigma_end;            /* [n_atoms*n_elements*n_sigmas] end of sigma s's prefix in segment e, local */
+  int32_t *bucket_start;         /* [n_atoms*(n_sigmas*n_elements+1)] bucket starts, local to offsets[i];
+                                    the last entry is the list length */
+  int32_t *sigma_end;            /* [n_atoms*n_sigmas] length of the prefix sigma s uses, local */
   int32_t *wrap;                 /* [n_atoms*3] m_i: Rw_i = R_i - (m1 a1 + m2 a2 + m3 a3) */
   double *rw;                    /* [3*n_atoms] wrapped positions, SoA (x block, y block, z block) */
   int32_t *reverse;              /* [capacity] or NULL: local index of (j, i, -n) in j's list;

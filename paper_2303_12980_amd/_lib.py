@@ -16,7 +16,7 @@ GMP_OK, GMP_E_INVALID, GMP_E_UNSUPPORTED, GMP_E_CELL = 0, 1, 2, 3
 GMP_E_CAPACITY, GMP_E_NONFINITE, GMP_E_HIP, GMP_E_NOMEM = 4, 5, 6, 7
 STATUS_NAMES = {0: "GMP_OK", 1: "GMP_E_INVALID", 2: "GMP_E_UNSUPPORTED", 3: "GMP_E_CELL",
                 4: "GMP_E_CAPACITY", 5: "GMP_E_NONFINITE", 6: "GMP_E_HIP", 7: "GMP_E_NOMEM"}
-GMP_FP64, GMP_FP32_COMPENSATED = 0, 1
+GMP_FP64, GMP_FP32_COMPENSATED, GMP_FP32_WIDE = 0, 1, 2
 
 # every symbol include/gmp.h declares
 EXPORTS = (
@@ -39,7 +39,7 @@ class BatchDesc(ctypes.Structure):
 
 class NbrDesc(ctypes.Structure):
     _fields_ = [("capacity", c_i64), ("n_pairs", c_i64), ("offsets", c_vp), ("j", c_vp), ("shift", c_vp),
-                ("elem_start", c_vp), ("sigma_end", c_vp), ("wrap", c_vp), ("rw", c_vp), ("reverse", c_vp)]
+                ("bucket_start", c_vp), ("sigma_end", c_vp), ("wrap", c_vp), ("rw", c_vp), ("reverse", c_vp)]
 
 
 class Tuning(ctypes.Structure):

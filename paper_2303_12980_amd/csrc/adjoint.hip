@@ -31,13 +31,6 @@ __device__ inline double exp_scaled(double a, double q) { return exp(a * q); }
 __device__ inline float fma_(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c); }
 
-template <bool F64> __device__ inline const typename Real<F64>::T *coef_ptr(const PlanDev &P, int s, int e);
-template <> __device__ inline const float *coef_ptr<false>(const PlanDev &P, int s, int e) {
-  return P.coef32 + ((size_t)(s * P.E + e) * P.kmax) * kCoefStride;
-}
-template <> __device__ inline const double *coef_ptr<true>(const PlanDev &P, int s, int e) {
-  return P.coef64 + ((size_t)(s * P.E + e) * P.kmax) * kCoefStride;
-}
 
 // coefficient block per (centre, sigma): M [nmono(L)], then Dx, Dy, Dz [nmono(L-1)] each
 __host__ __device__ inline int coef_block(int lmax) { return nmono(lmax) + 3 * nmono(lmax - 1); }
@@ -106,48 +99,64 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, int64_t N, const do
   }
 }
 
-template <int LMAX, bool F64>
-__global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDev nb, const void *bcoef_,
-                                                   void *vbuf_, int C, int64_t n_items) {
+// Per-pair adjoint vectors, persistent: wavefronts pull (centre, chunk)
+// items.  Lanes take consecutive pairs of the centre's list; a pair is used
+// by every sigma whose prefix contains it.  Radial coefficients come from
+// the LDS copy of the plan table (row of the lane's neighbour species); the
+// centre's polynomial coefficients M, Dx, Dy, Dz are wavefront-uniform.
+template <int LMAX, int KB, bool F64, bool LDS>
+__global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
+                                                   const void *bcoef_, void *vbuf_, int C, int64_t n_items,
+                                                   unsigned long long *counter, const void *tab_global) {
   using T = typename Real<F64>::T;
   constexpr int NM = nmono(LMAX), NM1 = nmono(LMAX - 1);
   constexpr int NB = NM + 3 * NM1;
-  const int lane = lane_id();
-  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (item >= n_items) return;
-  const int64_t i = item / C;
-  const int c = (int)(item - i * C);
-  const int64_t N = bt.n_atoms;
+  extern __shared__ double lds_dyn[];
+  __shared__ int lds_k[kMaxElements];
   const int S = P.S, E = P.E;
-  const T *bcoef = (const T *)bcoef_ + (size_t)i * S * NB;
+  const T *__restrict__ tabg = (const T *)tab_global;
+  T *tabl = (T *)lds_dyn;
+  if (LDS) {
+    const int n = S * E * KB * kCoefStride;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) tabl[idx] = tabg[idx];
+  }
+  for (int e = threadIdx.x; e < E; e += blockDim.x) lds_k[e] = P.kcount[e];
+  __syncthreads();
+  const int lane = lane_id();
+  const int64_t N = bt.n_atoms;
   T *vbuf = (T *)vbuf_;
-  const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
-  const double *cell = bt.cell + 9 * (int64_t)st;
-  const int pbc = bt.pbc[st] & 7;
-  const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
-  const int64_t base = nb.offsets[i];
-  const int cnt = (int)(nb.offsets[i + 1] - base);
-  const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
-
-  for (int e = 0; e < E; ++e) {
-    const int es = nb.elem_start[i * (E + 1) + e], ee = nb.elem_start[i * (E + 1) + e + 1];
-    const int lo = es > clo ? es : clo;
-    const int hi = ee < chi ? ee : chi;
-    if (hi <= lo) continue;
-    const int32_t *se = nb.sigma_end + (i * E + e) * S;
-    const int K = P.kcount[e];
-    for (int p0 = lo; p0 < hi; p0 += kWave) {
+  const int mask = P.order_mask;
+  for (;;) {
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(counter, 1ull);
+    const int64_t item = (int64_t)__shfl(it, 0, kWave);
+    if (item >= n_items) break;
+    const int64_t i = item / C;
+    const int c = (int)(item - i * C);
+    const T *bcoef = (const T *)bcoef_ + (size_t)i * S * NB;
+    const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+    const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
+    const int pbc = bt.pbc[st] & 7;
+    const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+    const int64_t base = nb.offsets[i];
+    const int cnt = (int)(nb.offsets[i + 1] - base);
+    const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
+    const int32_t *se = nb.sigma_end + i * S;
+    for (int p0 = clo; p0 < chi; p0 += kWave) {
       const int p = p0 + lane;
-      const bool act = p < hi;
+      const bool act = p < chi;
       int32_t j = (int32_t)i, w = 0;
       if (act) { j = nb.j[base + p]; w = nb.shift[base + p]; }
       double shx = 0.0, shy = 0.0, shz = 0.0;
       if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
-      const double dx = (nb.rw[j] - rix) + shx;
-      const double dy = (nb.rw[N + j] - riy) + shy;
-      const double dz = (nb.rw[2 * N + j] - riz) + shz;
+      const double4 rj = rw4[j];
+      const double dx = (rj.x - rix) + shx;
+      const double dy = (rj.y - riy) + shy;
+      const double dz = (rj.z - riz) + shz;
       const double q = (dx * dx + dy * dy) + dz * dz;
       const T xv = (T)dx, yv = (T)dy, zv = (T)dz, qv = (T)q;
+      const int e = shift_species(w);
+      const int K = lds_k[e];
       T mono[NM];
       mono[0] = (T)1;
 #pragma unroll
@@ -158,25 +167,29 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
       double vx = 0.0, vy = 0.0, vz = 0.0;
       for (int s = 0; s < S; ++s) {
         if (!(act && p < se[s])) continue;
-        const T *cf = coef_ptr<F64>(P, s, e);
+        const size_t roff = ((size_t)(s * E + e) * KB) * kCoefStride;
         const T *bc = bcoef + (size_t)s * NB;
         T cl[LMAX + 1], cp[LMAX + 1];
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) { cl[l] = (T)0; cp[l] = (T)0; }
-        for (int k = 0; k < K; ++k) {
-          const T *ck = cf + k * kCoefStride;
-          const T ek = exp_scaled(ck[0], qv);
 #pragma unroll
-          for (int l = 0; l <= LMAX; ++l) {
-            const T t = ck[1 + l] * ek;
-            cl[l] += t;
-            cp[l] = fma_(ck[6], t, cp[l]);
+        for (int k = 0; k < KB; ++k) {
+          if (k < K) {
+            const size_t o = roff + k * kCoefStride;
+            const T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+            const T ng = LDS ? tabl[o + 6] : tabg[o + 6];
+#pragma unroll
+            for (int l = 0; l <= LMAX; ++l) {
+              const T t = (LDS ? tabl[o + 1 + l] : tabg[o + 1 + l]) * ek;
+              cl[l] += t;
+              cp[l] = fma_(ng, t, cp[l]);
+            }
           }
         }
         T A = (T)0, Bx = (T)0, By = (T)0, Bz = (T)0;
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) {
-          if (!((P.order_mask >> l) & 1)) continue;
+          if (!((mask >> l) & 1)) continue;
           T Q = (T)0;
 #pragma unroll
           for (int mm = 0; mm < ncomp(l); ++mm) Q = fma_(bc[doff(l) + mm], mono[doff(l) + mm], Q);
@@ -283,15 +296,28 @@ __global__ __launch_bounds__(256) void k_cell_reduce(BatchDev bt, const double *
   }
 }
 
-using PairsFn = void (*)(PlanDev, BatchDev, NbrDev, const void *, void *, int, int64_t);
-template <bool F64> PairsFn pick_pairs(int lmax) {
+using PairsFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const void *, void *, int, int64_t,
+                         unsigned long long *, const void *);
+template <int L, bool F64, bool LDS> PairsFn pick_kb(int kb) {
+  if (kb <= 4) return k_bwd_pairs<L, 4, F64, LDS>;
+  if (kb <= 8) return k_bwd_pairs<L, 8, F64, LDS>;
+  return k_bwd_pairs<L, 16, F64, LDS>;
+}
+template <bool F64, bool LDS> PairsFn pick_pairs(int lmax, int kb) {
   switch (lmax) {
-    case 0: return k_bwd_pairs<0, F64>;
-    case 1: return k_bwd_pairs<1, F64>;
-    case 2: return k_bwd_pairs<2, F64>;
-    case 3: return k_bwd_pairs<3, F64>;
-    default: return k_bwd_pairs<4, F64>;
+    case 0: return pick_kb<0, F64, LDS>(kb);
+    case 1: return pick_kb<1, F64, LDS>(kb);
+    case 2: return pick_kb<2, F64, LDS>(kb);
+    case 3: return pick_kb<3, F64, LDS>(kb);
+    default: return pick_kb<4, F64, LDS>(kb);
   }
+}
+
+// AoS copy of the wrapped positions: one 32-byte gather per neighbour.
+__global__ void k_pack_rw_bwd(NbrDev nb, int64_t N, double4 *rw4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  rw4[i] = make_double4(nb.rw[i], nb.rw[N + i], nb.rw[2 * N + i], 0.0);
 }
 
 }  // namespace
@@ -300,9 +326,11 @@ size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms) {
   return (size_t)n_atoms * p->dev.S * coef_block(p->dev.lmax);
 }
 
+int persistent_blocks(const void *fn, size_t smem);
+
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
-                     double *grad_cell, int C, hipStream_t s) {
+                     double *grad_cell, unsigned long long *counter, double4 *rw4, int C, hipStream_t s) {
   const int64_t N = bt.n_atoms;
   if (N == 0) return;
   const bool f64 = p->prec == GMP_FP64;
@@ -315,9 +343,21 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
     GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N, components,
                grad_features, bcoef);
   const int64_t n_items = N * (int64_t)C;
-  PairsFn fn = f64 ? pick_pairs<true>(p->dev.lmax) : pick_pairs<false>(p->dev.lmax);
-  GMP_LAUNCH("adj_pairs", fn, dim3((unsigned)((n_items + 3) / 4)), dim3(256), 0, s, p->dev, bt, nb, bcoef, vbuf, C,
-             n_items);
+  fill_zero(counter, sizeof(unsigned long long), s);
+  GMP_LAUNCH("pack_positions", k_pack_rw_bwd, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, nb, N, rw4);
+  const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
+  const bool use_lds = tab_bytes <= 48 * 1024;
+  const size_t tsm = use_lds ? tab_bytes : 0;
+  const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
+  PairsFn fn = f64 ? (use_lds ? pick_pairs<true, true>(p->dev.lmax, p->dev.kb)
+                              : pick_pairs<true, false>(p->dev.lmax, p->dev.kb))
+                   : (use_lds ? pick_pairs<false, true>(p->dev.lmax, p->dev.kb)
+                              : pick_pairs<false, false>(p->dev.lmax, p->dev.kb));
+  int64_t pb = persistent_blocks((const void *)fn, tsm);
+  if (pb > (n_items + 3) / 4) pb = (n_items + 3) / 4;
+  if (pb < 1) pb = 1;
+  GMP_LAUNCH("adj_pairs", fn, dim3((unsigned)pb), dim3(256), tsm, s, p->dev, bt, nb, (const double4 *)rw4, bcoef, vbuf,
+             C, n_items, counter, tab);
   if (f64)
     GMP_LAUNCH("adj_gather", k_bwd_gather<true>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
                cellpart);

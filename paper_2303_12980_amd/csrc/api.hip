@@ -23,13 +23,14 @@ void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, con
 int normalized_group(const gmp_plan *p);
 int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs);
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
-                    int64_t *chunk_off, int64_t *scan_aux, int64_t pairs_bound, hipStream_t s);
+                    int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
+                    int64_t pairs_bound, hipStream_t s);
 void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off, void *features,
                    double *components, hipStream_t s);
 size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms);
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
-                     double *grad_cell, int C, hipStream_t s);
+                     double *grad_cell, unsigned long long *counter, double4 *rw4, int C, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -111,6 +112,8 @@ WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t capacity, vo
   L.partial = c.take<double>(partial_slots(p, N, capacity));
   L.nch = c.take<int64_t>(N);
   L.chunk_off = c.take<int64_t>(N + 1);
+  L.counter = c.take<unsigned long long>(32);
+  L.rw4 = c.take<double4>(N);
   L.bcoef = c.take<char>(bwd_coef_elems(p, N) * tsz);
   L.vbuf = c.take<char>((size_t)capacity * 4 * tsz);
   L.cellpart = c.take<double>((size_t)N * 9);
@@ -220,7 +223,7 @@ static gmp_status validate_desc(const gmp_probe_desc *d, int *mask_out, int *kma
   for (int e = 0; e < d->n_elements; ++e) {
     int k = d->prim_offsets[e + 1] - d->prim_offsets[e];
     if (k < 0) return set_error(GMP_E_INVALID, "prim_offsets must be ascending");
-    if (k > 32) return set_error(GMP_E_UNSUPPORTED, "at most 32 primitives per element");
+    if (k > 16) return set_error(GMP_E_UNSUPPORTED, "at most 16 primitives per element");
     if (k > kmax) kmax = k;
   }
   const int np = d->prim_offsets[d->n_elements];
@@ -264,7 +267,7 @@ gmp_status gmp_probe_cutoffs(const gmp_probe_desc *d, double *rc2) {
 gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp_plan **out) {
   if (!d || !out) return set_error(GMP_E_INVALID, "null argument");
   *out = nullptr;
-  if (precision != GMP_FP64 && precision != GMP_FP32_COMPENSATED)
+  if (precision != GMP_FP64 && precision != GMP_FP32_COMPENSATED && precision != GMP_FP32_WIDE)
     return set_error(GMP_E_INVALID, "unknown precision");
   int mask = 0, kmax = 1;
   gmp_status vst = validate_desc(d, &mask, &kmax);
@@ -282,6 +285,8 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   P.n_orders = p->n_orders;
   P.order_mask = mask;
   P.kmax = kmax;
+  const int kb = kmax <= 4 ? 4 : (kmax <= 8 ? 8 : 16);
+  P.kb = kb;
   P.lmax = 0;
   int coff = 0;
   for (int o = 0; o < p->n_orders; ++o) {
@@ -294,8 +299,8 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   P.ncomp_total = coff;
   P.nf = p->n_orders * p->S;
 
-  std::vector<float> c32((size_t)p->S * p->E * kmax * kCoefStride, 0.0f);
-  std::vector<double> c64((size_t)p->S * p->E * kmax * kCoefStride, 0.0);
+  std::vector<float> c32((size_t)p->S * p->E * kb * kCoefStride, 0.0f);
+  std::vector<double> c64((size_t)p->S * p->E * kb * kCoefStride, 0.0);
   double rcmax2 = 0.0;
   for (int s = 0; s < p->S; ++s) {
     const double sg = d->sigmas[s];
@@ -308,7 +313,7 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
         const double lam = alpha + beta;
         const double gam = alpha * beta / lam;
         const int kk = k - d->prim_offsets[e];
-        const size_t idx = (((size_t)s * p->E + e) * kmax + kk) * kCoefStride;
+        const size_t idx = (((size_t)s * p->E + e) * kb + kk) * kCoefStride;
         c64[idx] = -gam;
         c32[idx] = (float)(-gam * 1.4426950408889634);  // exp(-g q) = exp2(-g log2(e) q)
         const double ratio = beta / lam;
@@ -336,15 +341,6 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
     int r = 0;
     for (int t = 0; t < p->S; ++t) r += P.rc2[t] < P.rc2[s] ? 1 : 0;
     P.rank_lt[s] = r;
-  }
-  for (int h = 0; h < kMaxSigmas; ++h) { P.shell_end_sig[h] = -1; P.shell_prev_sig[h] = -1; }
-  for (int h = 0; h < p->S; ++h) {
-    int best_prev = -1;
-    for (int s = 0; s < p->S; ++s) {
-      if (P.rank_lt[s] == h) P.shell_end_sig[h] = s;
-      if (P.rank_lt[s] < h && (best_prev < 0 || P.rank_lt[s] > P.rank_lt[best_prev])) best_prev = s;
-    }
-    P.shell_prev_sig[h] = best_prev;
   }
   // moment -> component maps and weights
   std::vector<double> T;
@@ -446,7 +442,7 @@ gmp_status check_batch(const gmp_plan *p, const gmp_batch *b) {
 gmp_status check_nbrs(const gmp_plan *p, const gmp_batch *b, const gmp_neighbors *n, bool need_lists) {
   if (!n) return set_error(GMP_E_INVALID, "null neighbour lists");
   if (n->capacity < 0) return set_error(GMP_E_INVALID, "negative capacity");
-  if (!n->offsets || !n->elem_start || !n->sigma_end || !n->wrap || !n->rw)
+  if (!n->offsets || !n->bucket_start || !n->sigma_end || !n->wrap || !n->rw)
     return set_error(GMP_E_INVALID, "null neighbour arrays");
   if (need_lists && n->capacity > 0 && (!n->j || !n->shift)) return set_error(GMP_E_INVALID, "null j/shift");
   (void)p; (void)b;
@@ -471,7 +467,7 @@ NbrDev to_dev(const gmp_neighbors *n) {
   d.offsets = n->offsets;
   d.j = n->j;
   d.shift = n->shift;
-  d.elem_start = n->elem_start;
+  d.bucket_start = n->bucket_start;
   d.sigma_end = n->sigma_end;
   d.wrap = n->wrap;
   d.rw = n->rw;
@@ -592,7 +588,7 @@ gmp_status gmp_features(const gmp_plan *p, const gmp_batch *b, const gmp_neighbo
   BatchDev bt = to_dev(b);
   NbrDev nb = to_dev(n);
   const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
-  launch_overlap(p, bt, nb, L.partial, L.nch, L.chunk_off, L.scan_aux, pairs, s);
+  launch_overlap(p, bt, nb, L.partial, L.nch, L.chunk_off, L.scan_aux, L.counter, L.rw4, pairs, s);
   launch_finish(p, N, L.partial, L.chunk_off, features, components, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "feature kernels");
@@ -625,7 +621,7 @@ gmp_status gmp_features_backward(const gmp_plan *p, const gmp_batch *b, const gm
   int64_t C = want < by_pairs ? want : by_pairs;
   if (C < 1) C = 1;
   launch_backward(p, bt, nb, components, grad_features, L.bcoef, L.vbuf, L.cellpart, grad_pos, grad_cell,
-                  (int)C, s);
+                  L.counter, L.rw4, (int)C, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "adjoint kernels");
   return GMP_OK;

@@ -21,6 +21,7 @@ constexpr int kMaxSigmas = 16;
 constexpr int kMaxElements = 64;
 constexpr int kMaxL = 4;
 constexpr int kCoefStride = 8;    // per (sigma, element, primitive): -g', A0..A4, -gamma, pad
+constexpr int kMaxPrims = 16;
 constexpr int kSortMax = 8192;    // largest per-centre list sorted in LDS
 constexpr int kWave = 64;
 
@@ -79,17 +80,15 @@ struct StructInfo {
 
 // Device view of a plan (passed by value to kernels).
 struct PlanDev {
-  int S, E, n_orders, lmax, order_mask, kmax, nf, ncomp_total;
+  int S, E, n_orders, lmax, order_mask, kmax, kb, nf, ncomp_total;  // kb: primitive stride of the tables (4/8/16)
   int orders[kMaxOrders];
   int comp_off[kMaxOrders];       // offset of order o's (sigma, component) block in one centre's components
   int sig_order[kMaxSigmas];      // sigmas sorted by rc^2 ascending (stable)
   int rank_lt[kMaxSigmas];        // #{s': rc2[s'] < rc2[s]}
-  int shell_end_sig[kMaxSigmas];  // for shell h: a sigma with rank_lt == h, else -1
-  int shell_prev_sig[kMaxSigmas]; // for shell h: a sigma with the largest rank_lt < h, else -1
   double rc2[kMaxSigmas];
   double rcmax2;
-  const float *coef32;            // [S][E][kmax][kCoefStride]
-  const double *coef64;           // [S][E][kmax][kCoefStride]
+  const float *coef32;            // [S][E][kb][kCoefStride]: -gamma*log2(e), A_0..A_4, -gamma (zero rows past K_e)
+  const double *coef64;           // [S][E][kb][kCoefStride]: -gamma, A_0..A_4, -gamma
   const int *kcount;              // [E]
   const double *T;                // moment->component maps, per order l: ncomp(l)^2 at toff[l]
   int toff[kMaxL + 1];
@@ -111,8 +110,8 @@ struct NbrDev {
   int64_t *offsets;
   int32_t *j;
   int32_t *shift;
-  int32_t *elem_start;
-  int32_t *sigma_end;
+  int32_t *bucket_start;   // [N][S*E+1] local starts of buckets (shell h, species e) = h*E + e
+  int32_t *sigma_end;      // [N][S] end of each sigma's prefix
   int32_t *wrap;
   double *rw;
   int32_t *reverse;
@@ -150,6 +149,20 @@ __device__ inline void image_shift(const double *cell, int n1, int n2, int n3, d
   t = (double)n1 * cell[0] + (double)n2 * cell[3]; sx = t + (double)n3 * cell[6];
   t = (double)n1 * cell[1] + (double)n2 * cell[4]; sy = t + (double)n3 * cell[7];
   t = (double)n1 * cell[2] + (double)n2 * cell[5]; sz = t + (double)n3 * cell[8];
+}
+
+// Lattice rows held in registers for the duration of a work item.
+struct Cell9 {
+  double a[9];
+};
+__device__ inline Cell9 load_cell(const double *cell) {
+  Cell9 c;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) c.a[k] = cell[k];
+  return c;
+}
+__device__ inline void image_shift(const Cell9 &c, int n1, int n2, int n3, double &sx, double &sy, double &sz) {
+  image_shift(c.a, n1, n2, n3, sx, sy, sz);
 }
 
 __device__ inline int shift_n(int32_t w, int k) { return (int)(int8_t)((uint32_t)w >> (8 * k)); }
@@ -201,12 +214,14 @@ struct WsLayout {
   double *fw;             // [3][N]
   double *sx, *sy, *sz;   // bin-sorted wrapped positions
   int32_t *sid, *ssp;     // bin-sorted atom index and species
-  int32_t *cnt;           // [N][E][S]
+  int32_t *cnt;           // [N][S][E] neighbours per bucket (shell, species)
   int64_t *ptotal;        // [N]
   int64_t *scan_aux;      // scan block sums
   double *partial;        // overlap partial moments [chunk][sigma][monomial]
   int64_t *nch;           // [N] chunks per centre
   int64_t *chunk_off;     // [N+1] first chunk of each centre
+  unsigned long long *counter;  // work-item counter of the persistent kernels
+  double4 *rw4;           // [N] AoS copy of the wrapped positions
   void *bcoef;            // adjoint per-centre polynomial coefficients
   void *vbuf;             // adjoint per-pair vectors [capacity][4]
   double *cellpart;       // [N][9]

@@ -231,10 +231,7 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
         double dy = (sy[t] - riy) + shy;
         double dz = (sz[t] - riz) + shz;
         double q = (dx * dx + dy * dy) + dz * dz;
-        if (q <= P.rcmax2) {
-          int sh = shell_of(P, q);
-          atomicAdd(&c[ssp[t] * P.S + sh], 1);
-        }
+        if (q <= P.rcmax2) atomicAdd(&c[shell_of(P, q) * P.E + ssp[t]], 1);
       }
     }
   }
@@ -304,8 +301,9 @@ __device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3) {
   return ((uint64_t)j << 24) | ((uint64_t)(n1 + 128) << 16) | ((uint64_t)(n2 + 128) << 8) | (uint64_t)(n3 + 128);
 }
 
-// One workgroup per centre: fill its buckets in LDS, sort every bucket by
-// (j, n), write j / shift and the species-segment and sigma-prefix ends.
+// One workgroup per centre: fill its buckets (shell h, species e), in
+// bucket order h * E + e, in LDS; sort every bucket by (j, n); write j /
+// shift, the bucket starts and the sigma-prefix ends.
 __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                               const double *fw, const int64_t *bin_start,
                                               const double *sx, const double *sy, const double *sz,
@@ -332,12 +330,8 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
     if ((int64_t)acc != total) atomicOr(status, ST_INTERNAL);
   }
   __syncthreads();
-  // segment starts and sigma prefix ends (local indices)
-  for (int e = tid; e <= P.E; e += blockDim.x) nb.elem_start[i * (P.E + 1) + e] = bstart[e * P.S];
-  for (int t = tid; t < P.E * P.S; t += blockDim.x) {
-    int e = t / P.S, s = t - e * P.S;
-    nb.sigma_end[i * P.E * P.S + t] = bstart[e * P.S + P.rank_lt[s] + 1];
-  }
+  for (int b = tid; b <= nbk; b += blockDim.x) nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
+  for (int s = tid; s < P.S; s += blockDim.x) nb.sigma_end[i * P.S + s] = bstart[(P.rank_lt[s] + 1) * P.E];
   if (overflow || too_big) return;
   for (int b = tid; b < nbk; b += blockDim.x) cursor[b] = bstart[b];
   __syncthreads();
@@ -357,7 +351,7 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       double dz = (sz[t] - riz) + shz;
       double q = (dx * dx + dy * dy) + dz * dz;
       if (q <= P.rcmax2) {
-        int bk = ssp[t] * P.S + shell_of(P, q);
+        int bk = shell_of(P, q) * P.E + ssp[t];
         int pos = atomicAdd(&cursor[bk], 1);
         if (pos < bstart[bk + 1]) keys[pos] = make_key(sid[t], n[0], n[1], n[2]);
         else atomicOr(status, ST_INTERNAL);
@@ -369,7 +363,7 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
     const int b0 = bstart[b], bn = bstart[b + 1] - b0;
     if (bn == 0) continue;
     wave_sort(keys + b0, bn);
-    const int e = b / P.S;
+    const int e = b % P.E;
     for (int t = lane; t < bn; t += kWave) {
       uint64_t k = keys[b0 + t];
       int32_t jj = (int32_t)(k >> 24);
@@ -383,12 +377,13 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
 }
 
 // Reverse index: for pair (i, j, n) find (j, i, -n) in j's list by binary
-// search inside the bucket (species of i, shell of q) of j.
+// search inside j's bucket (shell of q, species of i).
 __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev nb, uint32_t *status) {
   const int64_t N = bt.n_atoms;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (i >= N) return;
   const int lane = lane_id();
+  const int nbk = P.E * P.S;
   const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
   const double *cell = bt.cell + 9 * (int64_t)s;
   const int pbc = bt.pbc[s] & 7;
@@ -407,11 +402,9 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
     double dy = (nb.rw[N + j] - riy) + shy;
     double dz = (nb.rw[2 * N + j] - riz) + shz;
     double q = (dx * dx + dy * dy) + dz * dz;
-    const int h = shell_of(P, q);
-    const int32_t *es = nb.elem_start + (int64_t)j * (P.E + 1);
-    const int32_t *se = nb.sigma_end + ((int64_t)j * P.E + ei) * P.S;
-    int lo = P.shell_prev_sig[h] < 0 ? es[ei] : se[P.shell_prev_sig[h]];
-    int hi = P.shell_end_sig[h] < 0 ? lo : se[P.shell_end_sig[h]];
+    const int b = shell_of(P, q) * P.E + ei;
+    const int32_t *bs = nb.bucket_start + (int64_t)j * (nbk + 1);
+    int lo = bs[b], hi = bs[b + 1];
     const uint64_t key = make_key(i, -n1, -n2, -n3);
     const int64_t jb = nb.offsets[j];
     int found = -1;

@@ -23,6 +23,10 @@
 //              products in FP32; accumulation as FP32 (hi, lo) two-sum pairs;
 //              cross-lane reduction in FP64.
 //   F64=true   everything FP64 (exp in FP64), plain accumulation.
+#include <map>
+#include <mutex>
+#include <type_traits>
+
 #include "gmp_internal.h"
 
 namespace gmp {
@@ -30,50 +34,10 @@ namespace {
 
 constexpr MonoTable kMT = make_mono_table();
 
-template <bool F64> struct Real;
-template <> struct Real<false> { using T = float; };
-template <> struct Real<true> { using T = double; };
-
 __device__ inline float exp_scaled(float a, float q) { return __builtin_amdgcn_exp2f(a * q); }
 __device__ inline double exp_scaled(double a, double q) { return exp(a * q); }
-
 __device__ inline float fma_(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c); }
-
-template <bool F64> __device__ inline const typename Real<F64>::T *coef_ptr(const PlanDev &P, int s, int e);
-template <> __device__ inline const float *coef_ptr<false>(const PlanDev &P, int s, int e) {
-  return P.coef32 + ((size_t)(s * P.E + e) * P.kmax) * kCoefStride;
-}
-template <> __device__ inline const double *coef_ptr<true>(const PlanDev &P, int s, int e) {
-  return P.coef64 + ((size_t)(s * P.E + e) * P.kmax) * kCoefStride;
-}
-
-// Accumulator of one sigma: two-sum pairs in FP32, plain sum in FP64.
-template <bool F64, int NM> struct Acc;
-template <int NM> struct Acc<false, NM> {
-  float hi[NM], lo[NM];
-  __device__ void zero() {
-#pragma unroll
-    for (int m = 0; m < NM; ++m) { hi[m] = 0.f; lo[m] = 0.f; }
-  }
-  __device__ void add(int m, float p) {
-    float s = hi[m] + p;
-    float bp = s - hi[m];
-    float ap = s - bp;
-    lo[m] += (hi[m] - ap) + (p - bp);
-    hi[m] = s;
-  }
-  __device__ double value(int m) const { return (double)hi[m] + (double)lo[m]; }
-};
-template <int NM> struct Acc<true, NM> {
-  double v[NM];
-  __device__ void zero() {
-#pragma unroll
-    for (int m = 0; m < NM; ++m) v[m] = 0.0;
-  }
-  __device__ void add(int m, double p) { v[m] += p; }
-  __device__ double value(int m) const { return v[m]; }
-};
 
 // Chunks of one centre's list: fixed-size pieces of kc pairs (kc = 0: whole
 // list), so the decomposition of a centre depends on its own list only and
@@ -85,6 +49,13 @@ __global__ void k_chunk_count(NbrDev nb, int64_t N, int kc, int64_t *nch) {
   nch[i] = kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1;
 }
 
+// AoS copy of the wrapped positions: one 32-byte gather per neighbour.
+__global__ void k_pack_rw(NbrDev nb, int64_t N, double4 *rw4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  rw4[i] = make_double4(nb.rw[i], nb.rw[N + i], nb.rw[2 * N + i], 0.0);
+}
+
 __device__ inline int64_t centre_of_chunk(const int64_t *chunk_off, int64_t N, int64_t q) {
   int64_t lo = 0, hi = N;  // chunk_off[lo] <= q < chunk_off[lo+1]
   while (hi - lo > 1) {
@@ -94,108 +65,229 @@ __device__ inline int64_t centre_of_chunk(const int64_t *chunk_off, int64_t N, i
   return lo;
 }
 
-template <int LMAX, int G, bool F64>
-__global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, double *partial,
-                                                 const int64_t *chunk_off, int n_groups, int kc,
-                                                 int64_t n_items) {
-  using T = typename Real<F64>::T;
-  constexpr int NM = nmono(LMAX);
-  const int lane = lane_id();
-  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (item >= n_items) return;
-  const int64_t N = bt.n_atoms;
-  const int64_t qc = item / n_groups;
-  const int g = (int)(item - qc * n_groups);
-  if (qc >= chunk_off[N]) return;
-  const int64_t i = centre_of_chunk(chunk_off, N, qc);
-  const int c = (int)(qc - chunk_off[i]);
-  const int S = P.S, E = P.E;
+// Accumulation policies of the overlap kernel.
+enum AccMode { ACC_F64 = 0, ACC_TWOSUM = 1, ACC_WIDE = 2 };
 
-  const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
-  const double *cell = bt.cell + 9 * (int64_t)st;
-  const int pbc = bt.pbc[st] & 7;
-  const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
-  const int64_t base = nb.offsets[i];
-  const int cnt = (int)(nb.offsets[i + 1] - base);
-  const int clo = kc > 0 ? c * kc : 0;
-  const int chi = kc > 0 ? (clo + kc < cnt ? clo + kc : cnt) : cnt;
-
-  int sg[G];
+// Per-lane accumulator of one sigma's moments.
+template <int MODE, int NM> struct Acc;
+// FP32 (hi, lo) pairs updated with Knuth's error-free two-sum.
+template <int NM> struct Acc<ACC_TWOSUM, NM> {
+  float hi[NM], lo[NM];
+  __device__ void zero() {
 #pragma unroll
-  for (int t = 0; t < G; ++t) {
-    int gi = g * G + t;
-    sg[t] = gi < S ? P.sig_order[gi] : -1;
+    for (int m = 0; m < NM; ++m) { hi[m] = 0.f; lo[m] = 0.f; }
   }
-  Acc<F64, NM> acc[G];
+  __device__ void add(int m, float p) {
+    const float s = hi[m] + p;
+    const float bp = s - hi[m];
+    const float ap = s - bp;
+    lo[m] += (hi[m] - ap) + (p - bp);
+    hi[m] = s;
+  }
+  __device__ double value(int m) const { return (double)hi[m] + (double)lo[m]; }
+};
+// FP64 accumulators (FP64 path and the wide FP32 path).
+template <int NM> struct Acc<ACC_F64, NM> {
+  double v[NM];
+  __device__ void zero() {
 #pragma unroll
-  for (int t = 0; t < G; ++t) acc[t].zero();
+    for (int m = 0; m < NM; ++m) v[m] = 0.0;
+  }
+  __device__ double value(int m) const { return v[m]; }
+};
+template <int NM> struct Acc<ACC_WIDE, NM> : Acc<ACC_F64, NM> {};
 
-  for (int e = 0; e < E; ++e) {
-    const int es = nb.elem_start[i * (E + 1) + e];
-    const int lo = es > clo ? es : clo;
-    int endg[G];
-    int emax = lo;
+// Fixed-order cross-lane sum of NV per-lane doubles, written to dst[0..NV):
+// rounds of 8 columns are transposed through LDS (each lane sums 8 rows of
+// one column), then the 8 row-group partials are combined with xor shuffles.
+// Every lane of a column group computes the same bits; lanes 0..7 store.
+template <int NV>
+__device__ inline void wave_reduce_store(const double (&v)[NV], double *dst, double *lds) {
+  const int lane = lane_id();
+  const int col = lane & 7, grp = lane >> 3;
 #pragma unroll
-    for (int t = 0; t < G; ++t) {
-      int en = lo;
-      if (sg[t] >= 0) {
-        en = nb.sigma_end[(i * E + e) * S + sg[t]];
-        en = en < chi ? en : chi;
-      }
-      endg[t] = en;
-      emax = en > emax ? en : emax;
+  for (int base = 0; base < NV; base += 8) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (base + c < NV) lds[lane * 9 + c] = v[base + c];
+    wave_lds_sync();
+    double s = 0.0;
+    if (base + col < NV) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) s += lds[(grp * 8 + r) * 9 + col];
     }
-    if (emax <= lo) continue;
-    const int K = P.kcount[e];
-    for (int p0 = lo; p0 < emax; p0 += kWave) {
-      const int p = p0 + lane;
-      const bool act = p < emax;
-      int32_t j = (int32_t)i, w = 0;
-      if (act) { j = nb.j[base + p]; w = nb.shift[base + p]; }
-      double shx = 0.0, shy = 0.0, shz = 0.0;
-      if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
-      const double dx = (nb.rw[j] - rix) + shx;
-      const double dy = (nb.rw[N + j] - riy) + shy;
-      const double dz = (nb.rw[2 * N + j] - riz) + shz;
-      const double q = (dx * dx + dy * dy) + dz * dz;
-      const T xv = (T)dx, yv = (T)dy, zv = (T)dz, qv = (T)q;
-      T mono[NM];
-      mono[0] = (T)1;
-#pragma unroll
-      for (int m = 1; m < NM; ++m) {
-        const T v = kMT.var[m] == 0 ? xv : (kMT.var[m] == 1 ? yv : zv);
-        mono[m] = v * mono[kMT.parent[m]];
+    s += __shfl_xor(s, 8, kWave);
+    s += __shfl_xor(s, 16, kWave);
+    s += __shfl_xor(s, 32, kWave);
+    if (lane < 8 && base + lane < NV) dst[base + lane] = s;
+    wave_lds_sync();
+  }
+}
+
+template <int MODE, int NM> __device__ inline double acc_value(const Acc<MODE, NM> &a, int m) { return a.value(m); }
+
+// Overlap kernel, persistent: every wavefront pulls work items (one chunk
+// of one centre's list) from a global counter until none are left, and
+// walks the sigmas of the item one after another in cutoff order, each over
+// its own prefix of the chunk.  The loads of pair data (j, shift) run two
+// steps ahead and the gathers of the neighbours' wrapped positions one step
+// ahead, continuously across the sigma passes.  Every monomial of degree
+// <= LMAX is accumulated (moments of orders that were not requested are
+// simply not read back).
+//
+// The coefficient table [sigma][element][KB][8] (exponent scale, A_0..A_4,
+// -gamma) is copied into LDS once per workgroup when it fits; lanes read
+// the row of their own neighbour's species.
+template <int LMAX, int KB, int MODE, bool LDS>
+__global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
+                                                 double *partial, const int64_t *chunk_off, int kc,
+                                                 unsigned long long *counter, const void *tab_global) {
+  constexpr bool F64 = MODE == ACC_F64;
+  using TR = typename std::conditional<F64, double, float>::type;                 // radial arithmetic
+  using TM = typename std::conditional<MODE == ACC_TWOSUM, float, double>::type;  // monomials
+  constexpr int NM = nmono(LMAX);
+  extern __shared__ double lds_dyn[];
+  __shared__ double lds_red[4][64 * 9];
+  __shared__ int lds_k[kMaxElements];
+  const int S = P.S, E = P.E;
+  const TR *__restrict__ tabg = (const TR *)tab_global;
+  TR *tabl = (TR *)lds_dyn;
+  if (LDS) {
+    const int n = S * E * KB * kCoefStride;
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) tabl[idx] = tabg[idx];
+  }
+  for (int e = threadIdx.x; e < E; e += blockDim.x) lds_k[e] = P.kcount[e];
+  __syncthreads();
+
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  const int64_t N = bt.n_atoms;
+  const int64_t n_items = chunk_off[N];
+  for (;;) {
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(counter, 1ull);
+    const int64_t qc = (int64_t)__shfl(it, 0, kWave);
+    if (qc >= n_items) break;
+    const int64_t i = centre_of_chunk(chunk_off, N, qc);
+    const int c = (int)(qc - chunk_off[i]);
+    const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+    const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
+    const int pbc = bt.pbc[st] & 7;
+    const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+    const int64_t base = nb.offsets[i];
+    const int cnt = (int)(nb.offsets[i + 1] - base);
+    const int clo = kc > 0 ? c * kc : 0;
+    const int chi = kc > 0 ? (clo + kc < cnt ? clo + kc : cnt) : cnt;
+    // per-item pass ends and sigma order, one per lane (lane t <-> t-th sigma by cutoff)
+    int end_lane = clo, so_lane = 0;
+    if (lane < S) {
+      so_lane = P.sig_order[lane];
+      const int en = nb.sigma_end[i * S + so_lane];
+      end_lane = en < chi ? en : chi;
+    }
+    auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+    auto pass_end = [&](int t) { return __builtin_amdgcn_readlane(end_lane, t); };
+    double *dst_item = partial + (size_t)qc * S * NM;
+    // sigmas whose prefix misses this chunk contribute zero moments
+    for (int t = 0; t < S; ++t)
+      if (pass_end(t) <= clo)
+        for (int m = lane; m < NM; m += kWave)
+          dst_item[(size_t)__builtin_amdgcn_readlane(so_lane, t) * NM + m] = 0.0;
+    // step iterator over (sigma pass t, pair block p0); pass ends are non-decreasing in t
+    int tb = 0, pb = clo;
+    while (tb < S && pass_end(tb) <= clo) ++tb;
+    if (tb >= S) continue;
+    int tc = tb, pc = pb;
+    auto advance = [&](int &t, int &p) {
+      p += kWave;
+      if (p >= pass_end(t)) {
+        ++t;
+        p = clo;
+        while (t < S && pass_end(t) <= clo) ++t;
       }
+      t = uni(t);
+      p = uni(p);
+    };
+    advance(tc, pc);
+    const int32_t ii = (int32_t)i;
+    // stage b: positions gathered; stage c: (j, shift) loaded
+    int32_t wb = 0, jc = ii, wc = 0;
+    double4 rb;
+    {
+      int32_t jb = ii;
+      const int p = pb + lane;
+      if (p < pass_end(tb)) { jb = nb.j[base + p]; wb = nb.shift[base + p]; }
+      if (tc < S && pc + lane < pass_end(tc)) { jc = nb.j[base + pc + lane]; wc = nb.shift[base + pc + lane]; }
+      rb = rw4[jb];
+    }
+    Acc<MODE, NM> acc;
+    acc.zero();
+    while (tb < S) {
+      const int ta = tb, pa = pb;
+      const int32_t w = wb;
+      const double rjx = rb.x, rjy = rb.y, rjz = rb.z;
+      // advance the pipeline
+      tb = tc; pb = pc; wb = wc;
+      rb = rw4[jc];
+      jc = ii; wc = 0;
+      if (tc < S) {
+        advance(tc, pc);
+        if (tc < S && pc + lane < pass_end(tc)) { jc = nb.j[base + pc + lane]; wc = nb.shift[base + pc + lane]; }
+      }
+      // current step: sigma sig_order[ta], pairs pa + lane
+      const int sgm = __builtin_amdgcn_readlane(so_lane, ta);
+      const int p = pa + lane;
+      if (p < pass_end(ta)) {
+        double shx = 0.0, shy = 0.0, shz = 0.0;
+        if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
+        const double dx = (rjx - rix) + shx;
+        const double dy = (rjy - riy) + shy;
+        const double dz = (rjz - riz) + shz;
+        const double q = (dx * dx + dy * dy) + dz * dz;
+        const TR qv = (TR)q;
+        const int e = shift_species(w);
+        const int K = lds_k[e];
+        const size_t roff = ((size_t)(sgm * E + e) * KB) * kCoefStride;
+        TR cl[LMAX + 1];
 #pragma unroll
-      for (int t = 0; t < G; ++t) {
-        if (p < endg[t]) {
-          const T *cf = coef_ptr<F64>(P, sg[t], e);
-          T cl[LMAX + 1];
+        for (int l = 0; l <= LMAX; ++l) cl[l] = (TR)0;
 #pragma unroll
-          for (int l = 0; l <= LMAX; ++l) cl[l] = (T)0;
-          for (int k = 0; k < K; ++k) {
-            const T ek = exp_scaled(cf[k * kCoefStride], qv);
+        for (int k = 0; k < KB; ++k) {
+          if (k < K) {
+            const size_t o = roff + k * kCoefStride;
+            const TR ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
 #pragma unroll
-            for (int l = 0; l <= LMAX; ++l) cl[l] = fma_(cf[k * kCoefStride + 1 + l], ek, cl[l]);
-          }
-#pragma unroll
-          for (int m = 0; m < NM; ++m) {
-            if ((P.order_mask >> kMT.deg[m]) & 1) acc[t].add(m, cl[kMT.deg[m]] * mono[m]);
+            for (int l = 0; l <= LMAX; ++l) cl[l] = fma_(LDS ? tabl[o + 1 + l] : tabg[o + 1 + l], ek, cl[l]);
           }
         }
+        TM mono[NM];
+        {
+          const TM xv = (TM)dx, yv = (TM)dy, zv = (TM)dz;
+          mono[0] = (TM)1;
+#pragma unroll
+          for (int m = 1; m < NM; ++m) {
+            const TM v = kMT.var[m] == 0 ? xv : (kMT.var[m] == 1 ? yv : zv);
+            mono[m] = v * mono[kMT.parent[m]];
+          }
+        }
+        if constexpr (MODE == ACC_TWOSUM) {
+#pragma unroll
+          for (int m = 0; m < NM; ++m) acc.add(m, cl[kMT.deg[m]] * mono[m]);
+        } else {
+          double cd[LMAX + 1];
+#pragma unroll
+          for (int l = 0; l <= LMAX; ++l) cd[l] = (double)cl[l];
+#pragma unroll
+          for (int m = 0; m < NM; ++m) acc.v[m] = fma(cd[kMT.deg[m]], mono[m], acc.v[m]);
+        }
       }
-    }
-  }
-  // cross-lane reduction in FP64; partial layout [chunk][sigma][monomial]
+      if (tb != ta) {  // the pass of sigma sgm is complete: FP64 cross-lane reduction, store, restart
+        double vals[NM];
 #pragma unroll
-  for (int t = 0; t < G; ++t) {
-    if (sg[t] < 0) continue;
-    double *dst = partial + ((size_t)qc * S + sg[t]) * NM;
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      if (!((P.order_mask >> kMT.deg[m]) & 1)) continue;
-      const double v = wave_sum(acc[t].value(m));
-      if (lane == (m & (kWave - 1))) dst[m] = v;
+        for (int m = 0; m < NM; ++m) vals[m] = acc.value(m);
+        wave_reduce_store<NM>(vals, dst_item + (size_t)sgm * NM, lds_red[wv]);
+        acc.zero();
+      }
     }
   }
 }
@@ -255,29 +347,36 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
   }
 }
 
-using OverlapFn = void (*)(PlanDev, BatchDev, NbrDev, double *, const int64_t *, int, int, int64_t);
+using OverlapFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, double *, const int64_t *, int,
+                           unsigned long long *, const void *);
 
-template <int L, bool F64> OverlapFn pick_g(int G) {
-  if (G >= 4) return k_overlap<L, 4, F64>;
-  if (G == 2) return k_overlap<L, 2, F64>;
-  return k_overlap<L, 1, F64>;
+template <int L, int MODE, bool LDS> OverlapFn pick_k(int kb) {
+  if (kb <= 4) return k_overlap<L, 4, MODE, LDS>;
+  if (kb <= 8) return k_overlap<L, 8, MODE, LDS>;
+  return k_overlap<L, 16, MODE, LDS>;
 }
 
-template <bool F64> OverlapFn pick(int lmax, int G) {
+template <int MODE, bool LDS> OverlapFn pick_l(int lmax, int kb) {
   switch (lmax) {
-    case 0: return pick_g<0, F64>(G);
-    case 1: return pick_g<1, F64>(G);
-    case 2: return pick_g<2, F64>(G);
-    case 3: return pick_g<3, F64>(G);
-    default: return pick_g<4, F64>(G);
+    case 0: return pick_k<0, MODE, LDS>(kb);
+    case 1: return pick_k<1, MODE, LDS>(kb);
+    case 2: return pick_k<2, MODE, LDS>(kb);
+    case 3: return pick_k<3, MODE, LDS>(kb);
+    default: return pick_k<4, MODE, LDS>(kb);
   }
+}
+
+template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb) {
+  if (prec == GMP_FP64) return pick_l<ACC_F64, LDS>(lmax, kb);
+  if (prec == GMP_FP32_WIDE) return pick_l<ACC_WIDE, LDS>(lmax, kb);
+  return pick_l<ACC_TWOSUM, LDS>(lmax, kb);
 }
 
 }  // namespace
 
 int normalized_group(const gmp_plan *p) {
   int G = p->tuning.sigma_group;
-  if (G >= 4) G = 4; else if (G >= 2) G = 2; else G = 1;
+  if (G >= 4 && p->dev.lmax <= 2) G = 4; else if (G >= 2) G = 2; else G = 1;
   return G;
 }
 
@@ -289,19 +388,44 @@ int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs) {
   return n_atoms + (kc > 0 ? pairs / kc + 1 : 0);
 }
 
+int persistent_blocks(const void *fn, size_t smem) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, size_t>, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(fn, smem);
+  auto itc = cache.find(key);
+  if (itc != cache.end()) return itc->second;
+  int dev = 0, cus = 256, per = 2;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, smem) != hipSuccess || per < 1) per = 1;
+  const int blocks = cus * per;
+  cache[key] = blocks;
+  return blocks;
+}
+
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
-                    int64_t *chunk_off, int64_t *scan_aux, int64_t pairs_bound, hipStream_t s) {
+                    int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
+                    int64_t pairs_bound, hipStream_t s) {
   const int64_t N = bt.n_atoms;
-  const int G = normalized_group(p);
-  const int n_groups = (p->dev.S + G - 1) / G;
   const int kc = chunk_size(p);
   GMP_LAUNCH("overlap_chunks", k_chunk_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, nb, N, kc, nch);
+  GMP_LAUNCH("pack_positions", k_pack_rw, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, nb, N, rw4);
   scan_i64(nch, chunk_off, N, scan_aux, s);
-  const int64_t n_items = max_chunks(p, N, pairs_bound) * n_groups;
-  const int64_t blocks = (n_items + 3) / 4;
-  OverlapFn fn = p->prec == GMP_FP64 ? pick<true>(p->dev.lmax, G) : pick<false>(p->dev.lmax, G);
-  GMP_LAUNCH("overlap", fn, dim3((unsigned)blocks), dim3(256), 0, s, p->dev, bt, nb, partial, chunk_off, n_groups,
-             kc, n_items);
+  fill_zero(counter, sizeof(unsigned long long), s);
+  const bool f64 = p->prec == GMP_FP64;
+  const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
+  const bool use_lds = tab_bytes <= 48 * 1024;
+  const size_t smem = use_lds ? tab_bytes : 0;
+  const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
+  OverlapFn fn = use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb) : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb);
+  const int64_t items_bound = max_chunks(p, N, pairs_bound);
+  int64_t blocks = persistent_blocks((const void *)fn, smem);
+  const int64_t need = (items_bound + 3) / 4;
+  if (blocks > need) blocks = need;
+  if (blocks < 1) blocks = 1;
+  GMP_LAUNCH("overlap", fn, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, (const double4 *)rw4, partial,
+             chunk_off, kc, counter, tab);
 }
 
 void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off, void *features,

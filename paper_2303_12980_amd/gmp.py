@@ -57,7 +57,7 @@ class GMPPlan:
         self._B = np.ascontiguousarray(B, dtype=np.float64)
         self._beta = np.ascontiguousarray(beta, dtype=np.float64)
         self.tau = float(overlap_threshold)
-        prec = {"fp64": _lib.GMP_FP64, "fp32c": _lib.GMP_FP32_COMPENSATED}[precision]
+        prec = {"fp64": _lib.GMP_FP64, "fp32c": _lib.GMP_FP32_COMPENSATED, "fp32w": _lib.GMP_FP32_WIDE}[precision]
         self.precision = precision
         d = _lib.ProbeDesc(len(self._orders), self._orders.ctypes.data_as(_lib.P_i32),
                            len(self._sigmas), self._sigmas.ctypes.data_as(_lib.P_dbl),
@@ -168,15 +168,15 @@ class Neighbors:
         self.offsets = torch.zeros(N + 1, dtype=torch.int64, device=dev)
         self.j = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
         self.shift = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
-        self.elem_start = torch.empty(N * (E + 1), dtype=torch.int32, device=dev)
-        self.sigma_end = torch.empty(N * E * S, dtype=torch.int32, device=dev)
+        self.bucket_start = torch.empty(N * (S * E + 1), dtype=torch.int32, device=dev)
+        self.sigma_end = torch.empty(N * S, dtype=torch.int32, device=dev)
         self.wrap = torch.empty(N * 3, dtype=torch.int32, device=dev)
         self.rw = torch.empty(3 * N, dtype=torch.float64, device=dev)
         self.reverse = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev) if reverse else None
 
     def desc(self):
         return _lib.NbrDesc(self.capacity, self.n_pairs, self.offsets.data_ptr(), self.j.data_ptr(),
-                            self.shift.data_ptr(), self.elem_start.data_ptr(), self.sigma_end.data_ptr(),
+                            self.shift.data_ptr(), self.bucket_start.data_ptr(), self.sigma_end.data_ptr(),
                             self.wrap.data_ptr(), self.rw.data_ptr(),
                             self.reverse.data_ptr() if self.reverse is not None else 0)
 

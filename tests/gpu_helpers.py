@@ -34,8 +34,8 @@ def check_neighbors(nb, batch_np, probes, centres=None):
     J = nb.j[:P].cpu().numpy()
     n, e = nb.shifts_numpy()
     E, S = probes.n_elements, len(probes.sigmas)
-    es = nb.elem_start.cpu().numpy().reshape(-1, E + 1)
-    se = nb.sigma_end.cpu().numpy().reshape(-1, E, S)
+    bs = nb.bucket_start.cpu().numpy().reshape(-1, S * E + 1)
+    se = nb.sigma_end.cpu().numpy().reshape(-1, S)
     wrap = nb.wrap.cpu().numpy().reshape(-1, 3)
     rw = nb.rw.cpu().numpy().reshape(3, -1).T
     checked = 0
@@ -54,12 +54,12 @@ def check_neighbors(nb, batch_np, probes, centres=None):
             assert np.array_equal(J[lo:hi], ref["j"] + a0)
             assert np.array_equal(n[lo:hi], ref["n"])
             assert np.array_equal(e[lo:hi], ref["e"])
-            # segment starts and sigma prefixes
-            for ee in range(E + 1):
-                assert es[gi, ee] == int(np.sum(ref["e"] < ee))
-            for ee in range(E):
-                for ss in range(S):
-                    assert se[gi, ee, ss] == int(np.sum(ref["e"] < ee) + np.sum((ref["e"] == ee) & (ref["q"] <= rc2[ss])))
+            # bucket starts (shell-major, species-minor) and sigma prefixes
+            bucket = ref["shell"] * E + ref["e"]
+            for b in range(S * E + 1):
+                assert bs[gi, b] == int(np.sum(bucket < b))
+            for ss in range(S):
+                assert se[gi, ss] == int(np.sum(ref["q"] <= rc2[ss]))
             checked += 1
     return checked
 

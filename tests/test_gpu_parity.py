@@ -54,7 +54,7 @@ def _small_batch(seed):
     return gs.make_batch(structs), probes
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32w"])
 def test_c1_neighbors_bit_exact(g, ws, c1, precision):
     b, p, _ = c1
     say(f"[c1 neighbours {precision}]")
@@ -73,15 +73,16 @@ def test_c1_features_fp64(g, ws, c1):
     say(f"  max rel {r:.2e}")
 
 
-def test_c1_features_fp32c(g, ws, c1):
+@pytest.mark.parametrize("precision", ["fp32c", "fp32w"])
+def test_c1_features_fp32(g, ws, c1, precision):
     b, p, (Fref, muref) = c1
-    say("[c1 features fp32c]")
-    plan, db, nb, F, mu = run_path(g, b, p, "fp32c", ws)
+    say(f"[c1 features {precision}]")
+    plan, db, nb, F, mu = run_path(g, b, p, precision, ws)
     r, a = assert_features(F.cpu().numpy(), Fref, p.tau, 1e-5)
     say(f"  max rel {r:.2e}")
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32c", 1e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32c", 1e-5), ("fp32w", 1e-5)])
 def test_small_batch_mixed_structures(g, ws, precision, tol):
     b, p = _small_batch(3)
     say(f"[small batch {precision}]")
@@ -101,15 +102,16 @@ def test_chunked_overlap_matches(g, ws, c1, chunk):
     assert_features(F.cpu().numpy(), Fref, p.tau, 1e-11)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32w"])
 @pytest.mark.parametrize("sg", [1, 2, 4])
-def test_sigma_groups(g, ws, c1, sg):
+def test_sigma_groups(g, ws, c1, sg, precision):
     b, p, (Fref, _) = c1
-    say(f"[c1 sigma group {sg}]")
-    plan, db, nb, F, mu = run_path(g, b, p, "fp32c", ws, tuning=dict(sigma_group=sg))
+    say(f"[c1 sigma group {sg} {precision}]")
+    plan, db, nb, F, mu = run_path(g, b, p, precision, ws, tuning=dict(sigma_group=sg))
     assert_features(F.cpu().numpy(), Fref, p.tau, 1e-5)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32c", 1e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32c", 1e-5), ("fp32w", 1e-5)])
 def test_backward_vs_oracle(g, ws, precision, tol):
     rng = np.random.default_rng(17)
     structs = [gs.small_periodic(rng, n_atoms=12, n_elements=2, density=0.06, dmin=1.3),
@@ -132,14 +134,15 @@ def test_backward_vs_oracle(g, ws, precision, tol):
         assert ep <= tol * scale and ec <= tol * scale
 
 
-def test_deterministic_and_batch_invariant(g, ws):
+@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32w"])
+def test_deterministic_and_batch_invariant(g, ws, precision):
     b, p = _small_batch(5)
-    say("[determinism]")
-    plan, db, nb, F1, mu1 = run_path(g, b, p, "fp32c", ws)
-    _, _, _, F2, mu2 = run_path(g, b, p, "fp32c", ws)
+    say(f"[determinism {precision}]")
+    plan, db, nb, F1, mu1 = run_path(g, b, p, precision, ws)
+    _, _, _, F2, mu2 = run_path(g, b, p, precision, ws)
     assert torch.equal(F1, F2) and torch.equal(mu1, mu2)
     for s in range(b.n_structs):
         one = gs.make_batch([b.structure(s)])
-        _, _, _, Fs, _ = run_path(g, one, p, "fp32c", ws)
+        _, _, _, Fs, _ = run_path(g, one, p, precision, ws)
         a0, a1 = b.atom_offsets[s], b.atom_offsets[s + 1]
         assert torch.equal(Fs, F1[a0:a1])
