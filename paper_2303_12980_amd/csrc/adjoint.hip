@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
     const int64_t base = nb.offsets[i];
     const int cnt = (int)(nb.offsets[i + 1] - base);
     const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
-    const int32_t *se = nb.sigma_end + i * S;
+    // sigma prefix ends, one per lane (lane s <-> sigma s)
+    const int end_lane = lane < S ? nb.sigma_end[i * S + lane] : 0;
     for (int p0 = clo; p0 < chi; p0 += kWave) {
       const int p = p0 + lane;
       const bool act = p < chi;
@@ -166,7 +167,8 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
       }
       double vx = 0.0, vy = 0.0, vz = 0.0;
       for (int s = 0; s < S; ++s) {
-        if (!(act && p < se[s])) continue;
+        const int ends = __builtin_amdgcn_readlane(end_lane, s);
+        if (!(act && p < ends)) continue;
         const size_t roff = ((size_t)(s * E + e) * KB) * kCoefStride;
         const T *bc = bcoef + (size_t)s * NB;
         T cl[LMAX + 1], cp[LMAX + 1];
@@ -242,7 +244,8 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BatchDev bt, NbrDev nb, cons
     const int32_t j = nb.j[p];
     const int32_t w = nb.shift[p];
     const int32_t rv = nb.reverse[p];
-    if (rv < 0) continue;  // flagged by the neighbour build; never for a consistent list
+    // a missing mirror is flagged by the neighbour build; never for a consistent list
+    if (rv < 0 || (int64_t)rv >= nb.offsets[j + 1] - nb.offsets[j]) continue;
     const T *va = vbuf + (size_t)p * 4;
     const T *vr = vbuf + (size_t)(nb.offsets[j] + rv) * 4;
     const double v0 = (double)va[0], v1 = (double)va[1], v2 = (double)va[2];

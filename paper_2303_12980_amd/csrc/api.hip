@@ -19,7 +19,8 @@ void launch_scatter(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int
 void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, hipStream_t s);
 void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int lds_keys,
                  hipStream_t s);
-void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, hipStream_t s);
+void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,
+                    hipStream_t s);
 int normalized_group(const gmp_plan *p);
 int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs);
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
@@ -114,6 +115,8 @@ WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t capacity, vo
   L.chunk_off = c.take<int64_t>(N + 1);
   L.counter = c.take<unsigned long long>(32);
   L.rw4 = c.take<double4>(N);
+  L.pair_key = c.take<uint64_t>((size_t)capacity);
+  L.pair_centre = c.take<int32_t>((size_t)capacity);
   L.bcoef = c.take<char>(bwd_coef_elems(p, N) * tsz);
   L.vbuf = c.take<char>((size_t)capacity * 4 * tsz);
   L.cellpart = c.take<double>((size_t)N * 9);
@@ -555,7 +558,7 @@ gmp_status gmp_build_neighbors(const gmp_plan *p, const gmp_batch *b, gmp_neighb
     lds_keys = lds_keys_for(p, kSortMax);
   }
   launch_fill(p, bt, nb, L, lds_keys, s);
-  if (n->reverse) launch_reverse(p, bt, nb, L, s);
+  if (n->reverse) launch_reverse(p, bt, nb, L, n_pairs ? *n_pairs : n->capacity, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "neighbour kernels");
   return GMP_OK;

@@ -76,6 +76,7 @@ struct StructInfo {
   int nb[3];          // bins per axis
   int pbc;
   int64_t bin_base;   // first bin slot of this structure
+  double lam_lo;      // lower bound of the smallest eigenvalue of the lattice metric (0: no bin culling)
 };
 
 // Device view of a plan (passed by value to kernels).
@@ -222,6 +223,8 @@ struct WsLayout {
   int64_t *chunk_off;     // [N+1] first chunk of each centre
   unsigned long long *counter;  // work-item counter of the persistent kernels
   double4 *rw4;           // [N] AoS copy of the wrapped positions
+  uint64_t *pair_key;     // [capacity] packed (j, n) of every pair (reverse search)
+  int32_t *pair_centre;   // [capacity] centre of every pair (reverse search)
   void *bcoef;            // adjoint per-centre polynomial coefficients
   void *vbuf;             // adjoint per-pair vectors [capacity][4]
   double *cellpart;       // [N][9]

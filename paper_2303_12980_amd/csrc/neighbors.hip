@@ -42,6 +42,7 @@ __global__ void k_struct_setup(BatchDev bt, StructInfo *info, double rcmax, int 
   I.bin_base = bt.atom_offsets[s] + s;
   for (int k = 0; k < 9; ++k) I.b[k] = 0.0;
   for (int k = 0; k < 3; ++k) { I.nb[k] = 1; I.reach[k] = 0.0; }
+  I.lam_lo = 0.0;
   if (pbc) {
     const double *a = bt.cell + 9 * (int64_t)s;
     double c23[3], c31[3], c12[3];
@@ -67,6 +68,30 @@ __global__ void k_struct_setup(BatchDev bt, StructInfo *info, double rcmax, int 
         I.reach[k] = rcmax * inv_h * (1.0 + 1e-12) + 1e-12;
         // image shifts must fit a signed byte
         if (I.reach[k] + 2.0 > 126.0) atomicOr(status, ST_SHIFT_RANGE);
+      }
+      // smallest eigenvalue of the metric G = A A^T (rows of A are the lattice vectors), for a lower
+      // bound |n.A|^2 >= lambda_min |n|^2 that lets the cell list skip bin images outside the cutoff
+      {
+        double Gm[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) Gm[r][c] = dot3(a + 3 * r, a + 3 * c);
+        const double p1 = Gm[0][1] * Gm[0][1] + Gm[0][2] * Gm[0][2] + Gm[1][2] * Gm[1][2];
+        const double qq = (Gm[0][0] + Gm[1][1] + Gm[2][2]) / 3.0;
+        const double d0 = Gm[0][0] - qq, d1 = Gm[1][1] - qq, d2 = Gm[2][2] - qq;
+        const double p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1;
+        double lmin;
+        if (p2 <= 0.0) {
+          lmin = qq;
+        } else {
+          const double pp = sqrt(p2 / 6.0);
+          const double b00 = d0 / pp, b11 = d1 / pp, b22 = d2 / pp;
+          const double b01 = Gm[0][1] / pp, b02 = Gm[0][2] / pp, b12 = Gm[1][2] / pp;
+          double r = 0.5 * (b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02));
+          r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+          const double phi = acos(r) / 3.0;
+          lmin = qq + 2.0 * pp * cos(phi + 2.0943951023931957);
+        }
+        I.lam_lo = (isfinite(lmin) && lmin > 0.0) ? 0.99 * lmin : 0.0;
       }
       // never more bins than atoms (bin slots per structure are n_s + 1)
       int64_t cap = n_s > 1 ? n_s : 1;
@@ -160,6 +185,7 @@ __device__ inline void vrange(const StructInfo &I, int k, double f, int &lo, int
 struct Cand {
   const StructInfo *I;
   const double *cell;
+  double f[3];
   int lo[3], hi[3], nv[3];
   int total;
 };
@@ -169,30 +195,106 @@ __device__ inline void cand_setup(Cand &C, const StructInfo *info, const BatchDe
   const int64_t N = bt.n_atoms;
   C.I = info + s;
   C.cell = bt.cell + 9 * (int64_t)s;
-  const double f[3] = {fw[i], fw[N + i], fw[2 * N + i]};
+  C.f[0] = fw[i]; C.f[1] = fw[N + i]; C.f[2] = fw[2 * N + i];
   C.total = 1;
   for (int k = 0; k < 3; ++k) {
-    vrange(*C.I, k, f[k], C.lo[k], C.hi[k]);
+    vrange(*C.I, k, C.f[k], C.lo[k], C.hi[k]);
     C.nv[k] = C.hi[k] - C.lo[k] + 1;
     C.total *= C.nv[k];
   }
 }
 
-// virtual bin v (linear index) -> real bin slot and image shift
-__device__ inline int64_t cand_bin(const Cand &C, int v, int n[3]) {
+// Virtual bin v (linear index) -> real bin slot and image shift; returns -1
+// when the whole bin image lies outside the cutoff sphere (fractional gaps
+// g_k to the centre satisfy lam_lo * |g|^2 > rc_max^2).
+__device__ inline int64_t cand_bin(const Cand &C, int v, int n[3], double rcmax2) {
   int r[3];
   int t = v;
   r[2] = t % C.nv[2]; t /= C.nv[2];
   r[1] = t % C.nv[1]; t /= C.nv[1];
   r[0] = t;
   int b[3];
+  double g2 = 0.0;
   for (int k = 0; k < 3; ++k) {
-    int V = C.lo[k] + r[k];
-    int nbk = C.I->nb[k];
+    const int V = C.lo[k] + r[k];
+    const int nbk = C.I->nb[k];
     b[k] = pmod(V, nbk);
     n[k] = floordiv(V, nbk);
+    if (C.I->pbc & (1 << k)) {
+      const double x0 = (double)V / (double)nbk, x1 = (double)(V + 1) / (double)nbk;
+      double g = x0 - C.f[k];
+      const double g1 = C.f[k] - x1;
+      g = g > g1 ? g : g1;
+      g -= 1e-9;
+      if (g > 0.0) g2 += g * g;
+    }
   }
+  if (C.I->lam_lo * g2 > rcmax2) return -1;
   return C.I->bin_base + ((int64_t)b[0] * C.I->nb[1] + b[1]) * C.I->nb[2] + b[2];
+}
+
+// Per-wavefront LDS scratch of the candidate enumeration.
+struct CandLds {
+  int pre[kWave];
+  int start[kWave];
+  int npk[kWave];
+  double sh[3][kWave];
+};
+
+// Calls f(t, n, shx, shy, shz) for every candidate atom t (index into the
+// bin-sorted arrays) of every bin image that is not culled.  Bin images are
+// taken 64 at a time (one per lane); their atoms are then flattened so that
+// consecutive lanes read consecutive atoms.  With several wavefronts on one
+// centre (wave w of nw), each wavefront takes every nw-th block of 64
+// flattened candidates of every chunk.
+template <typename F>
+__device__ inline void for_each_candidate(const Cand &C, const int64_t *bin_start, double rcmax2, int w, int nw,
+                                          CandLds &L, F &&f) {
+  const int lane = lane_id();
+  for (int v0 = 0; v0 < C.total; v0 += kWave) {
+    const int v = v0 + lane;
+    int cnt = 0, start = 0, npk = 0;
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    if (v < C.total) {
+      int n[3];
+      const int64_t bin = cand_bin(C, v, n, rcmax2);
+      if (bin >= 0) {
+        start = (int)bin_start[bin];
+        cnt = (int)(bin_start[bin + 1] - start);
+        npk = (n[0] & 0xff) | ((n[1] & 0xff) << 8) | ((n[2] & 0xff) << 16);
+        if (C.I->pbc) image_shift(C.cell, n[0], n[1], n[2], shx, shy, shz);
+      }
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    const int tot = __shfl(incl, kWave - 1, kWave);
+    L.pre[lane] = incl - cnt;
+    L.start[lane] = start;
+    L.npk[lane] = npk;
+    L.sh[0][lane] = shx;
+    L.sh[1][lane] = shy;
+    L.sh[2][lane] = shz;
+    wave_lds_sync();
+    for (int c0 = w * kWave; c0 < tot; c0 += nw * kWave) {
+      const int c = c0 + lane;
+      if (c < tot) {
+        int lo = 0, hi = kWave;  // largest lane with pre <= c
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (L.pre[mid] <= c) lo = mid; else hi = mid;
+        }
+        const int t = L.start[lo] + (c - L.pre[lo]);
+        const int pk = L.npk[lo];
+        const int n[3] = {(int)(int8_t)(pk & 0xff), (int)(int8_t)((pk >> 8) & 0xff), (int)(int8_t)((pk >> 16) & 0xff)};
+        f(t, n, L.sh[0][lo], L.sh[1][lo], L.sh[2][lo]);
+      }
+    }
+    wave_lds_sync();
+  }
 }
 
 __device__ inline int shell_of(const PlanDev &P, double q) {
@@ -201,13 +303,14 @@ __device__ inline int shell_of(const PlanDev &P, double q) {
   return sh;
 }
 
-// One wavefront per centre: count neighbours per (species, shell) bucket.
+// One wavefront per centre: count neighbours per (shell, species) bucket.
 __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                                const double *fw, const int64_t *bin_start,
                                                const double *sx, const double *sy, const double *sz,
                                                const int32_t *ssp, int32_t *cnt, int64_t *ptotal,
                                                uint32_t *status) {
   extern __shared__ int32_t lds_cnt[];
+  __shared__ CandLds lds_cand[4];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int nbk = P.E * P.S;
   int32_t *c = lds_cnt + w * nbk;
@@ -220,20 +323,14 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
     Cand C;
     cand_setup(C, info, bt, s, fw, i);
     const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
-    for (int v = 0; v < C.total; ++v) {
-      int n[3];
-      int64_t bin = cand_bin(C, v, n);
-      double shx = 0.0, shy = 0.0, shz = 0.0;
-      if (C.I->pbc) image_shift(C.cell, n[0], n[1], n[2], shx, shy, shz);
-      const int64_t b0 = bin_start[bin], b1 = bin_start[bin + 1];
-      for (int64_t t = b0 + lane; t < b1; t += kWave) {
-        double dx = (sx[t] - rix) + shx;
-        double dy = (sy[t] - riy) + shy;
-        double dz = (sz[t] - riz) + shz;
-        double q = (dx * dx + dy * dy) + dz * dz;
-        if (q <= P.rcmax2) atomicAdd(&c[shell_of(P, q) * P.E + ssp[t]], 1);
-      }
-    }
+    for_each_candidate(C, bin_start, P.rcmax2, 0, 1, lds_cand[w],
+                       [&](int t, const int *n, double shx, double shy, double shz) {
+                         const double dx = (sx[t] - rix) + shx;
+                         const double dy = (sy[t] - riy) + shy;
+                         const double dz = (sz[t] - riz) + shz;
+                         const double q = (dx * dx + dy * dy) + dz * dz;
+                         if (q <= P.rcmax2) atomicAdd(&c[shell_of(P, q) * P.E + ssp[t]], 1);
+                       });
   }
   wave_lds_sync();
   if (i < N) {
@@ -308,8 +405,10 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
                                               const double *fw, const int64_t *bin_start,
                                               const double *sx, const double *sy, const double *sz,
                                               const int32_t *sid, const int32_t *ssp, const int32_t *cnt,
-                                              int lds_keys, uint32_t *status) {
+                                              int lds_keys, uint64_t *pair_key, int32_t *pair_centre,
+                                              uint32_t *status) {
   extern __shared__ uint64_t lds_u64[];
+  __shared__ CandLds lds_cand[4];
   const int nbk = P.E * P.S;
   uint64_t *keys = lds_u64;
   int32_t *bstart = (int32_t *)(lds_u64 + lds_keys);  // [nbk+1]
@@ -339,25 +438,19 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   Cand C;
   cand_setup(C, info, bt, s, fw, i);
   const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
-  for (int v = w; v < C.total; v += nw) {
-    int n[3];
-    int64_t bin = cand_bin(C, v, n);
-    double shx = 0.0, shy = 0.0, shz = 0.0;
-    if (C.I->pbc) image_shift(C.cell, n[0], n[1], n[2], shx, shy, shz);
-    const int64_t b0 = bin_start[bin], b1 = bin_start[bin + 1];
-    for (int64_t t = b0 + lane; t < b1; t += kWave) {
-      double dx = (sx[t] - rix) + shx;
-      double dy = (sy[t] - riy) + shy;
-      double dz = (sz[t] - riz) + shz;
-      double q = (dx * dx + dy * dy) + dz * dz;
-      if (q <= P.rcmax2) {
-        int bk = shell_of(P, q) * P.E + ssp[t];
-        int pos = atomicAdd(&cursor[bk], 1);
-        if (pos < bstart[bk + 1]) keys[pos] = make_key(sid[t], n[0], n[1], n[2]);
-        else atomicOr(status, ST_INTERNAL);
-      }
-    }
-  }
+  for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
+                     [&](int t, const int *n, double shx, double shy, double shz) {
+                       const double dx = (sx[t] - rix) + shx;
+                       const double dy = (sy[t] - riy) + shy;
+                       const double dz = (sz[t] - riz) + shz;
+                       const double q = (dx * dx + dy * dy) + dz * dz;
+                       if (q <= P.rcmax2) {
+                         const int bk = shell_of(P, q) * P.E + ssp[t];
+                         const int pos = atomicAdd(&cursor[bk], 1);
+                         if (pos < bstart[bk + 1]) keys[pos] = make_key(sid[t], n[0], n[1], n[2]);
+                         else atomicOr(status, ST_INTERNAL);
+                       }
+                     });
   __syncthreads();
   for (int b = w; b < nbk; b += nw) {
     const int b0 = bstart[b], bn = bstart[b + 1] - b0;
@@ -372,52 +465,59 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       uint32_t n3 = (uint32_t)((k & 0xff) - 128) & 0xffu;
       nb.j[base + b0 + t] = jj;
       nb.shift[base + b0 + t] = (int32_t)(n1 | (n2 << 8) | (n3 << 16) | ((uint32_t)e << 24));
+      if (pair_key) {
+        pair_key[base + b0 + t] = k;
+        pair_centre[base + b0 + t] = (int32_t)i;
+      }
     }
   }
 }
 
-// Reverse index: for pair (i, j, n) find (j, i, -n) in j's list by binary
-// search inside j's bucket (shell of q, species of i).
-__global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev nb, uint32_t *status) {
+// Reverse index: pair (i, j, n) and its mirror (j, i, -n).  One thread per
+// pair; only the owner of each mirror couple -- i < j, or i == j with n >= 0
+// lexicographically -- searches its mirror (binary search over the packed
+// keys of j's bucket (shell of q, species of i)) and writes both entries.
+__global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev nb, const uint64_t *pair_key,
+                                                 const int32_t *pair_centre, int64_t n_pairs, uint32_t *status) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = bt.n_atoms;
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (i >= N) return;
-  const int lane = lane_id();
+  const int64_t total = nb.offsets[N];
+  if (p >= n_pairs || p >= total || total > nb.capacity) return;
   const int nbk = P.E * P.S;
+  const uint64_t kp = pair_key[p];
+  const int64_t i = pair_centre[p];
+  const int32_t j = (int32_t)(kp >> 24);
+  const int n1 = (int)((kp >> 16) & 0xff) - 128, n2 = (int)((kp >> 8) & 0xff) - 128, n3 = (int)(kp & 0xff) - 128;
+  const int lex = n1 != 0 ? n1 : (n2 != 0 ? n2 : n3);
+  if (!((int64_t)j > i || ((int64_t)j == i && lex >= 0))) return;
   const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
-  const double *cell = bt.cell + 9 * (int64_t)s;
   const int pbc = bt.pbc[s] & 7;
-  const int64_t base = nb.offsets[i], end = nb.offsets[i + 1];
-  if (end > nb.capacity) return;
+  double shx = 0.0, shy = 0.0, shz = 0.0;
+  if (pbc) image_shift(bt.cell + 9 * (int64_t)s, n1, n2, n3, shx, shy, shz);
+  const double dx = (nb.rw[j] - nb.rw[i]) + shx;
+  const double dy = (nb.rw[N + j] - nb.rw[N + i]) + shy;
+  const double dz = (nb.rw[2 * N + j] - nb.rw[2 * N + i]) + shz;
+  const double q = (dx * dx + dy * dy) + dz * dz;
   int ei = bt.species[i];
   ei = ei < 0 ? 0 : (ei >= P.E ? P.E - 1 : ei);
-  const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
-  for (int64_t p = base + lane; p < end; p += kWave) {
-    const int32_t j = nb.j[p];
-    const int32_t w = nb.shift[p];
-    const int n1 = shift_n(w, 0), n2 = shift_n(w, 1), n3 = shift_n(w, 2);
-    double shx = 0.0, shy = 0.0, shz = 0.0;
-    if (pbc) image_shift(cell, n1, n2, n3, shx, shy, shz);
-    double dx = (nb.rw[j] - rix) + shx;
-    double dy = (nb.rw[N + j] - riy) + shy;
-    double dz = (nb.rw[2 * N + j] - riz) + shz;
-    double q = (dx * dx + dy * dy) + dz * dz;
-    const int b = shell_of(P, q) * P.E + ei;
-    const int32_t *bs = nb.bucket_start + (int64_t)j * (nbk + 1);
-    int lo = bs[b], hi = bs[b + 1];
-    const uint64_t key = make_key(i, -n1, -n2, -n3);
-    const int64_t jb = nb.offsets[j];
-    int found = -1;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      const int32_t wm = nb.shift[jb + mid];
-      uint64_t km = make_key(nb.j[jb + mid], shift_n(wm, 0), shift_n(wm, 1), shift_n(wm, 2));
-      if (km == key) { found = mid; break; }
-      if (km < key) lo = mid + 1; else hi = mid;
-    }
-    if (found < 0) atomicOr(status, ST_INTERNAL);
-    nb.reverse[p] = found;
+  const int b = shell_of(P, q) * P.E + ei;
+  const int32_t *bs = nb.bucket_start + (int64_t)j * (nbk + 1);
+  int lo = bs[b], hi = bs[b + 1];
+  const uint64_t key = make_key(i, -n1, -n2, -n3);
+  const int64_t jb = nb.offsets[j];
+  int found = -1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const uint64_t km = pair_key[jb + mid];
+    if (km == key) { found = mid; break; }
+    if (km < key) lo = mid + 1; else hi = mid;
   }
+  if (found < 0) {
+    atomicOr(status, ST_INTERNAL);
+    return;
+  }
+  nb.reverse[p] = found;
+  nb.reverse[jb + found] = (int32_t)(p - nb.offsets[i]);
 }
 
 }  // namespace
@@ -454,12 +554,26 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
   int nbk = p->dev.E * p->dev.S;
   size_t smem = sizeof(uint64_t) * lds_keys + sizeof(int32_t) * (2 * nbk + 2);
   GMP_LAUNCH("nbr_fill_sort", k_fill, dim3((unsigned)bt.n_atoms), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
-             L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.cnt, lds_keys, L.status);
+             L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.cnt, lds_keys,
+             nb.reverse ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.status);
 }
 
-void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, hipStream_t s) {
-  int64_t blocks = (bt.n_atoms + 3) / 4;
-  GMP_LAUNCH("nbr_reverse", k_reverse, dim3((unsigned)blocks), dim3(256), 0, s, p->dev, bt, nb, L.status);
+__global__ void k_fill_minus_one(int32_t *a, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) a[t] = -1;
+}
+
+void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,
+                    hipStream_t s) {
+  {
+    int64_t b = (n_pairs + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    GMP_LAUNCH("nbr_reverse_init", k_fill_minus_one, dim3((unsigned)b), dim3(256), 0, s, nb.reverse, n_pairs);
+  }
+  const int64_t blocks = (n_pairs + 255) / 256;
+  if (blocks > 0)
+    GMP_LAUNCH("nbr_reverse", k_reverse, dim3((unsigned)blocks), dim3(256), 0, s, p->dev, bt, nb, L.pair_key,
+               L.pair_centre, n_pairs, L.status);
 }
 
 }  // namespace gmp

@@ -38,6 +38,15 @@ def check_neighbors(nb, batch_np, probes, centres=None):
     se = nb.sigma_end.cpu().numpy().reshape(-1, S)
     wrap = nb.wrap.cpu().numpy().reshape(-1, 3)
     rw = nb.rw.cpu().numpy().reshape(3, -1).T
+    if nb.reverse is not None:
+        # every pair's reverse entry is its mirror (j, i, -n)
+        rev = nb.reverse[:P].cpu().numpy().astype(np.int64)
+        assert np.all(rev >= 0)
+        centre = np.repeat(np.arange(len(offs) - 1), np.diff(offs))
+        tgt = offs[J] + rev
+        assert np.all(rev < np.diff(offs)[J])
+        assert np.array_equal(J[tgt], centre)
+        assert np.array_equal(n[tgt], -n)
     checked = 0
     for s in range(batch_np.n_structs):
         a0, a1 = int(batch_np.atom_offsets[s]), int(batch_np.atom_offsets[s + 1])
