@@ -113,6 +113,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
   constexpr int NB = NM + 3 * NM1;
   extern __shared__ double lds_dyn[];
   __shared__ int lds_k[kMaxElements];
+  __shared__ T lds_bc[4][kMaxSigmas * NB];  // per wavefront: the current centre's M, Dx, Dy, Dz
   const int S = P.S, E = P.E;
   const T *__restrict__ tabg = (const T *)tab_global;
   T *tabl = (T *)lds_dyn;
@@ -127,13 +128,16 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
   T *vbuf = (T *)vbuf_;
   const int mask = P.order_mask;
   for (;;) {
-    unsigned long long it = 0;
-    if (lane == 0) it = atomicAdd(counter, 1ull);
-    const int64_t item = (int64_t)__shfl(it, 0, kWave);
+    const int64_t item = next_item(counter);
     if (item >= n_items) break;
     const int64_t i = item / C;
     const int c = (int)(item - i * C);
-    const T *bcoef = (const T *)bcoef_ + (size_t)i * S * NB;
+    T *bcoef = lds_bc[threadIdx.x / kWave];
+    {
+      const T *src = (const T *)bcoef_ + (size_t)i * S * NB;
+      for (int t = lane; t < S * NB; t += kWave) bcoef[t] = src[t];
+      wave_lds_sync();
+    }
     const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
@@ -223,6 +227,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
         dst[3] = (T)0;
       }
     }
+    wave_lds_sync();  // every lane is done with this centre's coefficients
   }
 }
 

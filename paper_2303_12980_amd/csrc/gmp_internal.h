@@ -128,6 +128,20 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The value of lane 0 as a wavefront-uniform (scalar) value.
+__device__ inline int64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Next work item of a persistent kernel (one atomic per wavefront).
+__device__ inline int64_t next_item(unsigned long long *counter) {
+  unsigned long long it = 0;
+  if ((threadIdx.x & 63) == 0) it = atomicAdd(counter, 1ull);
+  return uniform64(__shfl(it, 0, 64));
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);

@@ -164,9 +164,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
   const int64_t N = bt.n_atoms;
   const int64_t n_items = chunk_off[N];
   for (;;) {
-    unsigned long long it = 0;
-    if (lane == 0) it = atomicAdd(counter, 1ull);
-    const int64_t qc = (int64_t)__shfl(it, 0, kWave);
+    const int64_t qc = next_item(counter);
     if (qc >= n_items) break;
     const int64_t i = centre_of_chunk(chunk_off, N, qc);
     const int c = (int)(qc - chunk_off[i]);
