@@ -116,11 +116,12 @@ def density_tables(rng, n_elements: int, n_prims, B_range=(0.01, 10.0),
 
 
 def _image_shifts(cell, reach):
-    """Integer lattice shifts covering every image within ``reach`` of the
-    home cell (cell rows are lattice vectors)."""
+    """Integer lattice shifts n with |n_k| <= ceil(1/2 + reach/h_k): every
+    image within ``reach`` of a point whose fractional offset was rounded
+    into [-1/2, 1/2] (cell rows are lattice vectors, h_k the heights)."""
     inv = np.linalg.inv(cell)
     heights = 1.0 / np.linalg.norm(inv, axis=0)
-    nmax = [int(math.ceil(reach / h)) + 1 for h in heights]
+    nmax = [int(math.ceil(0.5 + reach / h)) for h in heights]
     rng_ = [np.arange(-m, m + 1) for m in nmax]
     g = np.stack(np.meshgrid(*rng_, indexing="ij"), axis=-1).reshape(-1, 3)
     return g.astype(np.float64)
@@ -143,22 +144,37 @@ def rsa_periodic(rng, cell, n_atoms: int, dmin: float, max_tries=2_000_000):
     k = 0
     tries = 0
     d2 = dmin * dmin
+
+    def min_d2(r, others):
+        fr = (others - r) @ inv
+        fr -= np.round(fr)
+        dd = (fr @ cell)[:, None, :] + shifts[None, :, :]
+        return np.min(np.einsum("kid,kid->ki", dd, dd))
+
     while k < n_atoms:
-        tries += 1
+        # Candidates are drawn in blocks and accepted in draw order, each one
+        # tested against every point accepted before it: the same sequence as
+        # one-by-one random sequential addition with these draws.
+        block = rng.random((64, 3)) @ cell
+        tries += len(block)
         if tries > max_tries:
             raise RuntimeError("random sequential addition did not converge")
-        f = rng.random(3)
-        r = f @ cell
         if k:
-            diff = pts[:k] - r  # [k,3]
-            fr = diff @ inv
+            fr = (block[:, None, :] - pts[None, :k, :]) @ inv
             fr -= np.round(fr)
-            base = fr @ cell
-            dd = base[:, None, :] + shifts[None, :, :]
-            if np.min(np.einsum("ijk,ijk->ij", dd, dd)) < d2:
+            dd = (fr @ cell)[:, :, None, :] + shifts[None, None, :, :]
+            ok = np.min(np.einsum("bkid,bkid->bki", dd, dd), axis=(1, 2)) >= d2
+        else:
+            ok = np.ones(len(block), bool)
+        k_block = k
+        for bi in np.flatnonzero(ok):
+            r = block[bi]
+            if k > k_block and min_d2(r, pts[k_block:k]) < d2:
                 continue
-        pts[k] = r
-        k += 1
+            pts[k] = r
+            k += 1
+            if k == n_atoms:
+                break
     return pts
 
 
@@ -203,25 +219,35 @@ def _rsa_grid(rng, cell, inv, ng, n_atoms, dmin, max_tries):
 
 
 def rsa_cluster(rng, n_atoms: int, radius: float, dmin: float, max_tries=2_000_000):
-    """Random sequential addition inside a sphere of ``radius`` (no images)."""
+    """Random sequential addition inside a sphere of ``radius`` (no images).
+    Candidates are drawn in blocks and accepted in draw order."""
     rng = _rng(rng)
     pts = np.empty((n_atoms, 3))
     k = 0
     tries = 0
     d2 = dmin * dmin
     while k < n_atoms:
-        tries += 1
+        block = rng.uniform(-radius, radius, (64, 3))
+        tries += len(block)
         if tries > max_tries:
             raise RuntimeError("random sequential addition did not converge")
-        r = rng.uniform(-radius, radius, 3)
-        if r @ r > radius * radius:
-            continue
+        inside = np.einsum("bd,bd->b", block, block) <= radius * radius
         if k:
-            diff = pts[:k] - r
-            if np.min(np.einsum("ij,ij->i", diff, diff)) < d2:
-                continue
-        pts[k] = r
-        k += 1
+            diff = block[:, None, :] - pts[None, :k, :]
+            ok = inside & (np.min(np.einsum("bkd,bkd->bk", diff, diff), axis=1) >= d2)
+        else:
+            ok = inside
+        k_block = k
+        for bi in np.flatnonzero(ok):
+            r = block[bi]
+            if k > k_block:
+                dv = pts[k_block:k] - r
+                if np.min(np.einsum("kd,kd->k", dv, dv)) < d2:
+                    continue
+            pts[k] = r
+            k += 1
+            if k == n_atoms:
+                break
     return pts
 
 

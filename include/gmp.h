@@ -171,8 +171,13 @@ gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n
 gmp_status gmp_build_neighbors(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs,
                                int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream);
 
-/* Features [n_atoms * n_features] (float for GMP_FP32_COMPENSATED, double
- * for GMP_FP64), order-major: features[i*n_features + o*n_sigmas + s].
+/* Features [n_atoms * n_features] (float for the FP32 modes, double for
+ * GMP_FP64), order-major: features[i*n_features + o*n_sigmas + s].
+ * The pair set is the one in nbrs; displacements are evaluated at the
+ * batch's current coordinates and lattice with the wrap indices of the
+ * build (d = R_j - R_i + (n - m_j + m_i) . cell), so moving atoms or the
+ * cell after the build gives the features of the same pairs at the new
+ * geometry (bitwise the build's geometry when nothing moved).
  * components (optional, FP64) [n_atoms * n_components] laid out
  * (order, sigma, component) with components of order l in the order
  * (a descending, then b descending); required later by the backward. */

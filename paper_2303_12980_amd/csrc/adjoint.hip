@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
     const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
-    const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+    const double4 ri4 = rw4[i];
+    const double rix = ri4.x, riy = ri4.y, riz = ri4.z;
     const int64_t base = nb.offsets[i];
     const int cnt = (int)(nb.offsets[i + 1] - base);
     const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
@@ -322,10 +323,10 @@ template <bool F64, bool LDS> PairsFn pick_pairs(int lmax, int kb) {
 }
 
 // AoS copy of the wrapped positions: one 32-byte gather per neighbour.
-__global__ void k_pack_rw_bwd(NbrDev nb, int64_t N, double4 *rw4) {
+__global__ void k_pack_rw_bwd(BatchDev bt, NbrDev nb, int64_t N, double4 *rw4) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  rw4[i] = make_double4(nb.rw[i], nb.rw[N + i], nb.rw[2 * N + i], 0.0);
+  rw4[i] = wrapped_position(bt, nb, i);
 }
 
 }  // namespace
@@ -352,7 +353,7 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
                grad_features, bcoef);
   const int64_t n_items = N * (int64_t)C;
   fill_zero(counter, sizeof(unsigned long long), s);
-  GMP_LAUNCH("pack_positions", k_pack_rw_bwd, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, nb, N, rw4);
+  GMP_LAUNCH("pack_positions", k_pack_rw_bwd, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, rw4);
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;
   const size_t tsm = use_lds ? tab_bytes : 0;

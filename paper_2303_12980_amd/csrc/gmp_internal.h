@@ -180,6 +180,24 @@ __device__ inline void image_shift(const Cell9 &c, int n1, int n2, int n3, doubl
   image_shift(c.a, n1, n2, n3, sx, sy, sz);
 }
 
+// Wrapped position Rw_i = R_i - ((m1 a1 + m2 a2) + m3 a3) from the current
+// positions and lattice and the wrap indices of the neighbour build; the
+// same operation order as the build, so unchanged inputs give the same bits.
+__device__ inline double4 wrapped_position(const BatchDev &bt, const NbrDev &nb, int64_t i) {
+  const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  double r[3] = {bt.x[i], bt.y[i], bt.z[i]};
+  if (bt.pbc[s] & 7) {
+    const double *a = bt.cell + 9 * (int64_t)s;
+    const double m0 = (double)nb.wrap[3 * i], m1 = (double)nb.wrap[3 * i + 1], m2 = (double)nb.wrap[3 * i + 2];
+    for (int c = 0; c < 3; ++c) {
+      double t = m0 * a[c] + m1 * a[3 + c];
+      t = t + m2 * a[6 + c];
+      r[c] = r[c] - t;
+    }
+  }
+  return make_double4(r[0], r[1], r[2], 0.0);
+}
+
 __device__ inline int shift_n(int32_t w, int k) { return (int)(int8_t)((uint32_t)w >> (8 * k)); }
 __device__ inline int shift_species(int32_t w) { return (int)((uint32_t)w >> 24); }
 

@@ -50,10 +50,10 @@ __global__ void k_chunk_count(NbrDev nb, int64_t N, int kc, int64_t *nch) {
 }
 
 // AoS copy of the wrapped positions: one 32-byte gather per neighbour.
-__global__ void k_pack_rw(NbrDev nb, int64_t N, double4 *rw4) {
+__global__ void k_pack_rw(BatchDev bt, NbrDev nb, int64_t N, double4 *rw4) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  rw4[i] = make_double4(nb.rw[i], nb.rw[N + i], nb.rw[2 * N + i], 0.0);
+  rw4[i] = wrapped_position(bt, nb, i);
 }
 
 __device__ inline int64_t centre_of_chunk(const int64_t *chunk_off, int64_t N, int64_t q) {
@@ -171,7 +171,8 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
     const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
-    const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+    const double4 ri4 = rw4[i];
+    const double rix = ri4.x, riy = ri4.y, riz = ri4.z;
     const int64_t base = nb.offsets[i];
     const int cnt = (int)(nb.offsets[i + 1] - base);
     const int clo = kc > 0 ? c * kc : 0;
@@ -408,7 +409,7 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
   const int64_t N = bt.n_atoms;
   const int kc = chunk_size(p);
   GMP_LAUNCH("overlap_chunks", k_chunk_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, nb, N, kc, nch);
-  GMP_LAUNCH("pack_positions", k_pack_rw, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, nb, N, rw4);
+  GMP_LAUNCH("pack_positions", k_pack_rw, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, rw4);
   scan_i64(nch, chunk_off, N, scan_aux, s);
   fill_zero(counter, sizeof(unsigned long long), s);
   const bool f64 = p->prec == GMP_FP64;

@@ -24,51 +24,67 @@ def run_path(g, batch_np, probes, precision, ws, reverse=True, tuning=None):
     return plan, db, nb, F, mu
 
 
+def check_reverse(nb):
+    """Every pair's reverse entry is its mirror (j, i, -n) -- checked on the GPU."""
+    import torch
+    P = nb.n_pairs
+    offs = nb.offsets
+    cnt = offs[1:] - offs[:-1]
+    centre = torch.repeat_interleave(torch.arange(len(cnt), device=offs.device, dtype=torch.int64), cnt)
+    J = nb.j[:P].long()
+    rev = nb.reverse[:P].long()
+    assert bool((rev >= 0).all()) and bool((rev < cnt[J]).all())
+    tgt = offs[J] + rev
+    assert bool((J[tgt] == centre).all())
+    w = nb.shift[:P]
+    nk = [((w >> (8 * k)) & 0xff).to(torch.int8) for k in range(3)]
+    for k in range(3):
+        assert bool((nk[k][tgt].int() == -nk[k].int()).all())
+
+
 def check_neighbors(nb, batch_np, probes, centres=None):
     """Bit-exact comparison of the canonical lists (j, shift, species byte),
-    the species-segment starts and the sigma-prefix ends with the oracle."""
+    the bucket starts and the sigma-prefix ends with the oracle, for all
+    centres or the sampled ones ({structure: [local centres]}), plus the
+    reverse index of every pair."""
     rc2 = oracle.cutoffs(probes)
     offs = nb.offsets.cpu().numpy()
     P = int(offs[-1])
     assert P == nb.n_pairs
-    J = nb.j[:P].cpu().numpy()
-    n, e = nb.shifts_numpy()
     E, S = probes.n_elements, len(probes.sigmas)
-    bs = nb.bucket_start.cpu().numpy().reshape(-1, S * E + 1)
-    se = nb.sigma_end.cpu().numpy().reshape(-1, S)
-    wrap = nb.wrap.cpu().numpy().reshape(-1, 3)
-    rw = nb.rw.cpu().numpy().reshape(3, -1).T
     if nb.reverse is not None:
-        # every pair's reverse entry is its mirror (j, i, -n)
-        rev = nb.reverse[:P].cpu().numpy().astype(np.int64)
-        assert np.all(rev >= 0)
-        centre = np.repeat(np.arange(len(offs) - 1), np.diff(offs))
-        tgt = offs[J] + rev
-        assert np.all(rev < np.diff(offs)[J])
-        assert np.array_equal(J[tgt], centre)
-        assert np.array_equal(n[tgt], -n)
+        check_reverse(nb)
+    wrap_all = nb.wrap.view(-1, 3)
+    rw_all = nb.rw.view(3, -1)
     checked = 0
     for s in range(batch_np.n_structs):
+        loc = None if centres is None else centres.get(s, [])
+        if loc is not None and len(loc) == 0:
+            continue
         a0, a1 = int(batch_np.atom_offsets[s]), int(batch_np.atom_offsets[s + 1])
         struct = batch_np.structure(s)
         orw, om = oracle.wrap(struct[0], struct[2], struct[3])
-        assert np.array_equal(wrap[a0:a1], om)
-        assert rw[a0:a1].tobytes() == orw.tobytes()
-        loc = range(a1 - a0) if centres is None else [c for c in centres.get(s, [])]
+        assert np.array_equal(wrap_all[a0:a1].cpu().numpy(), om)
+        assert rw_all[:, a0:a1].t().contiguous().cpu().numpy().tobytes() == orw.tobytes()
+        if loc is None:
+            loc = range(a1 - a0)
         for li in loc:
             gi = a0 + li
             ref = oracle.neighbors(struct, rc2, li)
             lo, hi = int(offs[gi]), int(offs[gi + 1])
             assert hi - lo == len(ref["j"]), (s, li, hi - lo, len(ref["j"]))
-            assert np.array_equal(J[lo:hi], ref["j"] + a0)
-            assert np.array_equal(n[lo:hi], ref["n"])
-            assert np.array_equal(e[lo:hi], ref["e"])
-            # bucket starts (shell-major, species-minor) and sigma prefixes
+            J = nb.j[lo:hi].cpu().numpy()
+            w = nb.shift[lo:hi].cpu().numpy().view(np.uint8).reshape(-1, 4)
+            n = w[:, :3].view(np.int8).astype(np.int32)
+            e = w[:, 3].astype(np.int32)
+            assert np.array_equal(J, ref["j"] + a0)
+            assert np.array_equal(n, ref["n"])
+            assert np.array_equal(e, ref["e"])
+            bs = nb.bucket_start[gi * (S * E + 1):(gi + 1) * (S * E + 1)].cpu().numpy()
+            se = nb.sigma_end[gi * S:(gi + 1) * S].cpu().numpy()
             bucket = ref["shell"] * E + ref["e"]
-            for b in range(S * E + 1):
-                assert bs[gi, b] == int(np.sum(bucket < b))
-            for ss in range(S):
-                assert se[gi, ss] == int(np.sum(ref["q"] <= rc2[ss]))
+            assert np.array_equal(bs, np.searchsorted(np.sort(bucket), np.arange(S * E + 1), side="left"))
+            assert np.array_equal(se, np.array([int(np.sum(ref["q"] <= rc2[t])) for t in range(S)]))
             checked += 1
     return checked
 
