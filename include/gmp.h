@@ -137,20 +137,21 @@ gmp_status gmp_probe_cutoffs(const gmp_probe_desc *desc, double *rc2);
 gmp_status gmp_plan_info(const gmp_plan *plan, int32_t *n_features, int32_t *n_components,
                          double *rc2);
 
-/* Tuning knobs of the overlap and adjoint kernels (autotuned by the caller
- * or left at defaults).  sigma_group: sigmas per wavefront (1, 2, 4);
- * chunk_pairs: a centre's list is processed in pieces of this many pairs
- * (0 = never split); the piece boundaries depend only on that centre's own
- * list, so features of a structure are bitwise the same whether it is
- * featurized alone or inside a batch, for a given tuning; persistent: 1 =
- * persistent grid pulling work items; bin_divisor: cell-list bin edge is
- * about rc_max / bin_divisor.  The workspace size depends on the tuning.
- * Changing the tuning is not thread-safe with concurrent calls on the plan. */
+/* Tuning knobs (autotuned by the caller or left at defaults).
+ *  chunk_pairs:   a centre's list is processed in work items of this many
+ *                 pairs (0 = never split).  Item boundaries depend only on
+ *                 that centre's own list, so a structure's features are
+ *                 bitwise the same alone or inside a batch, for one tuning.
+ *  bin_divisor:   cell-list bin edge is about rc_max / bin_divisor (1..4).
+ *  blocks_per_cu: workgroups per compute unit of the persistent kernels
+ *                 (0 = as many as fit).
+ * The workspace size depends on the tuning.  Changing the tuning is not
+ * thread-safe with concurrent calls on the plan. */
 typedef struct {
-  int32_t sigma_group;
   int32_t chunk_pairs;
-  int32_t persistent;
-  int32_t bin_divisor;           /* 1..4 */
+  int32_t bin_divisor;
+  int32_t blocks_per_cu;
+  int32_t reserved;              /* must be 0 */
 } gmp_tuning;
 gmp_status gmp_plan_get_tuning(const gmp_plan *plan, gmp_tuning *out);
 gmp_status gmp_plan_set_tuning(gmp_plan *plan, const gmp_tuning *t);

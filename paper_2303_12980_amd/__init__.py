@@ -6,5 +6,6 @@ it until a plan is created, and a missing library raises instead of falling
 back to any CPU implementation.
 """
 from .gmp import (GMPPlan, DeviceBatch, Neighbors, Workspace, build_neighbors, features,  # noqa: F401
-                  features_backward, GMPFunction, feature_labels, profile, GMPError)
+                  features_backward, GMPFunction, feature_labels, profile, GMPError, rebuild_neighbors_nosync,
+                  check_status, CapturedStep)
 from ._lib import LIB_PATH, EXPORTS, load  # noqa: F401

@@ -43,7 +43,7 @@ class NbrDesc(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("sigma_group", c_i32), ("chunk_pairs", c_i32), ("persistent", c_i32), ("bin_divisor", c_i32)]
+    _fields_ = [("chunk_pairs", c_i32), ("bin_divisor", c_i32), ("blocks_per_cu", c_i32), ("reserved", c_i32)]
 
 
 class GMPError(RuntimeError):

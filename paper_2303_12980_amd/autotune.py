@@ -1,0 +1,105 @@
+"""Autotuner of the library's tuning knobs (chunk size of the per-centre
+work items, cell-list bin size, persistent grid size).
+
+Candidates are timed with the HIP events the library records around its
+own launches on the current stream (neighbour build + forward, optionally
+the adjoint), the fastest is set on the plan, and the choice is cached in
+a JSON file keyed by the device, the precision, the probe shape (l_max,
+sigmas, species, primitive stride) and log2 buckets of the atom count and
+of the mean list length.  GMP_AUTOTUNE=0 disables the search (cached or
+default values are used); GMP_TUNE_CACHE sets the cache path.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Dict, Iterable, Optional
+
+import torch
+
+from . import gmp as _g
+
+DEFAULT_CANDIDATES = [
+    dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0)
+    for c in (0, 512, 1024, 2048, 4096) for b in (2, 3, 4)
+]
+
+
+def _cache_path():
+    return os.environ.get("GMP_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "gmp_tune.json"))
+
+
+def _bucket(x: float) -> int:
+    return int(math.floor(math.log2(max(1.0, x))))
+
+
+def tuning_key(plan, batch, nb) -> str:
+    dev = torch.cuda.get_device_name(batch.species.device)
+    avg = nb.n_pairs / max(1, batch.n_atoms)
+    return (f"{dev}|{plan.precision}|L{int(max(plan.orders))}|S{len(plan.sigmas)}|E{plan.n_elements}"
+            f"|N{_bucket(batch.n_atoms)}|avg{_bucket(avg)}")
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time_config(plan, batch, ws, G, reps: int, backward: bool) -> float:
+    nb = _g.build_neighbors(plan, batch, ws)
+    for _ in range(2):  # warm: grows the workspace, fills occupancy caches
+        nb = _g.build_neighbors(plan, batch, ws, out=nb)
+        F, mu = _g.features(plan, batch, nb, ws)
+        if backward:
+            _g.features_backward(plan, batch, nb, ws, mu, F, G)
+    torch.cuda.synchronize()
+    with _g.profile() as pr:
+        for _ in range(reps):
+            nb = _g.build_neighbors(plan, batch, ws, out=nb)
+            F, mu = _g.features(plan, batch, nb, ws)
+            if backward:
+                _g.features_backward(plan, batch, nb, ws, mu, F, G)
+        torch.cuda.synchronize()
+    return sum(v[1] for v in pr.result.values()) / reps
+
+
+def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backward: bool = True,
+             reps: int = 3, cache_path: Optional[str] = None, force: bool = False) -> Dict:
+    """Pick and set the fastest tuning for this plan and batch shape.
+    Returns {"tuning": ..., "ms": ..., "key": ..., "cached": bool, "tried": [...]}."""
+    path = cache_path or _cache_path()
+    nb = _g.build_neighbors(plan, batch, ws)
+    key = tuning_key(plan, batch, nb)
+    cache = _load(path)
+    if not force and key in cache:
+        plan.set_tuning(**cache[key]["tuning"])
+        return dict(cache[key], key=key, cached=True)
+    if os.environ.get("GMP_AUTOTUNE", "1") == "0":
+        return dict(tuning=plan.get_tuning(), ms=None, key=key, cached=False, tried=[])
+    G = torch.ones((batch.n_atoms, plan.n_features), dtype=plan.dtype, device=batch.species.device)
+    tried = []
+    best = None
+    t0 = time.time()
+    for cand in (candidates or DEFAULT_CANDIDATES):
+        plan.set_tuning(**cand)
+        ms = _time_config(plan, batch, ws, G, reps, backward)
+        tried.append(dict(tuning=dict(cand), ms=ms))
+        if best is None or ms < best[1]:
+            best = (dict(cand), ms)
+    plan.set_tuning(**best[0])
+    entry = dict(tuning=best[0], ms=best[1], search_s=time.time() - t0)
+    cache[key] = entry
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return dict(entry, key=key, cached=False, tried=tried)

@@ -335,7 +335,7 @@ size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms) {
   return (size_t)n_atoms * p->dev.S * coef_block(p->dev.lmax);
 }
 
-int persistent_blocks(const void *fn, size_t smem);
+int persistent_blocks(const void *fn, size_t smem, int blocks_per_cu);
 
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
@@ -362,7 +362,7 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
                               : pick_pairs<true, false>(p->dev.lmax, p->dev.kb))
                    : (use_lds ? pick_pairs<false, true>(p->dev.lmax, p->dev.kb)
                               : pick_pairs<false, false>(p->dev.lmax, p->dev.kb));
-  int64_t pb = persistent_blocks((const void *)fn, tsm);
+  int64_t pb = persistent_blocks((const void *)fn, tsm, p->tuning.blocks_per_cu);
   if (pb > (n_items + 3) / 4) pb = (n_items + 3) / 4;
   if (pb < 1) pb = 1;
   GMP_LAUNCH("adj_pairs", fn, dim3((unsigned)pb), dim3(256), tsm, s, p->dev, bt, nb, (const double4 *)rw4, bcoef, vbuf,

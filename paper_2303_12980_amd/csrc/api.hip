@@ -21,7 +21,6 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
                  hipStream_t s);
 void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,
                     hipStream_t s);
-int normalized_group(const gmp_plan *p);
 int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs);
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
                     int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
@@ -378,10 +377,10 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   P.coef64 = (const double *)(base + o64);
   P.T = (const double *)(base + oT);
   P.kcount = (const int *)(base + ok);
-  p->tuning.sigma_group = P.lmax >= 3 ? 1 : 2;
   p->tuning.chunk_pairs = 2048;
-  p->tuning.persistent = 0;
   p->tuning.bin_divisor = 2;
+  p->tuning.blocks_per_cu = 0;
+  p->tuning.reserved = 0;
   *out = p;
   return GMP_OK;
 }
@@ -408,11 +407,10 @@ gmp_status gmp_plan_get_tuning(const gmp_plan *p, gmp_tuning *t) {
 
 gmp_status gmp_plan_set_tuning(gmp_plan *p, const gmp_tuning *t) {
   if (!p || !t) return set_error(GMP_E_INVALID, "null argument");
-  if (t->sigma_group != 1 && t->sigma_group != 2 && t->sigma_group != 4)
-    return set_error(GMP_E_INVALID, "sigma_group must be 1, 2 or 4");
   if (t->chunk_pairs < 0) return set_error(GMP_E_INVALID, "chunk_pairs must be >= 0");
   if (t->bin_divisor < 1 || t->bin_divisor > 4) return set_error(GMP_E_INVALID, "bin_divisor must be 1..4");
-  if (t->persistent != 0 && t->persistent != 1) return set_error(GMP_E_INVALID, "persistent must be 0 or 1");
+  if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return set_error(GMP_E_INVALID, "blocks_per_cu must be 0..64");
+  if (t->reserved != 0) return set_error(GMP_E_INVALID, "reserved tuning field must be 0");
   p->tuning = *t;
   return GMP_OK;
 }

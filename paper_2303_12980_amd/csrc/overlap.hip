@@ -373,12 +373,6 @@ template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb) {
 
 }  // namespace
 
-int normalized_group(const gmp_plan *p) {
-  int G = p->tuning.sigma_group;
-  if (G >= 4 && p->dev.lmax <= 2) G = 4; else if (G >= 2) G = 2; else G = 1;
-  return G;
-}
-
 int chunk_size(const gmp_plan *p) { return p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 0; }
 
 // upper bound on the number of chunks of a batch with at most `pairs` pairs
@@ -387,20 +381,33 @@ int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs) {
   return n_atoms + (kc > 0 ? pairs / kc + 1 : 0);
 }
 
-int persistent_blocks(const void *fn, size_t smem) {
+static int cus_cached() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, c = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+    cus = c > 0 ? c : 256;
+  }
+  return cus;
+}
+
+int persistent_blocks(const void *fn, size_t smem, int blocks_per_cu) {
   static std::mutex mu;
   static std::map<std::pair<const void *, size_t>, int> cache;
   std::lock_guard<std::mutex> lk(mu);
   auto key = std::make_pair(fn, smem);
   auto itc = cache.find(key);
-  if (itc != cache.end()) return itc->second;
+  if (itc != cache.end()) {
+    const int per_c = itc->second / (cus_cached() > 0 ? cus_cached() : 1);
+    return blocks_per_cu > 0 && blocks_per_cu < per_c ? cus_cached() * blocks_per_cu : itc->second;
+  }
   int dev = 0, cus = 256, per = 2;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, smem) != hipSuccess || per < 1) per = 1;
-  const int blocks = cus * per;
-  cache[key] = blocks;
-  return blocks;
+  cache[key] = cus * per;
+  return blocks_per_cu > 0 && blocks_per_cu < per ? cus * blocks_per_cu : cus * per;
 }
 
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
@@ -419,7 +426,7 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
   const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
   OverlapFn fn = use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb) : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb);
   const int64_t items_bound = max_chunks(p, N, pairs_bound);
-  int64_t blocks = persistent_blocks((const void *)fn, smem);
+  int64_t blocks = persistent_blocks((const void *)fn, smem, p->tuning.blocks_per_cu);
   const int64_t need = (items_bound + 3) / 4;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;

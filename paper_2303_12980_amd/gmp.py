@@ -19,8 +19,9 @@ import torch
 from . import _lib
 from ._lib import GMPError, check
 
-__all__ = ["GMPPlan", "DeviceBatch", "Neighbors", "Workspace", "build_neighbors", "features",
-           "features_backward", "GMPFunction", "feature_labels", "profile", "GMPError"]
+__all__ = ["GMPPlan", "DeviceBatch", "Neighbors", "Workspace", "build_neighbors", "rebuild_neighbors_nosync",
+           "check_status", "features", "features_backward", "GMPFunction", "CapturedStep", "feature_labels",
+           "profile", "GMPError"]
 
 
 def _stream_ptr(stream=None):
@@ -97,13 +98,12 @@ class GMPPlan:
     def get_tuning(self) -> dict:
         t = _lib.Tuning()
         check(_lib.load().gmp_plan_get_tuning(self._h, ctypes.byref(t)))
-        return dict(sigma_group=t.sigma_group, chunk_pairs=t.chunk_pairs, persistent=t.persistent,
-                    bin_divisor=t.bin_divisor)
+        return dict(chunk_pairs=t.chunk_pairs, bin_divisor=t.bin_divisor, blocks_per_cu=t.blocks_per_cu)
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
         cur.update(kw)
-        t = _lib.Tuning(cur["sigma_group"], cur["chunk_pairs"], cur["persistent"], cur["bin_divisor"])
+        t = _lib.Tuning(cur["chunk_pairs"], cur["bin_divisor"], cur["blocks_per_cu"], 0)
         check(_lib.load().gmp_plan_set_tuning(self._h, ctypes.byref(t)))
 
     def workspace_bytes(self, n_structs, n_atoms, capacity) -> int:
@@ -214,6 +214,24 @@ def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: 
     raise GMPError(_lib.GMP_E_CAPACITY, "capacity retry failed")
 
 
+def rebuild_neighbors_nosync(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, nb: Neighbors, stream=None):
+    """Rebuild the lists into nb without any host synchronization (usable
+    under stream capture).  nb.capacity must suffice; an overflow or a
+    device-side error is reported later by check_status()."""
+    L = _lib.load()
+    nbytes = plan.workspace_bytes(batch.n_structs, batch.n_atoms, nb.capacity)
+    buf = ws.get(nbytes)
+    bd, nd = batch.desc(), nb.desc()
+    check(L.gmp_build_neighbors(plan.handle, ctypes.byref(bd), ctypes.byref(nd), None, _ptr(buf), buf.numel(),
+                                _stream_ptr(stream)))
+    return nb
+
+
+def check_status(ws: Workspace, stream=None):
+    """Synchronize and raise on a device-side condition recorded in ws."""
+    check(_lib.load().gmp_check_status(_ptr(ws.buf), ws.buf.numel(), _stream_ptr(stream)))
+
+
 def features(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Workspace, with_components=True,
              xyz=None, cell=None, out=None, comp_out=None, stream=None):
     L = _lib.load()
@@ -269,6 +287,57 @@ class GMPFunction(torch.autograd.Function):
         gp, gc = features_backward(ctx.plan, ctx.batch, ctx.nb, ctx.ws, mu, F, gF.contiguous(), True,
                                    xyz=xyz.contiguous(), cell=cell.contiguous())
         return gp.t().contiguous(), gc.reshape(-1, 9), None, None, None, None
+
+
+class CapturedStep:
+    """Neighbour rebuild (no-sync mode) + forward (+ adjoint) recorded once
+    into a HIP graph through torch.cuda.graph and replayed: one host call
+    launches the whole batch.  Outputs live in fixed buffers (F, mu, and
+    grad_pos / grad_cell when backward=True); inputs are read from the
+    batch's tensors, so updating batch.xyz / batch.cell in place and
+    replaying featurizes the new geometry.  `nb` (from a sync build) fixes
+    the capacity; call check_status(ws) to see overflows."""
+
+    def __init__(self, plan: GMPPlan, batch: DeviceBatch, ws: Workspace, nb: Neighbors, backward=False, G=None):
+        self.plan, self.batch, self.ws, self.nb = plan, batch, ws, nb
+        dev = batch.species.device
+        N = batch.n_atoms
+        ws.get(plan.workspace_bytes(batch.n_structs, N, nb.capacity))  # grow before capture
+        self.F = torch.empty((N, plan.n_features), dtype=plan.dtype, device=dev)
+        self.mu = torch.empty((N, plan.n_components), dtype=torch.float64, device=dev)
+        self.backward = backward
+        if backward:
+            self.G = torch.zeros((N, plan.n_features), dtype=plan.dtype, device=dev)
+            if G is not None:
+                self.G.copy_(G)
+            self.gpos = torch.empty(3 * N, dtype=torch.float64, device=dev)
+            self.gcell = torch.empty(batch.n_structs * 9, dtype=torch.float64, device=dev)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self._run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._run()
+        # the graph holds raw addresses: keep every buffer it touches alive
+        self._held = (ws.buf, nb.offsets, nb.j, nb.shift, nb.bucket_start, nb.sigma_end, nb.wrap, nb.rw,
+                      nb.reverse, batch.xyz, batch.cell, batch.species, batch.atom_offsets, batch.pbc)
+
+    def _run(self):
+        L = _lib.load()
+        rebuild_neighbors_nosync(self.plan, self.batch, self.ws, self.nb)
+        features(self.plan, self.batch, self.nb, self.ws, True, out=self.F, comp_out=self.mu)
+        if self.backward:
+            buf = self.ws.buf
+            bd, nd = self.batch.desc(), self.nb.desc()
+            check(L.gmp_features_backward(self.plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(self.mu),
+                                          _ptr(self.F), _ptr(self.G), _ptr(self.gpos), _ptr(self.gcell), _ptr(buf),
+                                          buf.numel(), _stream_ptr(None)))
+
+    def replay(self):
+        self.graph.replay()
 
 
 class profile:

@@ -1,0 +1,118 @@
+"""Graph capture and the autotuner, on the GPU.
+
+A step (no-sync neighbour rebuild + forward + adjoint) recorded once into a
+HIP graph must reproduce the eager launches bit for bit on every replay,
+with other eager work and synchronizations between the replays, and must
+follow in-place updates of the positions.  The autotuner's choice must keep
+the results within the parity bar and must be served from its cache.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import gmp_synth as gs
+import oracle
+from gpu_helpers import say, assert_features
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_12980_amd as g
+    g.load()
+    return g
+
+
+def _batch(seed):
+    rng = np.random.default_rng(seed)
+    structs = [
+        gs.small_periodic(rng, n_atoms=40, n_elements=3, density=0.06, dmin=1.3),
+        gs.small_periodic(rng, n_atoms=3, n_elements=3, density=0.08, dmin=1.0),
+        gs.small_cluster(rng, n_atoms=12, n_elements=3, radius=3.5),
+        gs.small_periodic(rng, n_atoms=10, n_elements=3, density=0.04, dmin=1.3, pbc=3),
+    ]
+    probes = gs.small_probes(rng, orders=(0, 1, 2, 3, 4), n_sigmas=4, n_elements=3, n_prims=(1, 4), tau=1e-9)
+    return gs.make_batch(structs), probes
+
+
+def _eager(g, plan, db, ws, G):
+    nb = g.build_neighbors(plan, db, ws)
+    F, mu = g.features(plan, db, nb, ws)
+    gp, gc = g.features_backward(plan, db, nb, ws, mu, F, G)
+    torch.cuda.synchronize()
+    return nb, F.clone(), mu.clone(), gp.t().contiguous().view(-1).clone(), gc.reshape(-1).clone()
+
+
+def _same(a, b):
+    return a.shape == b.shape and bool(torch.equal(a, b))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32w"])
+def test_graph_replay_matches_eager(g, precision):
+    say(f"[graph replay {precision}]")
+    b, probes = _batch(5)
+    plan = g.GMPPlan.from_probes(probes, precision)
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    G = torch.as_tensor(np.random.default_rng(3).standard_normal((b.n_atoms, probes.n_features)),
+                        device="cuda").to(plan.dtype)
+    nb, F0, mu0, gp0, gc0 = _eager(g, plan, db, ws, G)
+    nbc = g.build_neighbors(plan, db, ws, capacity=2 * nb.n_pairs + 1024)
+    step = g.CapturedStep(plan, db, ws, nbc, backward=True, G=G)
+    other = g.GMPPlan.from_probes(probes, "fp64")
+    ws2 = g.Workspace()
+    for r in range(4):
+        step.replay()
+        torch.cuda.synchronize()
+        assert _same(step.F, F0), f"replay {r}: features differ"
+        assert _same(step.mu, mu0), f"replay {r}: components differ"
+        assert _same(step.gpos, gp0), f"replay {r}: position gradient differs"
+        assert _same(step.gcell, gc0), f"replay {r}: cell gradient differs"
+        # unrelated eager work between replays
+        nb2 = g.build_neighbors(other, db, ws2)
+        g.features(other, db, nb2, ws2)
+        torch.cuda.synchronize()
+    g.check_status(ws)
+    # in-place geometry update: the replay must featurize the new positions
+    rng = np.random.default_rng(9)
+    db.xyz.add_(torch.as_tensor(0.05 * rng.standard_normal(tuple(db.xyz.shape)), device="cuda"))
+    step.replay()
+    torch.cuda.synchronize()
+    g.check_status(ws)
+    ws3 = g.Workspace()
+    nb3, F1, mu1, gp1, gc1 = _eager(g, plan, db, ws3, G)
+    assert nb3.n_pairs <= nbc.capacity
+    assert _same(step.F, F1) and _same(step.mu, mu1)
+    assert _same(step.gpos, gp1) and _same(step.gcell, gc1)
+    assert not _same(F1, F0)
+
+
+def test_autotune_choice_and_cache(g, tmp_path):
+    say("[autotune]")
+    from paper_2303_12980_amd import autotune
+    b, probes = gs.config("C1")
+    plan = g.GMPPlan.from_probes(probes, "fp32c")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    cache = str(tmp_path / "tune.json")
+    cands = [dict(chunk_pairs=0, bin_divisor=2, blocks_per_cu=0), dict(chunk_pairs=256, bin_divisor=3, blocks_per_cu=0),
+             dict(chunk_pairs=1024, bin_divisor=2, blocks_per_cu=2)]
+    r = autotune.autotune(plan, db, ws, candidates=cands, reps=2, cache_path=cache)
+    assert not r["cached"] and len(r["tried"]) == 3
+    assert r["tuning"] in cands and plan.get_tuning() == r["tuning"]
+    assert r["ms"] == min(t["ms"] for t in r["tried"])
+    with open(cache) as f:
+        assert r["key"] in json.load(f)
+    plan2 = g.GMPPlan.from_probes(probes, "fp32c")
+    r2 = autotune.autotune(plan2, db, ws, candidates=cands, cache_path=cache)
+    assert r2["cached"] and plan2.get_tuning() == r["tuning"]
+    nb = g.build_neighbors(plan2, db, ws)
+    F, _ = g.features(plan2, db, nb, ws)
+    Fref = oracle.features_batch(b, probes)
+    assert_features(F.cpu().numpy(), Fref, probes.tau, 1e-5)

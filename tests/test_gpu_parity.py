@@ -98,17 +98,21 @@ def test_chunked_overlap_matches(g, ws, c1, chunk):
     """Splitting centres into chunks changes only the summation order."""
     b, p, (Fref, _) = c1
     say(f"[c1 chunk {chunk}]")
-    plan, db, nb, F, mu = run_path(g, b, p, "fp64", ws, tuning=dict(chunk_pairs=chunk, sigma_group=1))
+    plan, db, nb, F, mu = run_path(g, b, p, "fp64", ws, tuning=dict(chunk_pairs=chunk))
     assert_features(F.cpu().numpy(), Fref, p.tau, 1e-11)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32w"])
-@pytest.mark.parametrize("sg", [1, 2, 4])
-def test_sigma_groups(g, ws, c1, sg, precision):
+@pytest.mark.parametrize("bin_divisor,blocks", [(1, 0), (3, 1), (4, 0)])
+def test_tunings_do_not_change_lists_or_features(g, ws, c1, bin_divisor, blocks, precision):
+    """Cell-list bin size and the persistent grid size change only the work
+    decomposition: lists stay bit-exact, features within the tolerance."""
     b, p, (Fref, _) = c1
-    say(f"[c1 sigma group {sg} {precision}]")
-    plan, db, nb, F, mu = run_path(g, b, p, precision, ws, tuning=dict(sigma_group=sg))
-    assert_features(F.cpu().numpy(), Fref, p.tau, 1e-5)
+    say(f"[c1 bin_divisor {bin_divisor} blocks/CU {blocks} {precision}]")
+    plan, db, nb, F, mu = run_path(g, b, p, precision, ws,
+                                   tuning=dict(bin_divisor=bin_divisor, blocks_per_cu=blocks))
+    assert check_neighbors(nb, b, p, centres={0: [0, 17, 63]}) == 3
+    assert_features(F.cpu().numpy(), Fref, p.tau, 1e-11 if precision == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32c", 1e-5), ("fp32w", 1e-5)])
