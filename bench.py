@@ -35,6 +35,24 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0
 # v_exp_f32 is a quarter-rate transcendental: 256 CU x 4 SIMD x 16 lanes / 4 x 2.4 GHz
 PEAK_EXP_PER_S = 256 * 4 * 16 / 4 * 2.4e9
+# one wavefront VALU instruction per CU per cycle (4 SIMD x 16 lanes, 64-wide waves)
+VALU_WAVE_INSTS_PER_S = 256 * 2.4e9
+
+
+def counter_record(kernel):
+    """Counter figures committed under profiles/ for this kernel, or None
+    when the kernel's sources changed since they were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters_C2.json")) as f:
+            rec = json.load(f)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return rec if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def parse():
@@ -46,7 +64,105 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--sample-centres", type=int, default=48)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
+
+
+def _median_ms(fn, reps, torch):
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    return float(np.median(ts))
+
+
+def batched_vs_per_structure(g, gs, torch):
+    """2048 structures of 8-256 atoms (half periodic triclinic, half
+    clusters), FP32 compensated forward (neighbour build + overlap + norm):
+    one batched launch sequence replayed from a HIP graph, against the same
+    work issued structure by structure through the C ABI with pre-sized
+    capacity and no graph.  Outputs of the two must be bitwise equal."""
+    import ctypes
+    from paper_2303_12980_amd import _lib, autotune
+    t0 = time.time()
+    batch, probes = gs.config("C3")
+    print(f"[bench] batched workload: {batch.n_structs} structures, {batch.n_atoms} atoms "
+          f"({time.time() - t0:.1f}s to generate)", file=sys.stderr, flush=True)
+    db = g.DeviceBatch.from_batch(batch)
+    plan = g.GMPPlan.from_probes(probes, "fp32c")
+    ws = g.Workspace()
+    tune = autotune.autotune(plan, db, ws, backward=False, reps=2, candidates=[
+        dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0) for c in (1024, 2048, 4096) for b in (2, 3)],
+        cache_path=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
+    print(f"[bench] autotuned {tune['tuning']} ({'cached' if tune['cached'] else 'searched'})",
+          file=sys.stderr, flush=True)
+    nb = g.build_neighbors(plan, db, ws, reverse=False)
+    step = g.CapturedStep(plan, db, ws, nb, backward=False)
+    for _ in range(3):
+        step.replay()
+    graph_ms = _median_ms(step.replay, 20, torch)
+    g.check_status(ws)
+
+    def eager():
+        g.rebuild_neighbors_nosync(plan, db, ws, nb)
+        g.features(plan, db, nb, ws, True, out=step.F, comp_out=step.mu)
+    eager_ms = _median_ms(eager, 5, torch)
+    Fb, mub = step.F.clone(), step.mu.clone()
+
+    # per-structure launches: pre-built descriptors, one shared workspace
+    L = _lib.load()
+    offs_h = batch.atom_offsets
+    poffs = nb.offsets.cpu().numpy()
+    Fp = torch.empty_like(Fb)
+    mup = torch.empty_like(mub)
+    calls = []
+    need = 0
+    for s in range(batch.n_structs):
+        a0, a1 = int(offs_h[s]), int(offs_h[s + 1])
+        v = db.structure(s, a0, a1)
+        nbs = g.Neighbors(plan, v, int(poffs[a1] - poffs[a0]), reverse=False)
+        nbs.n_pairs = nbs.capacity
+        need = max(need, plan.workspace_bytes(1, a1 - a0, nbs.capacity))
+        calls.append((v, nbs, v.desc(), nbs.desc(), Fp[a0:a1], mup[a0:a1]))
+    wbuf = ws.get(need)
+    wptr, wn = wbuf.data_ptr(), wbuf.numel()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def per_structure():
+        for v, nbs, bd, nd, F, mu in calls:
+            st = L.gmp_build_neighbors(plan.handle, ctypes.byref(bd), ctypes.byref(nd), None, ctypes.c_void_p(wptr),
+                                       ctypes.c_size_t(wn), stream)
+            st = st or L.gmp_features(plan.handle, ctypes.byref(bd), ctypes.byref(nd), ctypes.c_void_p(F.data_ptr()),
+                                      ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(wptr), ctypes.c_size_t(wn),
+                                      stream)
+            if st:
+                _lib.check(st)
+    per_structure()
+    per_ms = _median_ms(per_structure, 3, torch)
+    g.check_status(ws)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    step.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    graph_event_ms = ev[0].elapsed_time(ev[1])
+    bitwise = bool(torch.equal(Fp, Fb)) and bool(torch.equal(mup, mub))
+    N, nf = batch.n_atoms, probes.n_features
+    return {
+        "workload": f"{batch.n_structs} structures, {N} atoms (8-256 each, half periodic triclinic at "
+                    f"0.08/A^3, half clusters), 10 elements, 3-6 primitives, l=0..4 x 8 sigma, fp32c forward",
+        "atoms": N, "pairs": int(nb.n_pairs), "tuning": tune["tuning"],
+        "graph_replay_ms": graph_ms, "graph_replay_event_ms": graph_event_ms, "batched_eager_ms": eager_ms,
+        "per_structure_ms": per_ms,
+        "speedup_graph_vs_per_structure": per_ms / graph_ms,
+        "atoms_features_per_s_graph": N * nf / (graph_ms * 1e-3),
+        "bitwise_equal_to_per_structure": bitwise,
+    }
 
 
 def algorithmic_counts(nb, probes, rc2):
@@ -86,6 +202,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(256 << 18, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     t0 = time.time()
     batch, probes = gs.config(args.workload)
     N, nf = batch.n_atoms, probes.n_features
@@ -145,8 +268,13 @@ def main():
     counts = algorithmic_counts(nb32, probes, plan32.rc2)
     ov = kern["overlap"]
     achieved = counts["flops"] / (ov["avg_ms"] * 1e-3) / 1e12
+    rec = counter_record("overlap")
     roofline = {"kernel": "overlap", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": rec["hbm_bytes_per_launch"] if rec else None,
+                "executed": ({"fp32_tflops": 64 * rec["valu_flops_fp32_per_wave"] / (ov["avg_ms"] * 1e-3) / 1e12,
+                              "valu_issue_frac": rec["valu_insts"] / (ov["avg_ms"] * 1e-3) / VALU_WAVE_INSTS_PER_S,
+                              "source": "profiles/counters_C2.json"} if rec else None),
                 "exp_rate_per_s": counts["exps"] / (ov["avg_ms"] * 1e-3),
                 "exp_frac": counts["exps"] / (ov["avg_ms"] * 1e-3) / PEAK_EXP_PER_S,
                 "algorithmic_flops_per_launch": counts["flops"], "avg_launch_ms": ov["avg_ms"],
@@ -165,19 +293,18 @@ def main():
         F64 = out64[0].cpu().numpy()[cs]
         acc["fp64_max_rel_err"] = float(np.max(np.abs(F64[big] - Fref[big]) / Fref[big]))
 
-    # CPU baseline: the oracle (forward) on a bounded sample of centres
+    # CPU baseline: the oracle, forward, over every centre of the workload
     cpu = None
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
         threads = min(threads, len(os.sched_getaffinity(0)))
-        n_s = min(N, 64 * threads)
-        cs2 = np.arange(n_s, dtype=np.int32)
         t = time.perf_counter()
-        oracle.features(batch.structure(0), probes, centres=cs2)
+        oracle.features(batch.structure(0), probes)
         dt = time.perf_counter() - t
-        cpu = {"value": n_s * nf / dt, "unit": "atoms*features/s", "cores": threads, "kind": "oracle",
-               "sample": f"FP64 oracle forward (brute-force neighbours + closed-form overlaps) for the first "
-                         f"{n_s} of {N} centres, {dt:.1f} s wall on {threads} OpenMP threads; forward only"}
+        cpu = {"value": N * nf / dt, "unit": "atoms*features/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 oracle forward (brute-force neighbours + closed-form overlaps) over all {N} "
+                         f"centres of the workload, {dt:.1f} s wall on {threads} OpenMP threads; forward only "
+                         f"(the oracle's analytic gradient is not timed)"}
 
     atoms_feat = N * nf
     value = atoms_feat / dt_fb
@@ -203,6 +330,12 @@ def main():
     }
     if not args.no_fp64:
         out["kernels_fp64_ms_per_step"] = {k: round(v[1] / max(3, args.steps // 4), 5) for k, v in prof64.items()}
+    if not args.no_batched:
+        del ws, nb32, out32
+        if not args.no_fp64:
+            del nb64, out64
+        torch.cuda.empty_cache()
+        out["batched"] = batched_vs_per_structure(g, gs, torch)
     print(json.dumps(out))
 
 

@@ -135,6 +135,19 @@ class DeviceBatch:
     def from_batch(cls, b, device="cuda"):
         return cls(b.atom_offsets, b.pos, b.species, b.cell, b.pbc, device)
 
+    def structure(self, s: int, a0: int, a1: int) -> "DeviceBatch":
+        """One-structure batch viewing this batch's memory (atoms a0:a1 of
+        structure s); host offsets are passed in to avoid a device read."""
+        v = DeviceBatch.__new__(DeviceBatch)
+        dev = self.species.device
+        v.atom_offsets = torch.tensor([0, a1 - a0], dtype=torch.int64, device=dev)
+        v.xyz = self.xyz[:, a0:a1]
+        v.species = self.species[a0:a1]
+        v.cell = self.cell[s:s + 1]
+        v.pbc = self.pbc[s:s + 1]
+        v.n_structs, v.n_atoms = 1, a1 - a0
+        return v
+
     def desc(self, xyz: Optional[torch.Tensor] = None, cell: Optional[torch.Tensor] = None):
         xyz = self.xyz if xyz is None else xyz
         cell = self.cell if cell is None else cell
