@@ -9,11 +9,15 @@ overlap threshold 1e-11; synthetic, seeded.
 
 One step = the whole hot path on that batch: lattice wrap + cell list +
 neighbour lists (with reverse index), forward features (overlap + norm),
-and the adjoint with a seeded N(0,1) upstream gradient (dL/dR, dL/dcell).
-The reported value is atoms*features/s of that step in the FP32
-compensated path; the FP64 path and forward-only rates are reported beside
-it.  Per-kernel durations come from HIP events recorded by the library on
-the launch stream (torch's current stream) during the timed steps.
+and the adjoint with a seeded N(0,1) upstream gradient (dL/dR, dL/dcell),
+recorded once into a HIP graph and replayed once per step (the neighbour
+build runs in its no-sync mode with the capacity of a first, synchronous
+build).  The reported value is atoms*features/s of that step in the FP32
+compensated path; the FP32-wide and FP64 paths, forward-only rates and
+eager (one host call per stage) timings are reported beside it.
+Per-kernel durations come from HIP events recorded by the library around
+each launch on the launch stream (torch's current stream) in separate
+eager steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -127,6 +131,7 @@ def batched_vs_per_structure(g, gs, torch):
         v = db.structure(s, a0, a1)
         nbs = g.Neighbors(plan, v, int(poffs[a1] - poffs[a0]), reverse=False)
         nbs.n_pairs = nbs.capacity
+        nbs.max_list = int(np.diff(poffs[a0:a1 + 1]).max())
         need = max(need, plan.workspace_bytes(1, a1 - a0, nbs.capacity))
         calls.append((v, nbs, v.desc(), nbs.desc(), Fp[a0:a1], mup[a0:a1]))
     wbuf = ws.get(need)
@@ -216,54 +221,62 @@ def main():
           file=sys.stderr, flush=True)
     db = g.DeviceBatch.from_batch(batch, dev)
     G = torch.as_tensor(np.random.default_rng(7).standard_normal((N, nf)), device=dev)
-    ws = g.Workspace(dev)
 
     def make(prec):
         plan = g.GMPPlan.from_probes(probes, prec)
-        nb = g.build_neighbors(plan, db, ws)
-        return plan, nb
+        w = g.Workspace(dev)
+        nb = g.build_neighbors(plan, db, w)
+        return plan, w, nb
 
-    def step(plan, nb, backward=True):
-        nb2 = g.build_neighbors(plan, db, ws, out=nb)
-        F, mu = g.features(plan, db, nb2, ws)
+    def eager_step(plan, w, nb, backward=True):
+        nb2 = g.build_neighbors(plan, db, w, out=nb)
+        F, mu = g.features(plan, db, nb2, w)
         if backward:
-            gp, gc = g.features_backward(plan, db, nb2, ws, mu, F, G)
-            return F, mu, gp, gc
-        return F, mu, None, None
+            g.features_backward(plan, db, nb2, w, mu, F, G)
+        return F
 
-    def timed(plan, nb, steps, warmup, backward=True, profile=False):
+    def wall_ms(fn, steps, warmup):
         for _ in range(warmup):
-            step(plan, nb, backward)
+            fn()
         torch.cuda.synchronize()
-        prof = None
-        if profile:
-            pctx = g.profile().__enter__()
         t = time.perf_counter()
         for _ in range(steps):
-            out = step(plan, nb, backward)
+            fn()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / steps
-        if profile:
-            pctx.__exit__(None, None, None)
-            prof = pctx.result
-        return dt, out, prof
+        return (time.perf_counter() - t) / steps * 1e3
 
-    results = {}
-    plan32, nb32 = make("fp32c")
-    dt_fb, out32, prof = timed(plan32, nb32, args.steps, args.warmup, True, True)
-    print(f"[bench] fp32c fwd+bwd {dt_fb * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-    dt_f, _, prof_f = timed(plan32, nb32, args.steps, 1, False, True)
-    results["fp32c"] = dict(fwd_bwd_ms=dt_fb * 1e3, fwd_ms=dt_f * 1e3)
-    if not args.no_fp64:
-        plan64, nb64 = make("fp64")
-        dt64_fb, out64, prof64 = timed(plan64, nb64, max(3, args.steps // 4), 1, True, True)
-        dt64_f, _, _ = timed(plan64, nb64, max(3, args.steps // 4), 1, False, False)
-        results["fp64"] = dict(fwd_bwd_ms=dt64_fb * 1e3, fwd_ms=dt64_f * 1e3)
-        print(f"[bench] fp64 fwd+bwd {dt64_fb * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    results, graphs = {}, {}
+    for prec in (["fp32c", "fp32w"] + ([] if args.no_fp64 else ["fp64"])):
+        plan, w, nb = make(prec)
+        r = {}
+        r["eager_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True), args.steps, args.warmup)
+        r["eager_fwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, False), args.steps, args.warmup)
+        fb = g.CapturedStep(plan, db, w, nb, backward=True, G=G)
+        r["graph_fwd_bwd_ms"] = wall_ms(fb.replay, args.steps, args.warmup)
+        fo = g.CapturedStep(plan, db, w, nb, backward=False)
+        r["graph_fwd_ms"] = wall_ms(fo.replay, args.steps, args.warmup)
+        g.check_status(w)
+        results[prec] = r
+        graphs[prec] = (plan, w, nb, fb)
+        print(f"[bench] {prec}: graph fwd+bwd {r['graph_fwd_bwd_ms']:.3f} ms, fwd {r['graph_fwd_ms']:.3f} ms; "
+              f"eager fwd+bwd {r['eager_fwd_bwd_ms']:.3f} ms", file=sys.stderr, flush=True)
 
-    # per-kernel averages over the timed fp32c steps
-    kern = {k: dict(launches=v[0], avg_ms=v[1] / v[0], ms_per_step=v[1] / args.steps) for k, v in prof.items()}
-    kern_f = {k: dict(launches=v[0], avg_ms=v[1] / v[0]) for k, v in prof_f.items()}
+    def kernel_profile(prec, backward, steps=5):
+        plan, w, nb, _ = graphs[prec]
+        eager_step(plan, w, nb, backward)
+        torch.cuda.synchronize()
+        with g.profile() as pr:
+            for _ in range(steps):
+                eager_step(plan, w, nb, backward)
+            torch.cuda.synchronize()
+        return {k: dict(launches=v[0], avg_ms=v[1] / v[0], ms_per_step=v[1] / steps) for k, v in pr.result.items()}
+
+    plan32, _, nb32, step32 = graphs["fp32c"]
+    dt_fb = results["fp32c"]["graph_fwd_bwd_ms"] * 1e-3
+    dt_f = results["fp32c"]["graph_fwd_ms"] * 1e-3
+    # per-kernel averages (library HIP events around each launch, eager steps)
+    kern = kernel_profile("fp32c", True)
+    kern_f = kernel_profile("fp32c", False)
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     counts = algorithmic_counts(nb32, probes, plan32.rc2)
     ov = kern["overlap"]
@@ -280,18 +293,16 @@ def main():
                 "algorithmic_flops_per_launch": counts["flops"], "avg_launch_ms": ov["avg_ms"],
                 "dominant_kernel_of_step": dom}
 
-    # accuracy on sampled centres vs the FP64 oracle
+    # accuracy on sampled centres vs the FP64 oracle (outputs of the last graph replays)
     import oracle
     rng = np.random.default_rng(11)
     cs = np.sort(rng.choice(N, size=min(args.sample_centres, N), replace=False))
     Fref = oracle.features(batch.structure(0), probes, centres=cs)
-    F32 = out32[0].cpu().numpy()[cs]
     big = Fref > probes.tau
-    acc = {"sampled_centres": int(len(cs)),
-           "fp32c_max_rel_err": float(np.max(np.abs(F32[big] - Fref[big]) / Fref[big]))}
-    if not args.no_fp64:
-        F64 = out64[0].cpu().numpy()[cs]
-        acc["fp64_max_rel_err"] = float(np.max(np.abs(F64[big] - Fref[big]) / Fref[big]))
+    acc = {"sampled_centres": int(len(cs)), "rule": "max |F-F_ref|/F_ref over F_ref > tau"}
+    for prec, (_, _, _, st) in graphs.items():
+        Fg = st.F.double().cpu().numpy()[cs]
+        acc[f"{prec}_max_rel_err"] = float(np.max(np.abs(Fg[big] - Fref[big]) / Fref[big]))
 
     # CPU baseline: the oracle, forward, over every centre of the workload
     cpu = None
@@ -309,7 +320,7 @@ def main():
     atoms_feat = N * nf
     value = atoms_feat / dt_fb
     out = {
-        "metric": "atoms*features/s (fwd+bwd, FP32 compensated, incl. neighbour build)",
+        "metric": "atoms*features/s (fwd+bwd, FP32 compensated, incl. neighbour build; one graph replay per step)",
         "value": value, "unit": "atoms*features/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt_fb * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -319,21 +330,22 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "rates": {
-            "fp32c_fwd_bwd": atoms_feat / dt_fb,
-            "fp32c_fwd": atoms_feat / dt_f,
-            **({"fp64_fwd_bwd": atoms_feat / (results["fp64"]["fwd_bwd_ms"] * 1e-3),
-                "fp64_fwd": atoms_feat / (results["fp64"]["fwd_ms"] * 1e-3)} if "fp64" in results else {}),
+            **{f"{prec}_{mode}": atoms_feat / (r[f"{kind}_{mode}_ms"] * 1e-3)
+               for prec, r in results.items() for kind in ("graph", "eager") for mode in ("fwd_bwd", "fwd")
+               if kind == "graph"},
+            **{f"{prec}_{mode}_eager": atoms_feat / (r[f"eager_{mode}_ms"] * 1e-3)
+               for prec, r in results.items() for mode in ("fwd_bwd", "fwd")},
             "fp32c_fwd_kernels_only": atoms_feat / (1e-3 * (kern_f["overlap"]["avg_ms"] + kern_f["norm"]["avg_ms"])),
         },
+        "timings_ms": results,
         "accuracy": acc,
         "kernels_fp32c_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in kern.items()},
     }
     if not args.no_fp64:
-        out["kernels_fp64_ms_per_step"] = {k: round(v[1] / max(3, args.steps // 4), 5) for k, v in prof64.items()}
+        out["kernels_fp64_ms_per_step"] = {k: round(v["ms_per_step"], 5) for k, v in kernel_profile("fp64", True).items()}
+    out["kernels_fp32w_ms_per_step"] = {k: round(v["ms_per_step"], 5) for k, v in kernel_profile("fp32w", True).items()}
     if not args.no_batched:
-        del ws, nb32, out32
-        if not args.no_fp64:
-            del nb64, out64
+        del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()
         out["batched"] = batched_vs_per_structure(g, gs, torch)
     print(json.dumps(out))

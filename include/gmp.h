@@ -116,6 +116,9 @@ typedef struct {
   double *rw;                    /* [3*n_atoms] wrapped positions, SoA (x block, y block, z block) */
   int32_t *reverse;              /* [capacity] or NULL: local index of (j, i, -n) in j's list;
                                     required by gmp_features_backward */
+  int64_t max_list;              /* [host] longest list of the last synchronous build (set by it); a
+                                    no-sync build sizes its in-LDS sort for this many entries (0: the
+                                    largest supported) and flags a longer list in the status word */
 } gmp_neighbors;
 
 /* Plan: validates the probe set, infers rc(sigma)^2 from the overlap

@@ -114,10 +114,10 @@ WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t capacity, vo
   L.chunk_off = c.take<int64_t>(N + 1);
   L.counter = c.take<unsigned long long>(32);
   L.rw4 = c.take<double4>(N);
-  L.pair_key = c.take<uint64_t>((size_t)capacity);
-  L.pair_centre = c.take<int32_t>((size_t)capacity);
   L.bcoef = c.take<char>(bwd_coef_elems(p, N) * tsz);
   L.vbuf = c.take<char>((size_t)capacity * 4 * tsz);
+  L.pair_key = c.take<uint64_t>((size_t)capacity);
+  L.pair_centre = c.take<int32_t>((size_t)capacity);
   L.cellpart = c.take<double>((size_t)N * 9);
   L.bytes = c.off + 256;
   return L;
@@ -443,6 +443,7 @@ gmp_status check_batch(const gmp_plan *p, const gmp_batch *b) {
 gmp_status check_nbrs(const gmp_plan *p, const gmp_batch *b, const gmp_neighbors *n, bool need_lists) {
   if (!n) return set_error(GMP_E_INVALID, "null neighbour lists");
   if (n->capacity < 0) return set_error(GMP_E_INVALID, "negative capacity");
+  if (n->max_list < 0) return set_error(GMP_E_INVALID, "negative max_list");
   if (!n->offsets || !n->bucket_start || !n->sigma_end || !n->wrap || !n->rw)
     return set_error(GMP_E_INVALID, "null neighbour arrays");
   if (need_lists && n->capacity > 0 && (!n->j || !n->shift)) return set_error(GMP_E_INVALID, "null j/shift");
@@ -549,11 +550,12 @@ gmp_status gmp_build_neighbors(const gmp_plan *p, const gmp_batch *b, gmp_neighb
     if ((int64_t)stw[4] > kSortMax)
       return set_error(GMP_E_UNSUPPORTED, "a centre has " + std::to_string(stw[4]) +
                                               " neighbours; the in-LDS sort holds " + std::to_string(kSortMax));
+    n->max_list = stw[4];
     lds_keys = lds_keys_for(p, stw[4]);
     if ((int64_t)stw[4] > lds_keys)
       return set_error(GMP_E_UNSUPPORTED, "a centre's neighbour list exceeds the in-LDS sort for this probe set");
   } else {
-    lds_keys = lds_keys_for(p, kSortMax);
+    lds_keys = lds_keys_for(p, n->max_list > 0 ? n->max_list : kSortMax);
   }
   launch_fill(p, bt, nb, L, lds_keys, s);
   if (n->reverse) launch_reverse(p, bt, nb, L, n_pairs ? *n_pairs : n->capacity, s);

@@ -303,19 +303,28 @@ __device__ inline int shell_of(const PlanDev &P, double q) {
   return sh;
 }
 
-// One wavefront per centre: count neighbours per (shell, species) bucket.
+// Workgroup index -> position in a sequence, such that the workgroups the
+// dispatcher places on one XCD (every eighth) take one contiguous range.
+__device__ inline int64_t xcd_contiguous(int64_t b, int64_t nblk) {
+  const int64_t x = b & 7, per = nblk >> 3, rem = nblk & 7;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
+// One wavefront per centre (centres in cell-list order): count neighbours per
+// (shell, species) bucket.
 __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                                const double *fw, const int64_t *bin_start,
                                                const double *sx, const double *sy, const double *sz,
-                                               const int32_t *ssp, int32_t *cnt, int64_t *ptotal,
-                                               uint32_t *status) {
+                                               const int32_t *sid, const int32_t *ssp, int32_t *cnt,
+                                               int64_t *ptotal, uint32_t *status) {
   extern __shared__ int32_t lds_cnt[];
   __shared__ CandLds lds_cand[4];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int nbk = P.E * P.S;
   int32_t *c = lds_cnt + w * nbk;
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
+  const int64_t slot = xcd_contiguous(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + w;
   const int64_t N = bt.n_atoms;
+  const int64_t i = slot < N ? sid[slot] : N;
   for (int t = lane; t < nbk; t += kWave) c[t] = 0;
   wave_lds_sync();
   if (i < N) {
@@ -398,9 +407,9 @@ __device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3) {
   return ((uint64_t)j << 24) | ((uint64_t)(n1 + 128) << 16) | ((uint64_t)(n2 + 128) << 8) | (uint64_t)(n3 + 128);
 }
 
-// One workgroup per centre: fill its buckets (shell h, species e), in
-// bucket order h * E + e, in LDS; sort every bucket by (j, n); write j /
-// shift, the bucket starts and the sigma-prefix ends.
+// One workgroup per centre (centres in cell-list order): fill its buckets
+// (shell h, species e), in bucket order h * E + e, in LDS; sort every bucket
+// by (j, n); write j / shift, the bucket starts and the sigma-prefix ends.
 __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                               const double *fw, const int64_t *bin_start,
                                               const double *sx, const double *sy, const double *sz,
@@ -413,7 +422,7 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   uint64_t *keys = lds_u64;
   int32_t *bstart = (int32_t *)(lds_u64 + lds_keys);  // [nbk+1]
   int32_t *cursor = bstart + nbk + 1;                 // [nbk]
-  const int64_t i = blockIdx.x;
+  const int64_t i = sid[xcd_contiguous(blockIdx.x, gridDim.x)];  // centres in cell-list order
   const int64_t N = bt.n_atoms;
   const int tid = threadIdx.x, w = tid / kWave, nw = blockDim.x / kWave, lane = lane_id();
   const int64_t base = nb.offsets[i];
@@ -546,7 +555,7 @@ void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const
   int64_t blocks = (bt.n_atoms + 3) / 4;
   size_t smem = sizeof(int32_t) * 4 * p->dev.E * p->dev.S;
   GMP_LAUNCH("nbr_count", k_count, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo, L.fw,
-             L.bin_start, L.sx, L.sy, L.sz, L.ssp, L.cnt, L.ptotal, L.status);
+             L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.cnt, L.ptotal, L.status);
 }
 
 void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int lds_keys,

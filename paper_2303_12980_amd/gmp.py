@@ -178,6 +178,7 @@ class Neighbors:
         E, S = plan.n_elements, len(plan.sigmas)
         self.capacity = int(capacity)
         self.n_pairs = 0
+        self.max_list = 0  # longest list of the last synchronous build (sizes no-sync rebuilds)
         self.offsets = torch.zeros(N + 1, dtype=torch.int64, device=dev)
         self.j = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
         self.shift = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
@@ -191,7 +192,7 @@ class Neighbors:
         return _lib.NbrDesc(self.capacity, self.n_pairs, self.offsets.data_ptr(), self.j.data_ptr(),
                             self.shift.data_ptr(), self.bucket_start.data_ptr(), self.sigma_end.data_ptr(),
                             self.wrap.data_ptr(), self.rw.data_ptr(),
-                            self.reverse.data_ptr() if self.reverse is not None else 0)
+                            self.reverse.data_ptr() if self.reverse is not None else 0, self.max_list)
 
     # host-side views for tests
     def shifts_numpy(self):
@@ -223,6 +224,7 @@ def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: 
             continue
         check(st)
         nb.n_pairs = int(npairs.value)
+        nb.max_list = int(nd.max_list)
         return nb
     raise GMPError(_lib.GMP_E_CAPACITY, "capacity retry failed")
 
