@@ -31,6 +31,7 @@ size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms);
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
                      double *grad_cell, unsigned long long *counter, double4 *rw4, int C, hipStream_t s);
+void fill_zero3(void *p0, size_t b0, void *p1, size_t b1, void *p2, size_t b2, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -516,16 +517,15 @@ gmp_status gmp_build_neighbors(const gmp_plan *p, const gmp_batch *b, gmp_neighb
   const int64_t N = b->n_atoms;
   BatchDev bt = to_dev(b);
   NbrDev nb = to_dev(n);
-  fill_zero(L.status, 64 * sizeof(uint32_t), s);
   if (N == 0) {
+    fill_zero(L.status, 64 * sizeof(uint32_t), s);
     fill_zero(n->offsets, sizeof(int64_t), s);
     n->n_pairs = 0;
     if (n_pairs) *n_pairs = 0;
     return GMP_OK;
   }
   const int64_t NB = N + b->n_structs;
-  fill_zero(L.bin_count, NB * sizeof(int32_t), s);
-  fill_zero(L.bin_fill, NB * sizeof(int32_t), s);
+  fill_zero3(L.status, 64 * sizeof(uint32_t), L.bin_count, NB * sizeof(int32_t), L.bin_fill, NB * sizeof(int32_t), s);
   launch_struct_setup(p, bt, L, s);
   launch_wrap(bt, nb, L, p->dev.E, s);
   scan_i32_to_i64(L.bin_count, L.bin_start, NB, L.scan_aux, s);

@@ -310,8 +310,8 @@ __device__ inline int64_t xcd_contiguous(int64_t b, int64_t nblk) {
   return x * per + (x < rem ? x : rem) + (b >> 3);
 }
 
-// One wavefront per centre (centres in cell-list order): count neighbours per
-// (shell, species) bucket.
+// One workgroup per centre (centres in cell-list order): count neighbours
+// per (shell, species) bucket; the wavefronts share the centre's candidates.
 __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                                const double *fw, const int64_t *bin_start,
                                                const double *sx, const double *sy, const double *sz,
@@ -319,40 +319,40 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
                                                int64_t *ptotal, uint32_t *status) {
   extern __shared__ int32_t lds_cnt[];
   __shared__ CandLds lds_cand[4];
-  const int w = threadIdx.x / kWave, lane = lane_id();
+  __shared__ int64_t lds_tot[4];
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave, lane = lane_id();
   const int nbk = P.E * P.S;
-  int32_t *c = lds_cnt + w * nbk;
-  const int64_t slot = xcd_contiguous(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + w;
+  int32_t *c = lds_cnt;
   const int64_t N = bt.n_atoms;
-  const int64_t i = slot < N ? sid[slot] : N;
-  for (int t = lane; t < nbk; t += kWave) c[t] = 0;
-  wave_lds_sync();
-  if (i < N) {
-    const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
-    Cand C;
-    cand_setup(C, info, bt, s, fw, i);
-    const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
-    for_each_candidate(C, bin_start, P.rcmax2, 0, 1, lds_cand[w],
-                       [&](int t, const int *n, double shx, double shy, double shz) {
-                         const double dx = (sx[t] - rix) + shx;
-                         const double dy = (sy[t] - riy) + shy;
-                         const double dz = (sz[t] - riz) + shz;
-                         const double q = (dx * dx + dy * dy) + dz * dz;
-                         if (q <= P.rcmax2) atomicAdd(&c[shell_of(P, q) * P.E + ssp[t]], 1);
-                       });
+  const int64_t i = sid[xcd_contiguous(blockIdx.x, gridDim.x)];
+  for (int t = threadIdx.x; t < nbk; t += blockDim.x) c[t] = 0;
+  __syncthreads();
+  const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  Cand C;
+  cand_setup(C, info, bt, s, fw, i);
+  const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+  for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
+                     [&](int t, const int *n, double shx, double shy, double shz) {
+                       const double dx = (sx[t] - rix) + shx;
+                       const double dy = (sy[t] - riy) + shy;
+                       const double dz = (sz[t] - riz) + shz;
+                       const double q = (dx * dx + dy * dy) + dz * dz;
+                       if (q <= P.rcmax2) atomicAdd(&c[shell_of(P, q) * P.E + ssp[t]], 1);
+                     });
+  __syncthreads();
+  int64_t tot = 0;
+  for (int t = threadIdx.x; t < nbk; t += blockDim.x) {
+    cnt[i * nbk + t] = c[t];
+    tot += c[t];
   }
-  wave_lds_sync();
-  if (i < N) {
-    int64_t tot = 0;
-    for (int t = lane; t < nbk; t += kWave) {
-      cnt[i * nbk + t] = c[t];
-      tot += c[t];
-    }
-    for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, kWave);
-    if (lane == 0) {
-      ptotal[i] = tot;
-      atomicMax(status + 4, (uint32_t)(tot > 0x7fffffff ? 0x7fffffff : tot));
-    }
+  for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, kWave);
+  if (lane == 0) lds_tot[w] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t all = 0;
+    for (int k = 0; k < nw; ++k) all += lds_tot[k];
+    ptotal[i] = all;
+    atomicMax(status + 4, (uint32_t)(all > 0x7fffffff ? 0x7fffffff : all));
   }
 }
 
@@ -361,23 +361,20 @@ __device__ inline void cmpswap(uint64_t *a, int i, int l) {
   if (x > y) { a[i] = y; a[l] = x; }
 }
 
-// Sort a[0..n) ascending by one wavefront: bitonic network whose first
-// merge stage compares mirror pairs, so every comparator is ascending and
-// indices >= n act as +infinity without being touched.
+// Sort a[0..n) of distinct keys ascending by one wavefront.  Up to 64 keys:
+// each lane counts the keys below its own (broadcast LDS reads) and stores
+// its key at that rank.  Longer: bitonic network whose first merge stage
+// compares mirror pairs, so every comparator is ascending and indices >= n
+// act as +infinity without being touched.
 __device__ void wave_sort(uint64_t *a, int n) {
   const int lane = lane_id();
   if (n <= 1) return;
   if (n <= kWave) {
-    uint64_t k = lane < n ? a[lane] : ~0ull;
-    for (int size = 2; size <= kWave; size <<= 1)
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        uint64_t o = __shfl_xor(k, stride, kWave);
-        bool up = (lane & size) == 0;
-        bool lower = (lane & stride) == 0;
-        uint64_t mn = k < o ? k : o, mx = k < o ? o : k;
-        k = (lower == up) ? mn : mx;
-      }
-    if (lane < n) a[lane] = k;
+    const uint64_t k = lane < n ? a[lane] : 0ull;
+    int rank = 0;
+    for (int m = 0; m < n; ++m) rank += a[m] < k ? 1 : 0;
+    wave_lds_sync();
+    if (lane < n) a[rank] = k;
     wave_lds_sync();
     return;
   }
@@ -552,8 +549,8 @@ void launch_scatter(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int
 }
 
 void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, hipStream_t s) {
-  int64_t blocks = (bt.n_atoms + 3) / 4;
-  size_t smem = sizeof(int32_t) * 4 * p->dev.E * p->dev.S;
+  int64_t blocks = bt.n_atoms;
+  size_t smem = sizeof(int32_t) * p->dev.E * p->dev.S;
   GMP_LAUNCH("nbr_count", k_count, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo, L.fw,
              L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.cnt, L.ptotal, L.status);
 }
