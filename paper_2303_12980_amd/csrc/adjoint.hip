@@ -103,7 +103,10 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, int64_t N, const do
 // items.  Lanes take consecutive pairs of the centre's list; a pair is used
 // by every sigma whose prefix contains it.  Radial coefficients come from
 // the LDS copy of the plan table (row of the lane's neighbour species); the
-// centre's polynomial coefficients M, Dx, Dy, Dz are wavefront-uniform.
+// centre's polynomial coefficients M, Dx, Dy, Dz are staged in LDS per item
+// and read wavefront-uniformly.  The loads of pair data (j, shift) run two
+// steps ahead and the gathers of the neighbours' wrapped positions one step
+// ahead.  Dynamic LDS: [coefficient table if staged][4 wavefronts][S * NB].
 template <int LMAX, int KB, bool F64, bool LDS>
 __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
                                                    const void *bcoef_, void *vbuf_, int C, int64_t n_items,
@@ -113,26 +116,23 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
   constexpr int NB = NM + 3 * NM1;
   extern __shared__ double lds_dyn[];
   __shared__ int lds_k[kMaxElements];
-  __shared__ T lds_bc[4][kMaxSigmas * NB];  // per wavefront: the current centre's M, Dx, Dy, Dz
   const int S = P.S, E = P.E;
   const T *__restrict__ tabg = (const T *)tab_global;
   T *tabl = (T *)lds_dyn;
-  if (LDS) {
-    const int n = S * E * KB * kCoefStride;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) tabl[idx] = tabg[idx];
-  }
+  const int tab_n = LDS ? S * E * KB * kCoefStride : 0;
+  if (LDS)
+    for (int idx = threadIdx.x; idx < tab_n; idx += blockDim.x) tabl[idx] = tabg[idx];
   for (int e = threadIdx.x; e < E; e += blockDim.x) lds_k[e] = P.kcount[e];
   __syncthreads();
   const int lane = lane_id();
-  const int64_t N = bt.n_atoms;
   T *vbuf = (T *)vbuf_;
   const int mask = P.order_mask;
+  T *bcoef = tabl + tab_n + (size_t)(threadIdx.x / kWave) * S * NB;
   for (;;) {
     const int64_t item = next_item(counter);
     if (item >= n_items) break;
     const int64_t i = item / C;
     const int c = (int)(item - i * C);
-    T *bcoef = lds_bc[threadIdx.x / kWave];
     {
       const T *src = (const T *)bcoef_ + (size_t)i * S * NB;
       for (int t = lane; t < S * NB; t += kWave) bcoef[t] = src[t];
@@ -148,17 +148,27 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
     const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
     // sigma prefix ends, one per lane (lane s <-> sigma s)
     const int end_lane = lane < S ? nb.sigma_end[i * S + lane] : 0;
+    // pipeline: (jb, wb, rb) current step, (jc, wc) the step after
+    const int32_t ii = (int32_t)i;
+    int32_t jb = ii, wb = 0, jc = ii, wc = 0;
+    if (clo + lane < chi) { jb = nb.j[base + clo + lane]; wb = nb.shift[base + clo + lane]; }
+    if (clo + kWave + lane < chi) { jc = nb.j[base + clo + kWave + lane]; wc = nb.shift[base + clo + kWave + lane]; }
+    double4 rb = rw4[jb];
     for (int p0 = clo; p0 < chi; p0 += kWave) {
       const int p = p0 + lane;
       const bool act = p < chi;
-      int32_t j = (int32_t)i, w = 0;
-      if (act) { j = nb.j[base + p]; w = nb.shift[base + p]; }
+      const int32_t w = wb;
+      const double rjx = rb.x, rjy = rb.y, rjz = rb.z;
+      rb = rw4[jc];
+      wb = wc;
+      jc = ii;
+      wc = 0;
+      if (p + 2 * kWave < chi) { jc = nb.j[base + p + 2 * kWave]; wc = nb.shift[base + p + 2 * kWave]; }
       double shx = 0.0, shy = 0.0, shz = 0.0;
       if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
-      const double4 rj = rw4[j];
-      const double dx = (rj.x - rix) + shx;
-      const double dy = (rj.y - riy) + shy;
-      const double dz = (rj.z - riz) + shz;
+      const double dx = (rjx - rix) + shx;
+      const double dy = (rjy - riy) + shy;
+      const double dz = (rjz - riz) + shz;
       const double q = (dx * dx + dy * dy) + dz * dz;
       const T xv = (T)dx, yv = (T)dy, zv = (T)dz, qv = (T)q;
       const int e = shift_species(w);
@@ -176,6 +186,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
         if (!(act && p < ends)) continue;
         const size_t roff = ((size_t)(s * E + e) * KB) * kCoefStride;
         const T *bc = bcoef + (size_t)s * NB;
+        // c_l = sum_k A e_k and c'_l = sum_k A (-gamma_k e_k)
         T cl[LMAX + 1], cp[LMAX + 1];
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) { cl[l] = (T)0; cp[l] = (T)0; }
@@ -184,12 +195,12 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
           if (k < K) {
             const size_t o = roff + k * kCoefStride;
             const T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
-            const T ng = LDS ? tabl[o + 6] : tabg[o + 6];
+            const T gk = (LDS ? tabl[o + 6] : tabg[o + 6]) * ek;
 #pragma unroll
             for (int l = 0; l <= LMAX; ++l) {
-              const T t = (LDS ? tabl[o + 1 + l] : tabg[o + 1 + l]) * ek;
-              cl[l] += t;
-              cp[l] = fma_(ng, t, cp[l]);
+              const T al = LDS ? tabl[o + 1 + l] : tabg[o + 1 + l];
+              cl[l] = fma_(al, ek, cl[l]);
+              cp[l] = fma_(al, gk, cp[l]);
             }
           }
         }
@@ -356,7 +367,7 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   GMP_LAUNCH("pack_positions", k_pack_rw_bwd, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, rw4);
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;
-  const size_t tsm = use_lds ? tab_bytes : 0;
+  const size_t tsm = (use_lds ? tab_bytes : 0) + 4 * (size_t)p->dev.S * coef_block(p->dev.lmax) * (f64 ? 8 : 4);
   const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
   PairsFn fn = f64 ? (use_lds ? pick_pairs<true, true>(p->dev.lmax, p->dev.kb)
                               : pick_pairs<true, false>(p->dev.lmax, p->dev.kb))

@@ -445,10 +445,11 @@ gmp_status check_nbrs(const gmp_plan *p, const gmp_batch *b, const gmp_neighbors
   if (!n) return set_error(GMP_E_INVALID, "null neighbour lists");
   if (n->capacity < 0) return set_error(GMP_E_INVALID, "negative capacity");
   if (n->max_list < 0) return set_error(GMP_E_INVALID, "negative max_list");
-  if (!n->offsets || !n->bucket_start || !n->sigma_end || !n->wrap || !n->rw)
+  if (!n->offsets) return set_error(GMP_E_INVALID, "null neighbour offsets");
+  if (b->n_atoms > 0 && (!n->bucket_start || !n->sigma_end || !n->wrap || !n->rw))
     return set_error(GMP_E_INVALID, "null neighbour arrays");
   if (need_lists && n->capacity > 0 && (!n->j || !n->shift)) return set_error(GMP_E_INVALID, "null j/shift");
-  (void)p; (void)b;
+  (void)p;
   return GMP_OK;
 }
 
@@ -581,6 +582,7 @@ gmp_status gmp_features(const gmp_plan *p, const gmp_batch *b, const gmp_neighbo
   if (st) return st;
   st = check_nbrs(p, b, n, true);
   if (st) return st;
+  if (b->n_atoms == 0) return GMP_OK;
   if (!features) return set_error(GMP_E_INVALID, "null features");
   if (!ws) return set_error(GMP_E_INVALID, "null workspace");
   hipStream_t s = (hipStream_t)stream;
@@ -606,6 +608,11 @@ gmp_status gmp_features_backward(const gmp_plan *p, const gmp_batch *b, const gm
   if (st) return st;
   st = check_nbrs(p, b, n, true);
   if (st) return st;
+  if (b->n_atoms == 0) {  // structures without atoms have a zero cell gradient
+    if (grad_cell && b->n_structs > 0)
+      fill_zero(grad_cell, (size_t)b->n_structs * 9 * sizeof(double), (hipStream_t)stream);
+    return GMP_OK;
+  }
   if (!components || !grad_features || !grad_pos) return set_error(GMP_E_INVALID, "null backward argument");
   if (!n->reverse) return set_error(GMP_E_INVALID, "backward needs the reverse-pair index");
   if (!ws) return set_error(GMP_E_INVALID, "null workspace");

@@ -1,0 +1,149 @@
+"""Edge cases of the HIP path through the C ABI: empty batches and empty
+structures, capacity overflow in the no-sync build, invalid inputs that the
+library must reject with a status code, and neighbour lists longer than the
+in-LDS sort."""
+import numpy as np
+import pytest
+
+import gmp_synth as gs
+import oracle
+from gpu_helpers import say, assert_features
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_12980_amd as g
+    g.load()
+    return g
+
+
+def _probes(seed=3, **kw):
+    return gs.small_probes(np.random.default_rng(seed), orders=(0, 1, 2, 3, 4), n_sigmas=3, n_elements=2,
+                           n_prims=(1, 3), tau=1e-9, **kw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_batch_without_atoms(g, precision):
+    say(f"[empty batch {precision}]")
+    p = _probes()
+    empty = gs.Batch(np.zeros(3, np.int64), np.zeros((0, 3)), np.zeros(0, np.int32),
+                     np.stack([np.eye(3) * 5.0, np.eye(3) * 6.0]), np.array([7, 0], np.uint8))
+    plan = g.GMPPlan.from_probes(p, precision)
+    db = g.DeviceBatch.from_batch(empty)
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    assert nb.n_pairs == 0
+    F, mu = g.features(plan, db, nb, ws)
+    assert tuple(F.shape) == (0, p.n_features)
+    gp, gc = g.features_backward(plan, db, nb, ws, mu, F, torch.zeros((0, p.n_features), device="cuda"))
+    torch.cuda.synchronize()
+    assert tuple(gp.shape) == (0, 3)
+    assert torch.equal(gc.cpu(), torch.zeros((2, 3, 3), dtype=torch.float64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_empty_structures_inside_a_batch(g, precision):
+    say(f"[empty structures inside a batch {precision}]")
+    rng = np.random.default_rng(8)
+    s1 = gs.small_periodic(rng, n_atoms=9, n_elements=2, density=0.06, dmin=1.3)
+    s2 = gs.small_cluster(rng, n_atoms=6, n_elements=2, radius=3.0)
+    none = (np.zeros((0, 3)), np.zeros(0, np.int32), np.eye(3) * 7.0, 7)
+    b = gs.make_batch([none, s1, none, s2, none])
+    p = _probes()
+    plan = g.GMPPlan.from_probes(p, precision)
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    F, mu = g.features(plan, db, nb, ws)
+    Fref = oracle.features_batch(b, p)
+    assert_features(F.cpu().numpy(), Fref, p.tau, 1e-11 if precision == "fp64" else 1e-5)
+    G = torch.as_tensor(rng.standard_normal((b.n_atoms, p.n_features)), device="cuda")
+    gp, gc = g.features_backward(plan, db, nb, ws, mu, F, G)
+    gc = gc.cpu().numpy()
+    for s in (0, 2, 4):
+        assert np.all(gc[s] == 0.0)
+
+
+def test_nosync_overflow_is_reported(g):
+    say("[no-sync capacity overflow]")
+    b, p = gs.config("C1")
+    plan = g.GMPPlan.from_probes(p, "fp32c")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    small = g.Neighbors(plan, db, nb.n_pairs // 2)
+    small.max_list = nb.max_list
+    g.rebuild_neighbors_nosync(plan, db, ws, small)
+    with pytest.raises(g.GMPError, match="CAPACITY"):
+        g.check_status(ws)
+    # the workspace status is cleared by the check: a fitting rebuild is clean again
+    g.rebuild_neighbors_nosync(plan, db, ws, nb)
+    g.check_status(ws)
+
+
+def test_two_call_capacity_pattern(g):
+    say("[two-call capacity]")
+    b, p = gs.config("C1")
+    plan = g.GMPPlan.from_probes(p, "fp64")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws, capacity=16)
+    ref = g.build_neighbors(plan, db, ws)
+    assert nb.capacity >= nb.n_pairs == ref.n_pairs
+    assert torch.equal(nb.j[:nb.n_pairs], ref.j[:ref.n_pairs])
+
+
+def test_species_out_of_range_is_rejected(g):
+    say("[species out of range]")
+    rng = np.random.default_rng(4)
+    pos, spec, cell, pbc = gs.small_periodic(rng, n_atoms=6, n_elements=2, density=0.06, dmin=1.3)
+    spec = spec.copy()
+    spec[2] = 5
+    b = gs.make_batch([(pos, spec, cell, pbc)])
+    plan = g.GMPPlan.from_probes(_probes(), "fp32c")
+    with pytest.raises(g.GMPError, match="INVALID"):
+        g.build_neighbors(plan, g.DeviceBatch.from_batch(b), g.Workspace())
+
+
+def test_nonfinite_position_is_rejected(g):
+    say("[non-finite position]")
+    rng = np.random.default_rng(5)
+    pos, spec, cell, pbc = gs.small_periodic(rng, n_atoms=6, n_elements=2, density=0.06, dmin=1.3)
+    pos = pos.copy()
+    pos[3, 1] = np.nan
+    b = gs.make_batch([(pos, spec, cell, pbc)])
+    plan = g.GMPPlan.from_probes(_probes(), "fp32c")
+    with pytest.raises(g.GMPError, match="NONFINITE"):
+        g.build_neighbors(plan, g.DeviceBatch.from_batch(b), g.Workspace())
+
+
+def test_singular_cell_is_rejected(g):
+    say("[singular cell]")
+    rng = np.random.default_rng(6)
+    pos, spec, cell, pbc = gs.small_periodic(rng, n_atoms=4, n_elements=2, density=0.06, dmin=1.3)
+    cell = np.array(cell, float).copy()
+    cell[2] = cell[0] + cell[1]
+    b = gs.make_batch([(pos, spec, cell, 7)])
+    plan = g.GMPPlan.from_probes(_probes(), "fp32c")
+    with pytest.raises(g.GMPError, match="CELL"):
+        g.build_neighbors(plan, g.DeviceBatch.from_batch(b), g.Workspace())
+
+
+def test_list_longer_than_the_sort_is_unsupported(g):
+    """One atom in a 1.8 A cubic cell with a ~26 A cutoff has ~12,000 images
+    inside the cutoff, more than one centre's in-LDS sort holds."""
+    say("[list longer than the in-LDS sort]")
+    p = gs.Probes(np.array([0], np.int32), np.array([3.0]), np.array([0, 1], np.int32), np.array([5.0]),
+                  np.array([0.3]), 1e-14)
+    rc = float(np.sqrt(oracle.cutoffs(p).max()))
+    assert 24.0 < rc < 30.0
+    b = gs.make_batch([(np.zeros((1, 3)), np.zeros(1, np.int32), np.eye(3) * 1.8, 7)])
+    plan = g.GMPPlan.from_probes(p, "fp64")
+    with pytest.raises(g.GMPError, match="UNSUPPORTED"):
+        g.build_neighbors(plan, g.DeviceBatch.from_batch(b), g.Workspace())
