@@ -133,6 +133,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
     if (item >= n_items) break;
     const int64_t i = item / C;
     const int c = (int)(item - i * C);
+    if (nb.offsets[i + 1] > nb.capacity) continue;  // list not written (overflowed no-sync build)
     {
       const T *src = (const T *)bcoef_ + (size_t)i * S * NB;
       for (int t = lane; t < S * NB; t += kWave) bcoef[t] = src[t];
@@ -253,7 +254,9 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BatchDev bt, NbrDev nb, cons
   const int64_t a = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int64_t N = bt.n_atoms;
   if (a >= N) return;
-  const int64_t base = nb.offsets[a], end = nb.offsets[a + 1];
+  const int64_t base = nb.offsets[a];
+  // a list that ends past the capacity was not written (overflowed no-sync build)
+  const int64_t end = nb.offsets[a + 1] > nb.capacity ? base : nb.offsets[a + 1];
   const int ma0 = nb.wrap[3 * a], ma1 = nb.wrap[3 * a + 1], ma2 = nb.wrap[3 * a + 2];
   double g[3] = {0.0, 0.0, 0.0};
   double cp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BatchDev bt, NbrDev nb, cons
     const int32_t w = nb.shift[p];
     const int32_t rv = nb.reverse[p];
     // a missing mirror is flagged by the neighbour build; never for a consistent list
-    if (rv < 0 || (int64_t)rv >= nb.offsets[j + 1] - nb.offsets[j]) continue;
+    if (rv < 0 || (int64_t)rv >= nb.offsets[j + 1] - nb.offsets[j] || nb.offsets[j + 1] > nb.capacity) continue;
     const T *va = vbuf + (size_t)p * 4;
     const T *vr = vbuf + (size_t)(nb.offsets[j] + rv) * 4;
     const double v0 = (double)va[0], v1 = (double)va[1], v2 = (double)va[2];

@@ -437,7 +437,23 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   __syncthreads();
   for (int b = tid; b <= nbk; b += blockDim.x) nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
   for (int s = tid; s < P.S; s += blockDim.x) nb.sigma_end[i * P.S + s] = bstart[(P.rank_lt[s] + 1) * P.E];
-  if (overflow || too_big) return;
+  if (overflow) return;  // consumers skip centres whose list ends past the capacity
+  if (too_big) {
+    // the list does not fit the in-LDS sort: leave in-range placeholder
+    // entries (the centre itself, no shift) so no consumer reads outside
+    // its arrays; the status word reports the condition
+    int ei = bt.species[i];
+    ei = ei < 0 ? 0 : (ei >= P.E ? P.E - 1 : ei);
+    for (int64_t t = tid; t < total; t += blockDim.x) {
+      nb.j[base + t] = (int32_t)i;
+      nb.shift[base + t] = (int32_t)((uint32_t)ei << 24);
+      if (pair_key) {
+        pair_key[base + t] = make_key(i, 0, 0, 0);
+        pair_centre[base + t] = (int32_t)i;
+      }
+    }
+    return;
+  }
   for (int b = tid; b < nbk; b += blockDim.x) cursor[b] = bstart[b];
   __syncthreads();
   const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
@@ -493,6 +509,10 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
   const uint64_t kp = pair_key[p];
   const int64_t i = pair_centre[p];
   const int32_t j = (int32_t)(kp >> 24);
+  if (i < 0 || i >= N || j < 0 || (int64_t)j >= N) {  // never for lists the fill wrote
+    atomicOr(status, ST_INTERNAL);
+    return;
+  }
   const int n1 = (int)((kp >> 16) & 0xff) - 128, n2 = (int)((kp >> 8) & 0xff) - 128, n3 = (int)(kp & 0xff) - 128;
   const int lex = n1 != 0 ? n1 : (n2 != 0 ? n2 : n3);
   if (!((int64_t)j > i || ((int64_t)j == i && lex >= 0))) return;

@@ -46,7 +46,9 @@ __global__ void k_chunk_count(NbrDev nb, int64_t N, int kc, int64_t *nch) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int64_t cnt = nb.offsets[i + 1] - nb.offsets[i];
-  nch[i] = kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1;
+  // a list that ends past the capacity was not written (overflowed no-sync
+  // build, reported in the status word): no work items, zero moments
+  nch[i] = nb.offsets[i + 1] > nb.capacity ? 0 : (kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1);
 }
 
 // AoS copy of the wrapped positions: one 32-byte gather per neighbour.

@@ -80,11 +80,25 @@ def test_nosync_overflow_is_reported(g):
     small = g.Neighbors(plan, db, nb.n_pairs // 2)
     small.max_list = nb.max_list
     g.rebuild_neighbors_nosync(plan, db, ws, small)
+    # the forward and the adjoint still run on the overflowed lists: centres
+    # whose list fits are exact, the others read nothing and give zeros
+    small.n_pairs = small.capacity
+    F, mu = g.features(plan, db, small, ws)
+    gp, gc = g.features_backward(plan, db, small, ws, mu, F, torch.ones_like(F))
+    torch.cuda.synchronize()
     with pytest.raises(g.GMPError, match="CAPACITY"):
         g.check_status(ws)
     # the workspace status is cleared by the check: a fitting rebuild is clean again
     g.rebuild_neighbors_nosync(plan, db, ws, nb)
     g.check_status(ws)
+    Fref, _ = g.features(plan, db, nb, ws)
+    offs = small.offsets.cpu().numpy()
+    fits = offs[1:] <= small.capacity
+    assert fits.any() and not fits.all()
+    Fh, Fr = F.cpu().numpy(), Fref.cpu().numpy()
+    assert np.array_equal(Fh[fits], Fr[fits])
+    assert np.all(Fh[~fits] == 0.0)
+    assert torch.isfinite(gp).all() and torch.isfinite(gc).all()
 
 
 def test_two_call_capacity_pattern(g):
