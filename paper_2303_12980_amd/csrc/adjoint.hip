@@ -37,8 +37,10 @@ __host__ __device__ inline int coef_block(int lmax) { return nmono(lmax) + 3 * n
 
 // One wavefront per centre.
 template <bool F64>
-__global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, int64_t N, const double *components,
-                                                  const void *grad_features, void *bcoef) {
+__global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev nb, const double *components,
+                                                  const void *grad_features, void *bcoef, double4 *rw4,
+                                                  unsigned long long *counter) {
+  const int64_t N = bt.n_atoms;
   using T = typename Real<F64>::T;
   extern __shared__ double lds_b[];
   const int w = threadIdx.x / kWave, lane = lane_id();
@@ -47,6 +49,9 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, int64_t N, const do
   double *scale = lds_b + (size_t)w * (P.nf + S * NM);  // [nf]
   double *M = scale + P.nf;                               // [S][NM]
   const bool live = i < N;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0ull;  // work items of the pair kernel
+  // AoS wrapped position (one 32-byte gather per neighbour in the pair kernel)
+  if (live && lane == 0) rw4[i] = wrapped_position(bt, nb, i);
   const double *mu = components + (size_t)i * P.ncomp_total;
   if (live) {
     for (int t = lane; t < P.nf; t += kWave) {
@@ -336,13 +341,6 @@ template <bool F64, bool LDS> PairsFn pick_pairs(int lmax, int kb) {
   }
 }
 
-// AoS copy of the wrapped positions: one 32-byte gather per neighbour.
-__global__ void k_pack_rw_bwd(BatchDev bt, NbrDev nb, int64_t N, double4 *rw4) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  rw4[i] = wrapped_position(bt, nb, i);
-}
-
 }  // namespace
 
 size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms) {
@@ -360,14 +358,12 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   const int64_t blocks = (N + 3) / 4;
   size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
   if (f64)
-    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N, components,
-               grad_features, bcoef);
+    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, components,
+               grad_features, bcoef, rw4, counter);
   else
-    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N, components,
-               grad_features, bcoef);
+    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, components,
+               grad_features, bcoef, rw4, counter);
   const int64_t n_items = N * (int64_t)C;
-  fill_zero(counter, sizeof(unsigned long long), s);
-  GMP_LAUNCH("pack_positions", k_pack_rw_bwd, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, rw4);
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;
   const size_t tsm = (use_lds ? tab_bytes : 0) + 4 * (size_t)p->dev.S * coef_block(p->dev.lmax) * (f64 ? 8 : 4);

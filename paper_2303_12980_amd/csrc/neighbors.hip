@@ -450,6 +450,7 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       if (pair_key) {
         pair_key[base + t] = make_key(i, 0, 0, 0);
         pair_centre[base + t] = (int32_t)i;
+        nb.reverse[base + t] = -1;
       }
     }
     return;
@@ -487,9 +488,10 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       uint32_t n3 = (uint32_t)((k & 0xff) - 128) & 0xffu;
       nb.j[base + b0 + t] = jj;
       nb.shift[base + b0 + t] = (int32_t)(n1 | (n2 << 8) | (n3 << 16) | ((uint32_t)e << 24));
-      if (pair_key) {
+      if (pair_key) {  // inputs of the reverse-index kernel; the index starts unresolved
         pair_key[base + b0 + t] = k;
         pair_centre[base + b0 + t] = (int32_t)i;
+        nb.reverse[base + b0 + t] = -1;
       }
     }
   }
@@ -584,18 +586,9 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
              nb.reverse ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.status);
 }
 
-__global__ void k_fill_minus_one(int32_t *a, int64_t n) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) a[t] = -1;
-}
-
 void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,
                     hipStream_t s) {
-  {
-    int64_t b = (n_pairs + 255) / 256;
-    if (b > 8192) b = 8192;
-    if (b < 1) b = 1;
-    GMP_LAUNCH("nbr_reverse_init", k_fill_minus_one, dim3((unsigned)b), dim3(256), 0, s, nb.reverse, n_pairs);
-  }
+  // every entry of every written list was set to -1 (unresolved) by the fill
   const int64_t blocks = (n_pairs + 255) / 256;
   if (blocks > 0)
     GMP_LAUNCH("nbr_reverse", k_reverse, dim3((unsigned)blocks), dim3(256), 0, s, p->dev, bt, nb, L.pair_key,

@@ -42,19 +42,20 @@ __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c
 // Chunks of one centre's list: fixed-size pieces of kc pairs (kc = 0: whole
 // list), so the decomposition of a centre depends on its own list only and
 // a batched launch sums in the same order as a launch over one structure.
-__global__ void k_chunk_count(NbrDev nb, int64_t N, int kc, int64_t *nch) {
+// Per atom: the number of chunks of its list (fixed-size pieces of kc pairs,
+// kc = 0: whole list, so the decomposition of a centre depends on its own
+// list only and a batched launch sums in the same order as a launch over one
+// structure) and its wrapped position as an AoS double4 (one 32-byte gather
+// per neighbour).  The first thread also clears the work-item counter.
+__global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int64_t N, int kc, int64_t *nch, double4 *rw4,
+                               unsigned long long *counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *counter = 0ull;
   if (i >= N) return;
   const int64_t cnt = nb.offsets[i + 1] - nb.offsets[i];
   // a list that ends past the capacity was not written (overflowed no-sync
   // build, reported in the status word): no work items, zero moments
   nch[i] = nb.offsets[i + 1] > nb.capacity ? 0 : (kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1);
-}
-
-// AoS copy of the wrapped positions: one 32-byte gather per neighbour.
-__global__ void k_pack_rw(BatchDev bt, NbrDev nb, int64_t N, double4 *rw4) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
   rw4[i] = wrapped_position(bt, nb, i);
 }
 
@@ -417,10 +418,9 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
                     int64_t pairs_bound, hipStream_t s) {
   const int64_t N = bt.n_atoms;
   const int kc = chunk_size(p);
-  GMP_LAUNCH("overlap_chunks", k_chunk_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, nb, N, kc, nch);
-  GMP_LAUNCH("pack_positions", k_pack_rw, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, rw4);
+  GMP_LAUNCH("overlap_prep", k_overlap_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, kc, nch,
+             rw4, counter);
   scan_i64(nch, chunk_off, N, scan_aux, s);
-  fill_zero(counter, sizeof(unsigned long long), s);
   const bool f64 = p->prec == GMP_FP64;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;
