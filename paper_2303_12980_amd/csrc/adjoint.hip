@@ -32,8 +32,13 @@ __device__ inline float fma_(float a, float b, float c) { return fmaf(a, b, c); 
 __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c); }
 
 
-// coefficient block per (centre, sigma): M [nmono(L)], then Dx, Dy, Dz [nmono(L-1)] each
-__host__ __device__ inline int coef_block(int lmax) { return nmono(lmax) + 3 * nmono(lmax - 1); }
+// coefficient block per (centre, sigma): M [nmono(L)], then Dx, Dy, Dz
+// [nmono(L-1)] each; every part starts on a multiple of 4 entries so the
+// pair kernel's wavefront-uniform LDS reads can be 16-byte vector reads
+__host__ __device__ constexpr int round4(int n) { return (n + 3) & ~3; }
+__host__ __device__ constexpr int coef_m(int lmax) { return round4(nmono(lmax)); }
+__host__ __device__ constexpr int coef_d(int lmax) { return round4(nmono(lmax - 1)); }
+__host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax) + 3 * coef_d(lmax); }
 
 // One wavefront per centre.
 template <bool F64>
@@ -46,6 +51,7 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
   const int S = P.S, NM = nmono(P.lmax), NM1 = nmono(P.lmax - 1), NB = coef_block(P.lmax);
+  const int NMP = coef_m(P.lmax), NDP = coef_d(P.lmax);
   double *scale = lds_b + (size_t)w * (P.nf + S * NM);  // [nf]
   double *M = scale + P.nf;                               // [S][NM]
   const bool live = i < N;
@@ -88,11 +94,11 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
     T *out = (T *)bcoef + (size_t)i * S * NB;
     for (int t = lane; t < S * NB; t += kWave) {
       const int s = t / NB, r = t - s * NB;
-      double v;
-      if (r < NM) {
-        v = M[s * NM + r];
-      } else {
-        const int ax = (r - NM) / NM1, m1 = (r - NM) - ax * NM1;  // derivative axis and lower monomial
+      double v = 0.0;
+      if (r < NMP) {
+        if (r < NM) v = M[s * NM + r];
+      } else if (NDP > 0 && (r - NMP) % NDP < NM1) {
+        const int ax = (r - NMP) / NDP, m1 = (r - NMP) - ax * NDP;  // derivative axis and lower monomial
         const int d1 = kMT.deg[m1];
         int a = kMT.ea[m1], b = kMT.eb[m1], c = kMT.ec[m1];
         double f;
@@ -117,9 +123,9 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
                                                    const void *bcoef_, void *vbuf_, int C, int64_t n_items,
                                                    unsigned long long *counter, const void *tab_global) {
   using T = typename Real<F64>::T;
-  constexpr int NM = nmono(LMAX), NM1 = nmono(LMAX - 1);
-  constexpr int NB = NM + 3 * NM1;
-  extern __shared__ double lds_dyn[];
+  constexpr int NM = nmono(LMAX);
+  constexpr int NMP = coef_m(LMAX), NDP = coef_d(LMAX), NB = coef_block(LMAX);
+  extern __shared__ __align__(16) double lds_dyn[];
   __shared__ int lds_k[kMaxElements];
   const int S = P.S, E = P.E;
   const T *__restrict__ tabg = (const T *)tab_global;
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
         const int ends = __builtin_amdgcn_readlane(end_lane, s);
         if (!(act && p < ends)) continue;
         const size_t roff = ((size_t)(s * E + e) * KB) * kCoefStride;
-        const T *bc = bcoef + (size_t)s * NB;
+        const T *bc = (const T *)__builtin_assume_aligned(bcoef + (size_t)s * NB, 16);
         // c_l = sum_k A e_k and c'_l = sum_k A (-gamma_k e_k)
         T cl[LMAX + 1], cp[LMAX + 1];
 #pragma unroll
@@ -223,9 +229,9 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
 #pragma unroll
             for (int mm = 0; mm < ncomp(l - 1); ++mm) {
               const T mv = mono[doff(l - 1) + mm];
-              gx = fma_(bc[NM + doff(l - 1) + mm], mv, gx);
-              gy = fma_(bc[NM + NM1 + doff(l - 1) + mm], mv, gy);
-              gz = fma_(bc[NM + 2 * NM1 + doff(l - 1) + mm], mv, gz);
+              gx = fma_(bc[NMP + doff(l - 1) + mm], mv, gx);
+              gy = fma_(bc[NMP + NDP + doff(l - 1) + mm], mv, gy);
+              gz = fma_(bc[NMP + 2 * NDP + doff(l - 1) + mm], mv, gz);
             }
             Bx = fma_(cl[l], gx, Bx);
             By = fma_(cl[l], gy, By);
