@@ -400,8 +400,12 @@ __device__ void wave_sort(uint64_t *a, int n) {
   }
 }
 
-__device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3) {
-  return ((uint64_t)j << 24) | ((uint64_t)(n1 + 128) << 16) | ((uint64_t)(n2 + 128) << 8) | (uint64_t)(n3 + 128);
+// Sort key of a pair inside one bucket: (j, n) with the bucket's shell in the
+// top bits (constant within a bucket, so the order is that of (j, n)); the
+// reverse-index search reads the shell from it.
+__device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3, int shell = 0) {
+  return ((uint64_t)shell << 60) | ((uint64_t)j << 24) | ((uint64_t)(n1 + 128) << 16) |
+         ((uint64_t)(n2 + 128) << 8) | (uint64_t)(n3 + 128);
 }
 
 // One workgroup per centre (centres in cell-list order): fill its buckets
@@ -468,9 +472,10 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
                        const double dz = (sz[t] - riz) + shz;
                        const double q = (dx * dx + dy * dy) + dz * dz;
                        if (q <= P.rcmax2) {
-                         const int bk = shell_of(P, q) * P.E + ssp[t];
+                         const int sh = shell_of(P, q);
+                         const int bk = sh * P.E + ssp[t];
                          const int pos = atomicAdd(&cursor[bk], 1);
-                         if (pos < bstart[bk + 1]) keys[pos] = make_key(sid[t], n[0], n[1], n[2]);
+                         if (pos < bstart[bk + 1]) keys[pos] = make_key(sid[t], n[0], n[1], n[2], sh);
                          else atomicOr(status, ST_INTERNAL);
                        }
                      });
@@ -482,7 +487,7 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
     const int e = b % P.E;
     for (int t = lane; t < bn; t += kWave) {
       uint64_t k = keys[b0 + t];
-      int32_t jj = (int32_t)(k >> 24);
+      int32_t jj = (int32_t)((k >> 24) & 0x7fffffffull);
       uint32_t n1 = (uint32_t)(((k >> 16) & 0xff) - 128) & 0xffu;
       uint32_t n2 = (uint32_t)(((k >> 8) & 0xff) - 128) & 0xffu;
       uint32_t n3 = (uint32_t)((k & 0xff) - 128) & 0xffu;
@@ -500,7 +505,8 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
 // Reverse index: pair (i, j, n) and its mirror (j, i, -n).  One thread per
 // pair; only the owner of each mirror couple -- i < j, or i == j with n >= 0
 // lexicographically -- searches its mirror (binary search over the packed
-// keys of j's bucket (shell of q, species of i)) and writes both entries.
+// keys of j's bucket (shell, species of i); the mirror has the same q, so
+// the shell stored in the pair's key) and writes both entries.
 __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev nb, const uint64_t *pair_key,
                                                  const int32_t *pair_centre, int64_t n_pairs, uint32_t *status) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -510,28 +516,21 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
   const int nbk = P.E * P.S;
   const uint64_t kp = pair_key[p];
   const int64_t i = pair_centre[p];
-  const int32_t j = (int32_t)(kp >> 24);
-  if (i < 0 || i >= N || j < 0 || (int64_t)j >= N) {  // never for lists the fill wrote
+  const int32_t j = (int32_t)((kp >> 24) & 0x7fffffffull);
+  const int h = (int)(kp >> 60);
+  if (i < 0 || i >= N || (int64_t)j >= N || h >= P.S) {  // never for lists the fill wrote
     atomicOr(status, ST_INTERNAL);
     return;
   }
   const int n1 = (int)((kp >> 16) & 0xff) - 128, n2 = (int)((kp >> 8) & 0xff) - 128, n3 = (int)(kp & 0xff) - 128;
   const int lex = n1 != 0 ? n1 : (n2 != 0 ? n2 : n3);
   if (!((int64_t)j > i || ((int64_t)j == i && lex >= 0))) return;
-  const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
-  const int pbc = bt.pbc[s] & 7;
-  double shx = 0.0, shy = 0.0, shz = 0.0;
-  if (pbc) image_shift(bt.cell + 9 * (int64_t)s, n1, n2, n3, shx, shy, shz);
-  const double dx = (nb.rw[j] - nb.rw[i]) + shx;
-  const double dy = (nb.rw[N + j] - nb.rw[N + i]) + shy;
-  const double dz = (nb.rw[2 * N + j] - nb.rw[2 * N + i]) + shz;
-  const double q = (dx * dx + dy * dy) + dz * dz;
   int ei = bt.species[i];
   ei = ei < 0 ? 0 : (ei >= P.E ? P.E - 1 : ei);
-  const int b = shell_of(P, q) * P.E + ei;
+  const int b = h * P.E + ei;  // the mirror has the same q, hence the same shell
   const int32_t *bs = nb.bucket_start + (int64_t)j * (nbk + 1);
   int lo = bs[b], hi = bs[b + 1];
-  const uint64_t key = make_key(i, -n1, -n2, -n3);
+  const uint64_t key = make_key(i, -n1, -n2, -n3, h);
   const int64_t jb = nb.offsets[j];
   int found = -1;
   while (lo < hi) {
