@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--sample-centres", type=int, default=48)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
+    ap.add_argument("--no-others", action="store_true", help="skip the other workloads (512 structures, 1e5 atoms)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
@@ -83,6 +84,42 @@ def _median_ms(fn, reps, torch):
         torch.cuda.synchronize()
         ts.append((time.perf_counter() - t) * 1e3)
     return float(np.median(ts))
+
+
+def other_workloads(g, gs, torch, steps=5, warmup=2):
+    """Graph-replayed fwd+bwd step (FP32 compensated, neighbour build
+    included) on the differentiation workload (512 periodic triclinic
+    structures of 32-200 atoms, l=0..3 x 6 sigma) and on the large single
+    system (100,000 atoms in a 102.8 A cubic cell, l=0..4 x 10 sigma)."""
+    out = {}
+    for name, label in (("C4", "512 periodic triclinic structures, 32-200 atoms, 4 elements, l=0..3 x 6 sigma"),
+                        ("C5", "periodic 102.8 A cubic cell, 100000 atoms, 6 elements, l=0..4 x 10 sigma")):
+        t0 = time.time()
+        batch, probes = gs.config(name)
+        gen_s = time.time() - t0
+        db = g.DeviceBatch.from_batch(batch)
+        plan = g.GMPPlan.from_probes(probes, "fp32c")
+        ws = g.Workspace()
+        nb = g.build_neighbors(plan, db, ws)
+        G = torch.as_tensor(np.random.default_rng(7).standard_normal((batch.n_atoms, probes.n_features)),
+                            device="cuda")
+        fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
+        fo = g.CapturedStep(plan, db, ws, nb, backward=False)
+        for _ in range(warmup):
+            fb.replay()
+            fo.replay()
+        t_fb = _median_ms(fb.replay, steps, torch)
+        t_fo = _median_ms(fo.replay, steps, torch)
+        g.check_status(ws)
+        af = batch.n_atoms * probes.n_features
+        out[name] = {"workload": label, "atoms": batch.n_atoms, "features_per_atom": probes.n_features,
+                     "pairs": int(nb.n_pairs), "fwd_bwd_ms": t_fb, "fwd_ms": t_fo,
+                     "atoms_features_per_s_fwd_bwd": af / (t_fb * 1e-3), "atoms_features_per_s_fwd": af / (t_fo * 1e-3)}
+        print(f"[bench] {name}: {batch.n_atoms} atoms, {nb.n_pairs} pairs (generated in {gen_s:.1f}s): "
+              f"fwd+bwd {t_fb:.2f} ms, fwd {t_fo:.2f} ms", file=sys.stderr, flush=True)
+        del fb, fo, nb, ws, db, G
+        torch.cuda.empty_cache()
+    return out
 
 
 def batched_vs_per_structure(g, gs, torch):
@@ -348,6 +385,8 @@ def main():
         del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()
         out["batched"] = batched_vs_per_structure(g, gs, torch)
+    if not args.no_others:
+        out["other_workloads"] = other_workloads(g, gs, torch)
     print(json.dumps(out))
 
 

@@ -44,7 +44,7 @@ __host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax) + 3
 template <bool F64>
 __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev nb, const double *components,
                                                   const void *grad_features, void *bcoef, double4 *rw4,
-                                                  unsigned long long *counter) {
+                                                  int32_t *astruct, unsigned long long *counter) {
   const int64_t N = bt.n_atoms;
   using T = typename Real<F64>::T;
   extern __shared__ double lds_b[];
@@ -57,7 +57,11 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   const bool live = i < N;
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0ull;  // work items of the pair kernel
   // AoS wrapped position (one 32-byte gather per neighbour in the pair kernel)
-  if (live && lane == 0) rw4[i] = wrapped_position(bt, nb, i);
+  if (live && lane == 0) {
+    const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+    astruct[i] = st;
+    rw4[i] = wrapped_position(bt, nb, i, st);
+  }
   const double *mu = components + (size_t)i * P.ncomp_total;
   if (live) {
     for (int t = lane; t < P.nf; t += kWave) {
@@ -120,7 +124,8 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
 // ahead.  Dynamic LDS: [coefficient table if staged][4 wavefronts][S * NB].
 template <int LMAX, int KB, bool F64, bool LDS>
 __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
-                                                   const void *bcoef_, void *vbuf_, int C, int64_t n_items,
+                                                   const int32_t *astruct, const void *bcoef_, void *vbuf_, int C,
+                                                   int64_t n_items,
                                                    unsigned long long *counter, const void *tab_global) {
   using T = typename Real<F64>::T;
   constexpr int NM = nmono(LMAX);
@@ -150,7 +155,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
       for (int t = lane; t < S * NB; t += kWave) bcoef[t] = src[t];
       wave_lds_sync();
     }
-    const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+    const int st = astruct[i];
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
     const double4 ri4 = rw4[i];
@@ -330,8 +335,8 @@ __global__ __launch_bounds__(256) void k_cell_reduce(BatchDev bt, const double *
   }
 }
 
-using PairsFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const void *, void *, int, int64_t,
-                         unsigned long long *, const void *);
+using PairsFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const int32_t *, const void *, void *, int,
+                         int64_t, unsigned long long *, const void *);
 template <int L, bool F64, bool LDS> PairsFn pick_kb(int kb) {
   if (kb <= 4) return k_bwd_pairs<L, 4, F64, LDS>;
   if (kb <= 8) return k_bwd_pairs<L, 8, F64, LDS>;
@@ -357,7 +362,8 @@ int persistent_blocks(const void *fn, size_t smem, int blocks_per_cu);
 
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
-                     double *grad_cell, unsigned long long *counter, double4 *rw4, int C, hipStream_t s) {
+                     double *grad_cell, unsigned long long *counter, double4 *rw4, int32_t *astruct, int C,
+                     hipStream_t s) {
   const int64_t N = bt.n_atoms;
   if (N == 0) return;
   const bool f64 = p->prec == GMP_FP64;
@@ -365,10 +371,10 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
   if (f64)
     GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, components,
-               grad_features, bcoef, rw4, counter);
+               grad_features, bcoef, rw4, astruct, counter);
   else
     GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, components,
-               grad_features, bcoef, rw4, counter);
+               grad_features, bcoef, rw4, astruct, counter);
   const int64_t n_items = N * (int64_t)C;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;
@@ -381,8 +387,8 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   int64_t pb = persistent_blocks((const void *)fn, tsm, p->tuning.blocks_per_cu);
   if (pb > (n_items + 3) / 4) pb = (n_items + 3) / 4;
   if (pb < 1) pb = 1;
-  GMP_LAUNCH("adj_pairs", fn, dim3((unsigned)pb), dim3(256), tsm, s, p->dev, bt, nb, (const double4 *)rw4, bcoef, vbuf,
-             C, n_items, counter, tab);
+  GMP_LAUNCH("adj_pairs", fn, dim3((unsigned)pb), dim3(256), tsm, s, p->dev, bt, nb, (const double4 *)rw4,
+             (const int32_t *)astruct, bcoef, vbuf, C, n_items, counter, tab);
   if (f64)
     GMP_LAUNCH("adj_gather", k_bwd_gather<true>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
                cellpart);

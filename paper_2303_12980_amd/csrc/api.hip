@@ -24,13 +24,14 @@ void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, con
 int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs);
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
                     int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
-                    int64_t pairs_bound, hipStream_t s);
+                    int32_t *astruct, int64_t pairs_bound, hipStream_t s);
 void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off, void *features,
                    double *components, hipStream_t s);
 size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms);
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
-                     double *grad_cell, unsigned long long *counter, double4 *rw4, int C, hipStream_t s);
+                     double *grad_cell, unsigned long long *counter, double4 *rw4, int32_t *astruct, int C,
+                     hipStream_t s);
 void fill_zero3(void *p0, size_t b0, void *p1, size_t b1, void *p2, size_t b2, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
@@ -98,6 +99,7 @@ WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t capacity, vo
   L.status = c.take<uint32_t>(64);
   L.sinfo = c.take<StructInfo>((size_t)n_structs);
   L.bin_of = c.take<int32_t>(N);
+  L.astruct = c.take<int32_t>(N);
   L.bin_count = c.take<int32_t>(NB);
   L.bin_fill = c.take<int32_t>(NB);
   L.bin_start = c.take<int64_t>(NB + 1);
@@ -593,7 +595,7 @@ gmp_status gmp_features(const gmp_plan *p, const gmp_batch *b, const gmp_neighbo
   BatchDev bt = to_dev(b);
   NbrDev nb = to_dev(n);
   const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
-  launch_overlap(p, bt, nb, L.partial, L.nch, L.chunk_off, L.scan_aux, L.counter, L.rw4, pairs, s);
+  launch_overlap(p, bt, nb, L.partial, L.nch, L.chunk_off, L.scan_aux, L.counter, L.rw4, L.astruct, pairs, s);
   launch_finish(p, N, L.partial, L.chunk_off, features, components, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "feature kernels");
@@ -631,7 +633,7 @@ gmp_status gmp_features_backward(const gmp_plan *p, const gmp_batch *b, const gm
   int64_t C = want < by_pairs ? want : by_pairs;
   if (C < 1) C = 1;
   launch_backward(p, bt, nb, components, grad_features, L.bcoef, L.vbuf, L.cellpart, grad_pos, grad_cell,
-                  L.counter, L.rw4, (int)C, s);
+                  L.counter, L.rw4, L.astruct, (int)C, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "adjoint kernels");
   return GMP_OK;

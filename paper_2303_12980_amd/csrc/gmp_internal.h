@@ -183,8 +183,7 @@ __device__ inline void image_shift(const Cell9 &c, int n1, int n2, int n3, doubl
 // Wrapped position Rw_i = R_i - ((m1 a1 + m2 a2) + m3 a3) from the current
 // positions and lattice and the wrap indices of the neighbour build; the
 // same operation order as the build, so unchanged inputs give the same bits.
-__device__ inline double4 wrapped_position(const BatchDev &bt, const NbrDev &nb, int64_t i) {
-  const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+__device__ inline double4 wrapped_position(const BatchDev &bt, const NbrDev &nb, int64_t i, int s) {
   double r[3] = {bt.x[i], bt.y[i], bt.z[i]};
   if (bt.pbc[s] & 7) {
     const double *a = bt.cell + 9 * (int64_t)s;
@@ -241,6 +240,7 @@ struct WsLayout {
   uint32_t *status;       // [64] words: [0] flags, [2..3] total pairs, [4] max count
   StructInfo *sinfo;
   int32_t *bin_of;
+  int32_t *astruct;       // [N] structure of every atom (written by the per-atom kernel of each stage)
   int32_t *bin_count;
   int64_t *bin_start;
   int32_t *bin_fill;

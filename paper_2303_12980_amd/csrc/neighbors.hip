@@ -107,7 +107,7 @@ __global__ void k_struct_setup(BatchDev bt, StructInfo *info, double rcmax, int 
 }
 
 __global__ void k_wrap(BatchDev bt, const StructInfo *info, NbrDev nb, double *fw, int32_t *bin_of,
-                       int32_t *bin_count, int n_elements, uint32_t *status) {
+                       int32_t *bin_count, int32_t *astruct, int n_elements, uint32_t *status) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= bt.n_atoms) return;
   {
@@ -116,6 +116,7 @@ __global__ void k_wrap(BatchDev bt, const StructInfo *info, NbrDev nb, double *f
   }
   const int64_t N = bt.n_atoms;
   const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  astruct[i] = s;
   const StructInfo &I = info[s];
   const double R[3] = {bt.x[i], bt.y[i], bt.z[i]};
   if (!(isfinite(R[0]) && isfinite(R[1]) && isfinite(R[2]))) atomicOr(status, ST_NONFINITE);
@@ -315,8 +316,8 @@ __device__ inline int64_t xcd_contiguous(int64_t b, int64_t nblk) {
 __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                                const double *fw, const int64_t *bin_start,
                                                const double *sx, const double *sy, const double *sz,
-                                               const int32_t *sid, const int32_t *ssp, int32_t *cnt,
-                                               int64_t *ptotal, uint32_t *status) {
+                                               const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
+                                               int32_t *cnt, int64_t *ptotal, uint32_t *status) {
   extern __shared__ int32_t lds_cnt[];
   __shared__ CandLds lds_cand[4];
   __shared__ int64_t lds_tot[4];
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
   const int64_t i = sid[xcd_contiguous(blockIdx.x, gridDim.x)];
   for (int t = threadIdx.x; t < nbk; t += blockDim.x) c[t] = 0;
   __syncthreads();
-  const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  const int s = astruct[i];
   Cand C;
   cand_setup(C, info, bt, s, fw, i);
   const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
@@ -414,9 +415,9 @@ __device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3, int shell
 __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                               const double *fw, const int64_t *bin_start,
                                               const double *sx, const double *sy, const double *sz,
-                                              const int32_t *sid, const int32_t *ssp, const int32_t *cnt,
-                                              int lds_keys, uint64_t *pair_key, int32_t *pair_centre,
-                                              uint32_t *status) {
+                                              const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
+                                              const int32_t *cnt, int lds_keys, uint64_t *pair_key,
+                                              int32_t *pair_centre, uint32_t *status) {
   extern __shared__ uint64_t lds_u64[];
   __shared__ CandLds lds_cand[4];
   const int nbk = P.E * P.S;
@@ -430,13 +431,26 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   const int64_t total = nb.offsets[i + 1] - base;
   const bool overflow = nb.offsets[i + 1] > nb.capacity;
   const bool too_big = total > lds_keys;
-  if (tid == 0) {
-    int32_t acc = 0;
-    for (int b = 0; b < nbk; ++b) { bstart[b] = acc; acc += cnt[i * nbk + b]; }
-    bstart[nbk] = acc;
-    if (overflow) atomicOr(status, ST_OVERFLOW);
-    if (too_big) atomicOr(status, ST_SORT_SIZE);
-    if ((int64_t)acc != total) atomicOr(status, ST_INTERNAL);
+  if (w == 0) {  // bucket starts: exclusive scan of the centre's bucket counts
+    int32_t carry = 0;
+    for (int b0 = 0; b0 < nbk; b0 += kWave) {
+      const int b = b0 + lane;
+      const int32_t v = b < nbk ? cnt[i * nbk + b] : 0;
+      int32_t incl = v;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+      }
+      if (b < nbk) bstart[b] = carry + incl - v;
+      carry += __shfl(incl, kWave - 1, kWave);
+    }
+    if (lane == 0) {
+      bstart[nbk] = carry;
+      if (overflow) atomicOr(status, ST_OVERFLOW);
+      if (too_big) atomicOr(status, ST_SORT_SIZE);
+      if ((int64_t)carry != total) atomicOr(status, ST_INTERNAL);
+    }
   }
   __syncthreads();
   for (int b = tid; b <= nbk; b += blockDim.x) nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
@@ -461,7 +475,7 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   }
   for (int b = tid; b < nbk; b += blockDim.x) cursor[b] = bstart[b];
   __syncthreads();
-  const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  const int s = astruct[i];
   Cand C;
   cand_setup(C, info, bt, s, fw, i);
   const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
@@ -560,7 +574,7 @@ void launch_struct_setup(const gmp_plan *p, const BatchDev &bt, const WsLayout &
 void launch_wrap(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_elements, hipStream_t s) {
   int64_t blocks = (bt.n_atoms + 255) / 256;
   GMP_LAUNCH("nbr_wrap", k_wrap, dim3((unsigned)blocks), dim3(256), 0, s, bt, L.sinfo, nb, L.fw, L.bin_of,
-             L.bin_count, n_elements, L.status);
+             L.bin_count, L.astruct, n_elements, L.status);
 }
 
 void launch_scatter(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_elements, hipStream_t s) {
@@ -573,7 +587,7 @@ void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const
   int64_t blocks = bt.n_atoms;
   size_t smem = sizeof(int32_t) * p->dev.E * p->dev.S;
   GMP_LAUNCH("nbr_count", k_count, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo, L.fw,
-             L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.cnt, L.ptotal, L.status);
+             L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, L.ptotal, L.status);
 }
 
 void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int lds_keys,
@@ -581,7 +595,7 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
   int nbk = p->dev.E * p->dev.S;
   size_t smem = sizeof(uint64_t) * lds_keys + sizeof(int32_t) * (2 * nbk + 2);
   GMP_LAUNCH("nbr_fill_sort", k_fill, dim3((unsigned)bt.n_atoms), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
-             L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.cnt, lds_keys,
+             L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, lds_keys,
              nb.reverse ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.status);
 }
 

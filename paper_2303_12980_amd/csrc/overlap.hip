@@ -45,10 +45,11 @@ __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c
 // Per atom: the number of chunks of its list (fixed-size pieces of kc pairs,
 // kc = 0: whole list, so the decomposition of a centre depends on its own
 // list only and a batched launch sums in the same order as a launch over one
-// structure) and its wrapped position as an AoS double4 (one 32-byte gather
-// per neighbour).  The first thread also clears the work-item counter.
+// structure), its structure, and its wrapped position as an AoS double4 (one
+// 32-byte gather per neighbour).  The first thread also clears the work-item
+// counter.
 __global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int64_t N, int kc, int64_t *nch, double4 *rw4,
-                               unsigned long long *counter) {
+                               int32_t *astruct, unsigned long long *counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *counter = 0ull;
   if (i >= N) return;
@@ -56,7 +57,9 @@ __global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int64_t N, int kc, int64_
   // a list that ends past the capacity was not written (overflowed no-sync
   // build, reported in the status word): no work items, zero moments
   nch[i] = nb.offsets[i + 1] > nb.capacity ? 0 : (kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1);
-  rw4[i] = wrapped_position(bt, nb, i);
+  const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  astruct[i] = st;
+  rw4[i] = wrapped_position(bt, nb, i, st);
 }
 
 __device__ inline int64_t centre_of_chunk(const int64_t *chunk_off, int64_t N, int64_t q) {
@@ -143,8 +146,8 @@ template <int MODE, int NM> __device__ inline double acc_value(const Acc<MODE, N
 // the row of their own neighbour's species.
 template <int LMAX, int KB, int MODE, bool LDS>
 __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
-                                                 double *partial, const int64_t *chunk_off, int kc,
-                                                 unsigned long long *counter, const void *tab_global) {
+                                                 const int32_t *astruct, double *partial, const int64_t *chunk_off,
+                                                 int kc, unsigned long long *counter, const void *tab_global) {
   constexpr bool F64 = MODE == ACC_F64;
   using TR = typename std::conditional<F64, double, float>::type;                 // radial arithmetic
   using TM = typename std::conditional<MODE == ACC_TWOSUM, float, double>::type;  // monomials
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
     if (qc >= n_items) break;
     const int64_t i = centre_of_chunk(chunk_off, N, qc);
     const int c = (int)(qc - chunk_off[i]);
-    const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+    const int st = astruct[i];
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
     const double4 ri4 = rw4[i];
@@ -349,8 +352,8 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
   }
 }
 
-using OverlapFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, double *, const int64_t *, int,
-                           unsigned long long *, const void *);
+using OverlapFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const int32_t *, double *, const int64_t *,
+                           int, unsigned long long *, const void *);
 
 template <int L, int MODE, bool LDS> OverlapFn pick_k(int kb) {
   if (kb <= 4) return k_overlap<L, 4, MODE, LDS>;
@@ -415,11 +418,11 @@ int persistent_blocks(const void *fn, size_t smem, int blocks_per_cu) {
 
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
                     int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
-                    int64_t pairs_bound, hipStream_t s) {
+                    int32_t *astruct, int64_t pairs_bound, hipStream_t s) {
   const int64_t N = bt.n_atoms;
   const int kc = chunk_size(p);
   GMP_LAUNCH("overlap_prep", k_overlap_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, kc, nch,
-             rw4, counter);
+             rw4, astruct, counter);
   scan_i64(nch, chunk_off, N, scan_aux, s);
   const bool f64 = p->prec == GMP_FP64;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
@@ -432,8 +435,8 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
   const int64_t need = (items_bound + 3) / 4;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  GMP_LAUNCH("overlap", fn, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, (const double4 *)rw4, partial,
-             chunk_off, kc, counter, tab);
+  GMP_LAUNCH("overlap", fn, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, (const double4 *)rw4,
+             (const int32_t *)astruct, partial, chunk_off, kc, counter, tab);
 }
 
 void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off, void *features,
