@@ -104,7 +104,8 @@ def other_workloads(g, gs, torch, steps=5, warmup=2):
         G = torch.as_tensor(np.random.default_rng(7).standard_normal((batch.n_atoms, probes.n_features)),
                             device="cuda")
         fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
-        fo = g.CapturedStep(plan, db, ws, nb, backward=False)
+        nbf = g.build_neighbors(plan, db, ws, reverse=False)
+        fo = g.CapturedStep(plan, db, ws, nbf, backward=False)
         for _ in range(warmup):
             fb.replay()
             fo.replay()
@@ -117,7 +118,7 @@ def other_workloads(g, gs, torch, steps=5, warmup=2):
                      "atoms_features_per_s_fwd_bwd": af / (t_fb * 1e-3), "atoms_features_per_s_fwd": af / (t_fo * 1e-3)}
         print(f"[bench] {name}: {batch.n_atoms} atoms, {nb.n_pairs} pairs (generated in {gen_s:.1f}s): "
               f"fwd+bwd {t_fb:.2f} ms, fwd {t_fo:.2f} ms", file=sys.stderr, flush=True)
-        del fb, fo, nb, ws, db, G
+        del fb, fo, nb, nbf, ws, db, G
         torch.cuda.empty_cache()
     return out
 
@@ -266,7 +267,8 @@ def main():
         return plan, w, nb
 
     def eager_step(plan, w, nb, backward=True):
-        nb2 = g.build_neighbors(plan, db, w, out=nb)
+        # a forward-only step builds its lists without the reverse index
+        nb2 = g.build_neighbors(plan, db, w, reverse=backward, out=nb)
         F, mu = g.features(plan, db, nb2, w)
         if backward:
             g.features_backward(plan, db, nb2, w, mu, F, G)
@@ -285,21 +287,23 @@ def main():
     results, graphs = {}, {}
     for prec in (["fp32c", "fp32w"] + ([] if args.no_fp64 else ["fp64"])):
         plan, w, nb = make(prec)
+        nbf = g.build_neighbors(plan, db, w, reverse=False)
         r = {}
         r["eager_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True), args.steps, args.warmup)
-        r["eager_fwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, False), args.steps, args.warmup)
+        r["eager_fwd_ms"] = wall_ms(lambda: eager_step(plan, w, nbf, False), args.steps, args.warmup)
         fb = g.CapturedStep(plan, db, w, nb, backward=True, G=G)
         r["graph_fwd_bwd_ms"] = wall_ms(fb.replay, args.steps, args.warmup)
-        fo = g.CapturedStep(plan, db, w, nb, backward=False)
+        fo = g.CapturedStep(plan, db, w, nbf, backward=False)
         r["graph_fwd_ms"] = wall_ms(fo.replay, args.steps, args.warmup)
         g.check_status(w)
         results[prec] = r
-        graphs[prec] = (plan, w, nb, fb)
+        graphs[prec] = (plan, w, nb, fb, nbf)
         print(f"[bench] {prec}: graph fwd+bwd {r['graph_fwd_bwd_ms']:.3f} ms, fwd {r['graph_fwd_ms']:.3f} ms; "
               f"eager fwd+bwd {r['eager_fwd_bwd_ms']:.3f} ms", file=sys.stderr, flush=True)
 
     def kernel_profile(prec, backward, steps=5):
-        plan, w, nb, _ = graphs[prec]
+        plan, w, nb, _, nbf = graphs[prec]
+        nb = nb if backward else nbf
         eager_step(plan, w, nb, backward)
         torch.cuda.synchronize()
         with g.profile() as pr:
@@ -308,7 +312,7 @@ def main():
             torch.cuda.synchronize()
         return {k: dict(launches=v[0], avg_ms=v[1] / v[0], ms_per_step=v[1] / steps) for k, v in pr.result.items()}
 
-    plan32, _, nb32, step32 = graphs["fp32c"]
+    plan32, _, nb32, step32, _ = graphs["fp32c"]
     dt_fb = results["fp32c"]["graph_fwd_bwd_ms"] * 1e-3
     dt_f = results["fp32c"]["graph_fwd_ms"] * 1e-3
     # per-kernel averages (library HIP events around each launch, eager steps)
@@ -337,7 +341,7 @@ def main():
     Fref = oracle.features(batch.structure(0), probes, centres=cs)
     big = Fref > probes.tau
     acc = {"sampled_centres": int(len(cs)), "rule": "max |F-F_ref|/F_ref over F_ref > tau"}
-    for prec, (_, _, _, st) in graphs.items():
+    for prec, (_, _, _, st, _) in graphs.items():
         Fg = st.F.double().cpu().numpy()[cs]
         acc[f"{prec}_max_rel_err"] = float(np.max(np.abs(Fg[big] - Fref[big]) / Fref[big]))
 
