@@ -5,9 +5,10 @@ Candidates are timed with the HIP events the library records around its
 own launches on the current stream (neighbour build + forward, optionally
 the adjoint), the fastest is set on the plan, and the choice is cached in
 a JSON file keyed by the device, the precision, the probe shape (l_max,
-sigmas, species, primitive stride) and log2 buckets of the atom count and
-of the mean list length.  GMP_AUTOTUNE=0 disables the search (cached or
-default values are used); GMP_TUNE_CACHE sets the cache path.
+sigmas, species, largest primitive count per element) and log2 buckets of
+the atom count and of the mean list length.
+GMP_AUTOTUNE=0 disables the search (cached or default values are used);
+GMP_TUNE_CACHE sets the cache path.
 """
 from __future__ import annotations
 
@@ -24,7 +25,7 @@ from . import gmp as _g
 DEFAULT_CANDIDATES = [
     dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0)
     for c in (0, 512, 1024, 2048, 4096) for b in (2, 3, 4)
-]
+] + [dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=k) for k in (1, 2)]
 
 
 def _cache_path():
@@ -36,9 +37,13 @@ def _bucket(x: float) -> int:
 
 
 def tuning_key(plan, batch, nb) -> str:
+    """Device, precision, l_max, sigma count, species count, largest
+    primitive count per element, and log2 buckets of the atom count and of
+    the mean neighbour-list length."""
     dev = torch.cuda.get_device_name(batch.species.device)
     avg = nb.n_pairs / max(1, batch.n_atoms)
-    return (f"{dev}|{plan.precision}|L{int(max(plan.orders))}|S{len(plan.sigmas)}|E{plan.n_elements}"
+    kmax = int(max(int(b) - int(a) for a, b in zip(plan._poff[:-1], plan._poff[1:])))
+    return (f"{dev}|{plan.precision}|L{int(max(plan.orders))}|S{len(plan.sigmas)}|E{plan.n_elements}|K{kmax}"
             f"|N{_bucket(batch.n_atoms)}|avg{_bucket(avg)}")
 
 
