@@ -266,11 +266,23 @@ def main():
         nb = g.build_neighbors(plan, db, w)
         return plan, w, nb
 
-    def eager_step(plan, w, nb, backward=True):
-        # a forward-only step builds its lists without the reverse index
-        nb2 = g.build_neighbors(plan, db, w, reverse=backward, out=nb)
+    rev_stream = torch.cuda.Stream()
+    ev_built, ev_rev = torch.cuda.Event(), torch.cuda.Event()
+
+    def eager_step(plan, w, nb, backward=True, split=False):
+        # a forward-only step builds its lists without the reverse index; with
+        # split the reverse-pair search runs on a second stream beside the forward
+        nb2 = g.build_neighbors(plan, db, w, reverse=backward, out=nb, defer_reverse=split)
+        if split:
+            ev_built.record()
+            rev_stream.wait_event(ev_built)
+            with torch.cuda.stream(rev_stream):
+                g.build_reverse(plan, db, w, nb2)
+            ev_rev.record(rev_stream)
         F, mu = g.features(plan, db, nb2, w)
         if backward:
+            if split:
+                torch.cuda.current_stream().wait_event(ev_rev)
             g.features_backward(plan, db, nb2, w, mu, F, G)
         return F
 
@@ -291,6 +303,7 @@ def main():
         r = {}
         r["eager_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True), args.steps, args.warmup)
         r["eager_fwd_ms"] = wall_ms(lambda: eager_step(plan, w, nbf, False), args.steps, args.warmup)
+        r["eager_split_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True, True), args.steps, args.warmup)
         fb = g.CapturedStep(plan, db, w, nb, backward=True, G=G)
         r["graph_fwd_bwd_ms"] = wall_ms(fb.replay, args.steps, args.warmup)
         fo = g.CapturedStep(plan, db, w, nbf, backward=False)
@@ -299,7 +312,8 @@ def main():
         results[prec] = r
         graphs[prec] = (plan, w, nb, fb, nbf)
         print(f"[bench] {prec}: graph fwd+bwd {r['graph_fwd_bwd_ms']:.3f} ms, fwd {r['graph_fwd_ms']:.3f} ms; "
-              f"eager fwd+bwd {r['eager_fwd_bwd_ms']:.3f} ms", file=sys.stderr, flush=True)
+              f"eager fwd+bwd {r['eager_fwd_bwd_ms']:.3f} ms (reverse on a second stream: "
+              f"{r['eager_split_fwd_bwd_ms']:.3f} ms)", file=sys.stderr, flush=True)
 
     def kernel_profile(prec, backward, steps=5):
         plan, w, nb, _, nbf = graphs[prec]

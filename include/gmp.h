@@ -175,6 +175,25 @@ gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n
 gmp_status gmp_build_neighbors(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs,
                                int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream);
 
+/* gmp_build_neighbors without the reverse-pair search: when nbrs->reverse
+ * is not NULL its entries are set to -1 and the search keys are kept in
+ * `ws`; gmp_build_reverse then completes the index.  gmp_features does not
+ * read the reverse index, so the search may run on a second stream (one
+ * that waits for this build) while the forward runs; it must have finished
+ * before gmp_features_backward.  Same modes, capacity and status rules as
+ * gmp_build_neighbors. */
+gmp_status gmp_build_lists(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs,
+                           int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream);
+
+/* The reverse-pair index (nbrs->reverse) of the lists most recently built
+ * by gmp_build_lists into `ws`; reads the search keys that build left in
+ * `ws` and nothing that gmp_features writes, so it may run concurrently
+ * with gmp_features on the same workspace, but not with another build.
+ * Uses nbrs->n_pairs when set (sync mode), else nbrs->capacity, as the
+ * bound of the pair range. */
+gmp_status gmp_build_reverse(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs, void *ws,
+                             size_t ws_bytes, void *stream);
+
 /* Features [n_atoms * n_features] (float for the FP32 modes, double for
  * GMP_FP64), order-major: features[i*n_features + o*n_sigmas + s].
  * The pair set is the one in nbrs; displacements are evaluated at the

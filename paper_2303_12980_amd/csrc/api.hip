@@ -503,12 +503,10 @@ int lds_keys_for(const gmp_plan *p, int64_t maxcnt) {
   return (int)want;
 }
 
-}  // namespace
-
-extern "C" {
-
-gmp_status gmp_build_neighbors(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, int64_t *n_pairs,
-                               void *ws, size_t ws_bytes, void *stream) {
+// The neighbour build; the reverse-pair search is launched only when
+// `with_reverse` (gmp_build_lists leaves it to gmp_build_reverse).
+gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, int64_t *n_pairs, void *ws,
+                      size_t ws_bytes, void *stream, bool with_reverse) {
   gmp_status st = check_batch(p, b);
   if (st) return st;
   st = check_nbrs(p, b, n, true);
@@ -561,9 +559,41 @@ gmp_status gmp_build_neighbors(const gmp_plan *p, const gmp_batch *b, gmp_neighb
     lds_keys = lds_keys_for(p, n->max_list > 0 ? n->max_list : kSortMax);
   }
   launch_fill(p, bt, nb, L, lds_keys, s);
-  if (n->reverse) launch_reverse(p, bt, nb, L, n_pairs ? *n_pairs : n->capacity, s);
+  if (n->reverse && with_reverse) launch_reverse(p, bt, nb, L, n_pairs ? *n_pairs : n->capacity, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "neighbour kernels");
+  return GMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gmp_status gmp_build_neighbors(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, int64_t *n_pairs,
+                               void *ws, size_t ws_bytes, void *stream) {
+  return build_impl(p, b, n, n_pairs, ws, ws_bytes, stream, true);
+}
+
+gmp_status gmp_build_lists(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, int64_t *n_pairs, void *ws,
+                           size_t ws_bytes, void *stream) {
+  return build_impl(p, b, n, n_pairs, ws, ws_bytes, stream, false);
+}
+
+gmp_status gmp_build_reverse(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, void *ws, size_t ws_bytes,
+                             void *stream) {
+  gmp_status st = check_batch(p, b);
+  if (st) return st;
+  st = check_nbrs(p, b, n, true);
+  if (st) return st;
+  if (!n->reverse) return set_error(GMP_E_INVALID, "null reverse index");
+  if (!ws) return set_error(GMP_E_INVALID, "null workspace");
+  WsLayout L = carve(p, b->n_structs, b->n_atoms, n->capacity, ws, ws_bytes);
+  if (L.bytes > ws_bytes) return set_error(GMP_E_NOMEM, "workspace too small");
+  if (b->n_atoms == 0) return GMP_OK;
+  const int64_t bound = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
+  launch_reverse(p, to_dev(b), to_dev(n), L, bound, (hipStream_t)stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(e, "reverse-index kernel");
   return GMP_OK;
 }
 

@@ -20,6 +20,7 @@ from . import _lib
 from ._lib import GMPError, check
 
 __all__ = ["GMPPlan", "DeviceBatch", "Neighbors", "Workspace", "build_neighbors", "rebuild_neighbors_nosync",
+           "build_reverse",
            "check_status", "features", "features_backward", "GMPFunction", "CapturedStep", "feature_labels",
            "profile", "GMPError"]
 
@@ -201,11 +202,15 @@ class Neighbors:
 
 
 def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: Optional[int] = None,
-                    reverse: bool = True, stream=None, out: Optional[Neighbors] = None) -> Neighbors:
+                    reverse: bool = True, stream=None, out: Optional[Neighbors] = None,
+                    defer_reverse: bool = False) -> Neighbors:
     """Neighbour lists with the two-call capacity pattern.  ``out`` reuses
     the buffers of an earlier result for the same batch shape when its
-    capacity suffices."""
+    capacity suffices.  With ``defer_reverse`` the reverse-pair search is
+    left to build_reverse (which may run on another stream while the
+    forward runs)."""
     L = _lib.load()
+    call = L.gmp_build_lists if defer_reverse else L.gmp_build_neighbors
     if capacity is None:
         capacity = out.capacity if out is not None else max(1024, batch.n_atoms * 64)
     for _ in range(2):
@@ -217,8 +222,8 @@ def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: 
         buf = ws.get(nbytes)
         bd, nd = batch.desc(), nb.desc()
         npairs = ctypes.c_int64(0)
-        st = L.gmp_build_neighbors(plan.handle, ctypes.byref(bd), ctypes.byref(nd), ctypes.byref(npairs),
-                                   _ptr(buf), buf.numel(), _stream_ptr(stream))
+        st = call(plan.handle, ctypes.byref(bd), ctypes.byref(nd), ctypes.byref(npairs), _ptr(buf), buf.numel(),
+                  _stream_ptr(stream))
         if st == _lib.GMP_E_CAPACITY:
             capacity = int(npairs.value)
             continue
@@ -229,16 +234,25 @@ def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: 
     raise GMPError(_lib.GMP_E_CAPACITY, "capacity retry failed")
 
 
-def rebuild_neighbors_nosync(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, nb: Neighbors, stream=None):
+def rebuild_neighbors_nosync(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, nb: Neighbors, stream=None,
+                             defer_reverse: bool = False):
     """Rebuild the lists into nb without any host synchronization (usable
     under stream capture).  nb.capacity must suffice; an overflow or a
     device-side error is reported later by check_status()."""
     L = _lib.load()
+    call = L.gmp_build_lists if defer_reverse else L.gmp_build_neighbors
     nbytes = plan.workspace_bytes(batch.n_structs, batch.n_atoms, nb.capacity)
     buf = ws.get(nbytes)
     bd, nd = batch.desc(), nb.desc()
-    check(L.gmp_build_neighbors(plan.handle, ctypes.byref(bd), ctypes.byref(nd), None, _ptr(buf), buf.numel(),
-                                _stream_ptr(stream)))
+    check(call(plan.handle, ctypes.byref(bd), ctypes.byref(nd), None, _ptr(buf), buf.numel(), _stream_ptr(stream)))
+    return nb
+
+
+def build_reverse(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, nb: Neighbors, stream=None):
+    """Reverse-pair index of lists built with defer_reverse into ``ws``."""
+    bd, nd = batch.desc(), nb.desc()
+    check(_lib.load().gmp_build_reverse(plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(ws.buf),
+                                        ws.buf.numel(), _stream_ptr(stream)))
     return nb
 
 
@@ -311,9 +325,13 @@ class CapturedStep:
     grad_pos / grad_cell when backward=True); inputs are read from the
     batch's tensors, so updating batch.xyz / batch.cell in place and
     replaying featurizes the new geometry.  `nb` (from a sync build) fixes
-    the capacity; call check_status(ws) to see overflows."""
+    the capacity; call check_status(ws) to see overflows.  With backward
+    and concurrent_reverse, the reverse-pair search is recorded on a second
+    stream beside the forward and the adjoint waits for it (measured slower
+    than one stream on the C2 step, so off by default)."""
 
-    def __init__(self, plan: GMPPlan, batch: DeviceBatch, ws: Workspace, nb: Neighbors, backward=False, G=None):
+    def __init__(self, plan: GMPPlan, batch: DeviceBatch, ws: Workspace, nb: Neighbors, backward=False, G=None,
+                 concurrent_reverse=False):
         self.plan, self.batch, self.ws, self.nb = plan, batch, ws, nb
         dev = batch.species.device
         N = batch.n_atoms
@@ -321,6 +339,11 @@ class CapturedStep:
         self.F = torch.empty((N, plan.n_features), dtype=plan.dtype, device=dev)
         self.mu = torch.empty((N, plan.n_components), dtype=torch.float64, device=dev)
         self.backward = backward
+        self.split = backward and concurrent_reverse and nb.reverse is not None
+        if self.split:
+            self.rev_stream = torch.cuda.Stream()
+            self.ev_built = torch.cuda.Event()
+            self.ev_rev = torch.cuda.Event()
         if backward:
             self.G = torch.zeros((N, plan.n_features), dtype=plan.dtype, device=dev)
             if G is not None:
@@ -342,9 +365,18 @@ class CapturedStep:
 
     def _run(self):
         L = _lib.load()
-        rebuild_neighbors_nosync(self.plan, self.batch, self.ws, self.nb)
+        main = torch.cuda.current_stream()
+        rebuild_neighbors_nosync(self.plan, self.batch, self.ws, self.nb, defer_reverse=self.split)
+        if self.split:
+            self.ev_built.record(main)
+            self.rev_stream.wait_event(self.ev_built)
+            with torch.cuda.stream(self.rev_stream):
+                build_reverse(self.plan, self.batch, self.ws, self.nb)
+            self.ev_rev.record(self.rev_stream)
         features(self.plan, self.batch, self.nb, self.ws, True, out=self.F, comp_out=self.mu)
         if self.backward:
+            if self.split:
+                main.wait_event(self.ev_rev)
             buf = self.ws.buf
             bd, nd = self.batch.desc(), self.nb.desc()
             check(L.gmp_features_backward(self.plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(self.mu),

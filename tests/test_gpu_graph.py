@@ -53,9 +53,11 @@ def _same(a, b):
     return a.shape == b.shape and bool(torch.equal(a, b))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32w"])
-def test_graph_replay_matches_eager(g, precision):
-    say(f"[graph replay {precision}]")
+@pytest.mark.parametrize("precision,split", [("fp64", False), ("fp32c", False), ("fp32w", False), ("fp32c", True)])
+def test_graph_replay_matches_eager(g, precision, split):
+    """split: the reverse-pair search recorded on a second stream beside the
+    forward (gmp_build_lists + gmp_build_reverse)."""
+    say(f"[graph replay {precision} split={split}]")
     b, probes = _batch(5)
     plan = g.GMPPlan.from_probes(probes, precision)
     db = g.DeviceBatch.from_batch(b)
@@ -64,7 +66,7 @@ def test_graph_replay_matches_eager(g, precision):
                         device="cuda").to(plan.dtype)
     nb, F0, mu0, gp0, gc0 = _eager(g, plan, db, ws, G)
     nbc = g.build_neighbors(plan, db, ws, capacity=2 * nb.n_pairs + 1024)
-    step = g.CapturedStep(plan, db, ws, nbc, backward=True, G=G)
+    step = g.CapturedStep(plan, db, ws, nbc, backward=True, G=G, concurrent_reverse=split)
     other = g.GMPPlan.from_probes(probes, "fp64")
     ws2 = g.Workspace()
     for r in range(4):
