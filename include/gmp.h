@@ -170,8 +170,12 @@ gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n
  * count exceeds nbrs->capacity it returns GMP_E_CAPACITY with *n_pairs set
  * to the required count (offsets are valid; call again with a larger
  * capacity).  No-sync mode (n_pairs == NULL, usable under graph capture):
- * never syncs; an overflow is flagged in the workspace status word and the
- * lists are left incomplete (see gmp_check_status). */
+ * never syncs; an overflow is flagged in the workspace status word (see
+ * gmp_check_status): lists that would end past the capacity are not written
+ * and gmp_features / gmp_features_backward treat them as empty (zero
+ * features and gradients for those centres), and a list longer than the
+ * in-LDS sort sized from nbrs->max_list is replaced by placeholder entries;
+ * every kernel stays inside the caller's arrays. */
 gmp_status gmp_build_neighbors(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs,
                                int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream);
 
