@@ -11,10 +11,10 @@
 //   dL/dR_j += v, dL/dR_i -= v, dL/da_m += (n_m - m_{j,m} + m_{i,m}) v.
 //
 // Determinism without atomics: every centre writes the v of its own pairs
-// (pair-owner scatter into a per-pair buffer); each atom then gathers, in
-// list order, -v of its own pairs plus v of the reverse pairs (j, i, -n);
-// the cell gradient is a fixed-order per-structure reduction of per-atom
-// partials.
+// into a per-pair buffer; each atom then gathers, in list order, -v of its
+// own pairs plus v of the reverse pairs (j, i, -n) found through the
+// reverse-pair index; the cell gradient is a fixed-order per-structure
+// reduction of per-atom partials.
 #include "gmp_internal.h"
 
 namespace gmp {

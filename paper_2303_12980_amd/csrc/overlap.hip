@@ -11,18 +11,19 @@
 // of every monomial m of each requested degree, and the norm kernel maps
 // moments to components with the plan's exact integer matrices (FP64).
 //
-// Work decomposition: one wavefront per (centre, sigma group, chunk of the
-// centre's list); lanes take consecutive pairs.  Each centre's list is
-// grouped by neighbour species, so within a segment the density primitives
-// are wavefront-uniform and are read through the scalar cache; within a
-// segment the pairs a sigma uses form a prefix, so a sigma's lanes stop at
-// its own cutoff without testing q.
+// Work decomposition: persistent wavefronts pull work items (a chunk of one
+// centre's list) from a global counter; lanes take consecutive pairs.  The
+// list is ordered by cutoff shell first, so the pairs a sigma uses form a
+// prefix and each sigma is one pass over its own prefix, without testing q.
+// Lanes read the coefficient row of their own neighbour's species from the
+// LDS copy of the plan table.
 //
-// Precision policies:
-//   F64=false  displacement rounded to FP32; monomials, exp2, radial sums and
-//              products in FP32; accumulation as FP32 (hi, lo) two-sum pairs;
-//              cross-lane reduction in FP64.
-//   F64=true   everything FP64 (exp in FP64), plain accumulation.
+// Precision policies (template MODE):
+//   FP32 compensated: displacement rounded to FP32; monomials, exp2, radial
+//              sums and products in FP32; per-lane accumulation as FP32
+//              (hi, lo) two-sum pairs; cross-lane reduction in FP64.
+//   FP32 wide: FP32 exp2 and radial sums, FP64 monomials and accumulation.
+//   FP64:      everything FP64 (exp in FP64), plain accumulation.
 #include <map>
 #include <mutex>
 #include <type_traits>
