@@ -33,7 +33,8 @@ __all__ = [
 class Probes:
     """Probe set plus per-element density primitives.
 
-    orders:        angular orders l (each in 0..4), output order as given
+    orders:        angular orders l (each in 0..4, or -1 for the local
+                   density, which takes no sigma), output order as given
     sigmas:        Gaussian probe widths in Angstrom, output order as given
     prim_offsets:  int32 [n_elements+1]; element e owns primitives
                    prim_offsets[e] .. prim_offsets[e+1]-1
@@ -53,7 +54,7 @@ class Probes:
 
     @property
     def n_features(self) -> int:
-        return int(len(self.orders) * len(self.sigmas))
+        return int(sum(1 if int(l) == -1 else len(self.sigmas) for l in self.orders))
 
 
 @dataclasses.dataclass

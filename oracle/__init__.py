@@ -54,12 +54,16 @@ def lib():
             c_int, c_dbl, c_i64 = ctypes.c_int, ctypes.c_double, ctypes.c_int64
             L.oracle_cutoffs.argtypes = [c_int, dp, c_int, ip, dp, dp, c_dbl, dp]
             L.oracle_cutoffs.restype = c_int
+            L.oracle_density_cutoff.argtypes = [c_int, ip, dp, dp, c_dbl, dp]
+            L.oracle_density_cutoff.restype = c_int
             L.oracle_wrap.argtypes = [c_int, dp, dp, c_int, dp, ip]
             L.oracle_wrap.restype = c_int
             L.oracle_neighbors.argtypes = [c_int, dp, ip, dp, c_int, c_int, dp, c_int, c_i64,
                                            ip, ip, dp, ip, ip]
             L.oracle_neighbors.restype = c_i64
             probe_args = [c_int, ip, c_int, dp, c_int, ip, dp, dp, c_dbl]
+            L.oracle_slot_cutoffs.argtypes = [*probe_args, dp]
+            L.oracle_slot_cutoffs.restype = c_int
             L.oracle_features.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp]
             L.oracle_features.restype = c_int
             L.oracle_grad.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, dp, dp, dp, dp]
@@ -109,17 +113,44 @@ def _probe_args(probes):
     return keep, args
 
 
-def n_components(orders: Sequence[int]) -> int:
-    return int(sum((l + 1) * (l + 2) // 2 for l in orders))
+def n_components(orders: Sequence[int], n_sigmas: int) -> int:
+    """Components of one centre: n_sigmas * ncomp(l) per order, 1 for order -1."""
+    return int(sum(1 if l == -1 else n_sigmas * (l + 1) * (l + 2) // 2 for l in orders))
 
 
-def cutoffs(probes) -> np.ndarray:
+def n_features(orders: Sequence[int], n_sigmas: int) -> int:
+    """Features of one centre: n_sigmas per order, 1 for order -1."""
+    return int(sum(1 if l == -1 else n_sigmas for l in orders))
+
+
+def n_slots(probes) -> int:
+    """Cutoff slots: the sigmas, plus the density when order -1 is requested."""
+    return len(probes.sigmas) + (1 if -1 in [int(l) for l in probes.orders] else 0)
+
+
+def sigma_cutoffs(probes) -> np.ndarray:
     """rc(sigma)^2 for every sigma."""
     keep, a = _probe_args(probes)
     rc2 = np.zeros(len(probes.sigmas))
-    _, rp = _d(rc2)
     _check(lib().oracle_cutoffs(a[2], a[3], a[4], a[5], a[6], a[7], a[8],
                                 rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return rc2
+
+
+def density_cutoff(probes) -> float:
+    """rc_{-1}^2 of the local density (order -1)."""
+    keep, a = _probe_args(probes)
+    out = ctypes.c_double(0.0)
+    _check(lib().oracle_density_cutoff(a[4], a[5], a[6], a[7], a[8], ctypes.byref(out)))
+    return out.value
+
+
+def cutoffs(probes) -> np.ndarray:
+    """rc^2 of every cutoff slot: the sigmas in order, then the density when
+    order -1 is requested."""
+    keep, a = _probe_args(probes)
+    rc2 = np.zeros(n_slots(probes))
+    _check(lib().oracle_slot_cutoffs(*a, rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return rc2
 
 
@@ -160,8 +191,8 @@ def neighbors(struct, rc2, centre: int):
 
 
 def features(struct, probes, centres: Optional[Sequence[int]] = None, with_mu: bool = False):
-    """F [n_centres, n_orders*n_sigmas] (order-major) and optionally mu
-    [n_centres, sum_o ncomp(l_o)*n_sigmas] laid out (order, sigma, component)."""
+    """F [n_centres, nf] (order-major, sigma-minor; one feature for order -1)
+    and optionally mu [n_centres, nc] laid out (order, sigma, component)."""
     pos, spec, cell, pbc = struct
     pos, pp = _d(pos)
     spec, sp = _i(spec)
@@ -173,9 +204,9 @@ def features(struct, probes, centres: Optional[Sequence[int]] = None, with_mu: b
     else:
         carr, cptr = _i(np.asarray(centres))
         nc = ncent = len(carr)
-    nf = len(probes.orders) * len(probes.sigmas)
+    nf = n_features(probes.orders, len(probes.sigmas))
     F = np.zeros((ncent, nf))
-    ncomp = n_components(probes.orders) * len(probes.sigmas)
+    ncomp = n_components(probes.orders, len(probes.sigmas))
     mu = np.zeros((ncent, ncomp)) if with_mu else None
     _check(lib().oracle_features(len(pos), pp, sp, cp, int(pbc), *a, nc, cptr,
                                  F.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -205,7 +236,7 @@ def grad(struct, probes, G):
     G, gp = _d(G)
     n = len(pos)
     gpos = np.zeros((n, 3)); gcell = np.zeros((3, 3))
-    F = np.zeros((n, len(probes.orders) * len(probes.sigmas)))
+    F = np.zeros((n, n_features(probes.orders, len(probes.sigmas))))
     _check(lib().oracle_grad(n, pp, sp, cp, int(pbc), *a, gp,
                              gpos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              gcell.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

@@ -22,6 +22,15 @@
  *   cutoff       rc(s)^2 = max over elements, primitives of ln(|A0|/tau)/gam,
  *                A0 = B (alpha/lam)^(3/2); 0 when |A0| <= tau
  *
+ * Order -1 is the local density at the centre (section "Examples": it takes
+ * no width and gives one feature, placed where -1 stands in the orders):
+ *   rho_i = sum_{(j,n)} sum_k B_{e_j,k} exp(-beta_{e_j,k} |d|^2),  F_{i,-1} = |rho_i|
+ * the limit s -> 0 of the order-0 component (the probe Gaussian tends to a
+ * delta function: alpha/lam -> 1, gam -> beta).  Its cutoff is the same
+ * limit of the rule above, rc_{-1}^2 = max ln(|B|/tau)/beta, held in one
+ * extra cutoff slot after the sigmas ("slots" below are the sigmas plus,
+ * when order -1 is requested, the density).
+ *
  * The closed form follows from the Gaussian product theorem and the mean
  * value property of harmonic polynomials; the test suite pins it against
  * brute-force quadrature of the integral.
@@ -35,8 +44,8 @@
  *   d    = (Rw_j - Rw_i) + s(n) ;  q = (d.x^2 + d.y^2) + d.z^2
  *   (j, n) is a neighbour of i when q <= max_s rc(s)^2, n ranging over Z^3 on
  *   periodic axes (the centre itself and its own images included).
- *   shell(q) = number of sigmas with rc(s)^2 < q; sigma s uses the pairs with
- *   q <= rc(s)^2, i.e. shell(q) <= #{s' : rc(s')^2 < rc(s)^2}.
+ *   shell(q) = number of slots with rc^2 < q; a slot uses the pairs with
+ *   q <= its rc^2, i.e. shell(q) <= #{slots with a smaller rc^2}.
  *   Canonical order: ascending (shell, species of j, j, n1, n2, n3), so the
  *   pairs every sigma uses form a prefix of the list.
  *
@@ -142,6 +151,7 @@ static int ncomp(int l) { return (l + 1) * (l + 2) / 2; }
 /* components of order l in the order (a desc, then b desc) */
 static void comp_abc(int l, int idx, int *a, int *b, int *c) {
   int k = 0;
+  *a = *b = *c = 0;
   for (int aa = l; aa >= 0; --aa)
     for (int bb = l - aa; bb >= 0; --bb) {
       if (k == idx) { *a = aa; *b = bb; *c = l - aa - bb; return; }
@@ -188,6 +198,46 @@ int oracle_cutoffs(int n_sigmas, const double *sigmas, int n_elements,
     rc2[s] = best;
   }
   return OR_OK;
+}
+
+/* rc_{-1}^2 = max over primitives with |B| > tau of ln(|B|/tau)/beta */
+int oracle_density_cutoff(int n_elements, const int32_t *prim_offsets, const double *B,
+                          const double *beta, double tau, double *rc2) {
+  if (!(tau > 0.0)) return OR_E_INVALID;
+  double best = 0.0;
+  for (int e = 0; e < n_elements; ++e)
+    for (int k = prim_offsets[e]; k < prim_offsets[e + 1]; ++k) {
+      if (!(beta[k] > 0.0)) return OR_E_INVALID;
+      if (fabs(B[k]) <= tau) continue;
+      double r2 = log(fabs(B[k]) / tau) / beta[k];
+      if (r2 > best) best = r2;
+    }
+  *rc2 = best;
+  return OR_OK;
+}
+
+static int has_density(const probes_t *P) {
+  for (int o = 0; o < P->n_orders; ++o) if (P->orders[o] == -1) return 1;
+  return 0;
+}
+static int n_slots(const probes_t *P) { return P->n_sigmas + has_density(P); }
+
+/* cutoffs of every slot: the sigmas in order, then the density if requested */
+static int slot_cutoffs(const probes_t *P, double *rc2) {
+  int st = oracle_cutoffs(P->n_sigmas, P->sigmas, P->n_elements, P->prim_offsets, P->B, P->beta,
+                          P->tau, rc2);
+  if (!st && has_density(P))
+    st = oracle_density_cutoff(P->n_elements, P->prim_offsets, P->B, P->beta, P->tau,
+                               rc2 + P->n_sigmas);
+  return st;
+}
+
+/* density of element e's primitives at squared distance q, as a dual number */
+static dual density(const probes_t *P, int e, dual q) {
+  dual acc = dconst(0.0);
+  for (int k = P->prim_offsets[e]; k < P->prim_offsets[e + 1]; ++k)
+    acc = dadd(acc, dscale(P->B[k], dexp(dscale(-P->beta[k], q))));
+  return acc;
 }
 
 /* radial factor c_{l,s,e}(q) as a dual number in d */
@@ -367,45 +417,65 @@ int64_t oracle_neighbors(int n_atoms, const double *pos, const int32_t *species,
 /* ------------------------------------------------------------------ */
 /* features                                                            */
 /* ------------------------------------------------------------------ */
+/* components and features of one order: order -1 has one of each */
+static int order_comps(const probes_t *P, int l) { return l < 0 ? 1 : P->n_sigmas * ncomp(l); }
+static int order_feats(const probes_t *P, int l) { return l < 0 ? 1 : P->n_sigmas; }
+
 static int total_comps(const probes_t *P) {
   int t = 0;
-  for (int o = 0; o < P->n_orders; ++o) t += ncomp(P->orders[o]);
+  for (int o = 0; o < P->n_orders; ++o) t += order_comps(P, P->orders[o]);
+  return t;
+}
+
+static int total_feats(const probes_t *P) {
+  int t = 0;
+  for (int o = 0; o < P->n_orders; ++o) t += order_feats(P, P->orders[o]);
   return t;
 }
 
 static int check_probes(const probes_t *P) {
   if (P->n_orders < 1 || P->n_sigmas < 1 || P->n_elements < 1) return OR_E_INVALID;
   for (int o = 0; o < P->n_orders; ++o)
-    if (P->orders[o] < 0 || P->orders[o] > 4) return OR_E_INVALID;
+    if (P->orders[o] < -1 || P->orders[o] > 4) return OR_E_INVALID;
   return OR_OK;
 }
 
-/* mu and F for centre i from its pair list; mu layout [order][sigma][comp] */
-static void centre_features(const probes_t *P, const pair_t *pairs, int64_t np,
-                            const double *rc2, double *mu, double *F) {
-  int nc = total_comps(P);
-  memset(mu, 0, sizeof(double) * (size_t)nc * P->n_sigmas);
-  for (int64_t p = 0; p < np; ++p) {
-    const pair_t *pp = pairs + p;
-    dual x = dconst(pp->d[0]), y = dconst(pp->d[1]), z = dconst(pp->d[2]);
-    dual q = dconst(pp->q);
-    int off = 0;
-    for (int o = 0; o < P->n_orders; ++o) {
-      int l = P->orders[o];
-      for (int s = 0; s < P->n_sigmas; ++s) {
-        if (!(pp->q <= rc2[s])) continue;
-        double c = radial(P, l, s, pp->e, q).v;
-        for (int k = 0; k < ncomp(l); ++k) {
-          int a, b, cc; comp_abc(l, k, &a, &b, &cc);
-          mu[(size_t)(off + s * ncomp(l) + k)] += c * solid_harmonic(a, b, cc, x, y, z).v;
-        }
-      }
-      off += P->n_sigmas * ncomp(l);
-    }
-  }
+/* add one pair's terms to mu, laid out [order][sigma][comp] (order -1: one
+ * entry); `use` is the squared distance that decides which slots see the
+ * pair, (x, y, z) and q the displacement and squared distance evaluated */
+static void pair_terms(const probes_t *P, const pair_t *pp, double use, const double *rc2, double *mu) {
+  dual x = dconst(pp->d[0]), y = dconst(pp->d[1]), z = dconst(pp->d[2]);
+  dual q = dconst(pp->q);
   int off = 0;
   for (int o = 0; o < P->n_orders; ++o) {
     int l = P->orders[o];
+    if (l < 0) {
+      if (use <= rc2[P->n_sigmas]) mu[off] += density(P, pp->e, q).v;
+      off += 1;
+      continue;
+    }
+    for (int s = 0; s < P->n_sigmas; ++s) {
+      if (!(use <= rc2[s])) continue;
+      double c = radial(P, l, s, pp->e, q).v;
+      for (int k = 0; k < ncomp(l); ++k) {
+        int a, b, cc; comp_abc(l, k, &a, &b, &cc);
+        mu[(size_t)(off + s * ncomp(l) + k)] += c * solid_harmonic(a, b, cc, x, y, z).v;
+      }
+    }
+    off += order_comps(P, l);
+  }
+}
+
+/* features from mu: weighted root-sum-square per (order, sigma); |rho| for order -1 */
+static void norms(const probes_t *P, const double *mu, double *F) {
+  int off = 0, f = 0;
+  for (int o = 0; o < P->n_orders; ++o) {
+    int l = P->orders[o];
+    if (l < 0) {
+      F[f++] = fabs(mu[off]);
+      off += 1;
+      continue;
+    }
     for (int s = 0; s < P->n_sigmas; ++s) {
       double acc = 0.0;
       for (int k = 0; k < ncomp(l); ++k) {
@@ -413,16 +483,25 @@ static void centre_features(const probes_t *P, const pair_t *pairs, int64_t np,
         double v = mu[off + s * ncomp(l) + k];
         acc += comp_weight(a, b, cc) * v * v;
       }
-      F[o * P->n_sigmas + s] = sqrt(acc);
+      F[f++] = sqrt(acc);
     }
-    off += P->n_sigmas * ncomp(l);
+    off += order_comps(P, l);
   }
+}
+
+/* mu and F for centre i from its pair list */
+static void centre_features(const probes_t *P, const pair_t *pairs, int64_t np,
+                            const double *rc2, double *mu, double *F) {
+  memset(mu, 0, sizeof(double) * (size_t)total_comps(P));
+  for (int64_t p = 0; p < np; ++p) pair_terms(P, pairs + p, pairs[p].q, rc2, mu);
+  norms(P, mu, F);
 }
 
 /*
  * Features of the listed centres of one structure (all centres when
- * n_centres < 0).  F is [n_centres][n_orders*n_sigmas]; mu (optional) is
- * [n_centres][sum_o ncomp(l_o) * n_sigmas] in (order, sigma, component) order.
+ * n_centres < 0).  F is [n_centres][nf], nf = sum over orders of n_sigmas
+ * (1 for order -1); mu (optional) is [n_centres][nc], nc = sum over orders
+ * of n_sigmas*ncomp(l) (1 for order -1), in (order, sigma, component) order.
  */
 int oracle_features(int n_atoms, const double *pos, const int32_t *species,
                     const double *cell, int pbc,
@@ -435,24 +514,25 @@ int oracle_features(int n_atoms, const double *pos, const int32_t *species,
   if (st) return st;
   for (int i = 0; i < n_atoms; ++i)
     if (species[i] < 0 || species[i] >= n_elements) return OR_E_INVALID;
-  double *rc2 = (double *)malloc(sizeof(double) * n_sigmas);
-  st = oracle_cutoffs(n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, rc2);
+  const int ns = n_slots(&P);
+  double *rc2 = (double *)malloc(sizeof(double) * ns);
+  st = slot_cutoffs(&P, rc2);
   double rcmax2 = 0.0;
-  for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  for (int s = 0; s < ns; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
   sys_t S; double *rw = NULL; int32_t *m = NULL;
   if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
   if (st) { free(rc2); return st; }
   int nc = total_comps(&P);
   int ncent = n_centres < 0 ? n_atoms : n_centres;
-  int nf = n_orders * n_sigmas;
+  int nf = total_feats(&P);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < ncent; ++t) {
     int i = n_centres < 0 ? t : centres[t];
     pair_t *pairs;
-    int64_t np = collect(&S, i, n_sigmas, rc2, &pairs);
-    double *mu_i = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
+    int64_t np = collect(&S, i, ns, rc2, &pairs);
+    double *mu_i = (double *)malloc(sizeof(double) * (size_t)nc);
     centre_features(&P, pairs, np, rc2, mu_i, F + (size_t)t * nf);
-    if (mu) memcpy(mu + (size_t)t * nc * n_sigmas, mu_i, sizeof(double) * (size_t)nc * n_sigmas);
+    if (mu) memcpy(mu + (size_t)t * nc, mu_i, sizeof(double) * (size_t)nc);
     free(mu_i); free(pairs);
   }
   free(rc2); free(rw); free(m);
@@ -462,7 +542,7 @@ int oracle_features(int n_atoms, const double *pos, const int32_t *species,
 /* ------------------------------------------------------------------ */
 /* gradient of L = sum G F                                             */
 /* ------------------------------------------------------------------ */
-/* v = sum_{o,s,c} W grad_d[c_{l,s}(q) P_c(d)] for one pair */
+/* v = sum W grad_d[term] over the pair's terms (same layout as mu) */
 static void pair_v(const probes_t *P, const pair_t *pp, const double *rc2, const double *W,
                    double v[3]) {
   dual x = dvar(pp->d[0], 0), y = dvar(pp->d[1], 1), z = dvar(pp->d[2], 2);
@@ -471,6 +551,14 @@ static void pair_v(const probes_t *P, const pair_t *pp, const double *rc2, const
   int off = 0;
   for (int o = 0; o < P->n_orders; ++o) {
     int l = P->orders[o];
+    if (l < 0) {
+      if (pp->q <= rc2[P->n_sigmas] && W[off] != 0.0) {
+        dual t = density(P, pp->e, q);
+        v[0] += W[off] * t.g[0]; v[1] += W[off] * t.g[1]; v[2] += W[off] * t.g[2];
+      }
+      off += 1;
+      continue;
+    }
     for (int s = 0; s < P->n_sigmas; ++s) {
       if (!(pp->q <= rc2[s])) continue;
       dual c = radial(P, l, s, pp->e, q);
@@ -482,30 +570,36 @@ static void pair_v(const probes_t *P, const pair_t *pp, const double *rc2, const
         v[0] += w * t.g[0]; v[1] += w * t.g[1]; v[2] += w * t.g[2];
       }
     }
-    off += P->n_sigmas * ncomp(l);
+    off += order_comps(P, l);
   }
 }
 
+/* W = dL/dmu = G dF/dmu: G w mu / F per component (0 when F = 0); for
+ * order -1, F = |rho| and W = G rho / |rho| */
 static void make_W(const probes_t *P, const double *mu, const double *F, const double *G, double *W) {
-  int off = 0;
+  int off = 0, f = 0;
   for (int o = 0; o < P->n_orders; ++o) {
     int l = P->orders[o];
-    for (int s = 0; s < P->n_sigmas; ++s) {
-      double f = F[o * P->n_sigmas + s];
-      double g = G[o * P->n_sigmas + s];
+    if (l < 0) {
+      W[off] = F[f] > 0.0 ? G[f] * mu[off] / F[f] : 0.0;
+      ++f;
+      off += 1;
+      continue;
+    }
+    for (int s = 0; s < P->n_sigmas; ++s, ++f) {
       for (int k = 0; k < ncomp(l); ++k) {
         int a, b, cc; comp_abc(l, k, &a, &b, &cc);
         int idx = off + s * ncomp(l) + k;
-        W[idx] = f > 0.0 ? g * comp_weight(a, b, cc) * mu[idx] / f : 0.0;
+        W[idx] = F[f] > 0.0 ? G[f] * comp_weight(a, b, cc) * mu[idx] / F[f] : 0.0;
       }
     }
-    off += P->n_sigmas * ncomp(l);
+    off += order_comps(P, l);
   }
 }
 
 /*
- * Analytic gradient of L = sum_{i,o,s} G[i][o*S+s] F[i][o*S+s] for one
- * structure.  grad_pos [n_atoms*3], grad_cell [9] (row m = d/d a_m).
+ * Analytic gradient of L = sum_{i,f} G[i][f] F[i][f] for one structure.
+ * grad_pos [n_atoms*3], grad_cell [9] (row m = d/d a_m).
  * Also returns F [n_atoms*nf] when F_out is not NULL.
  */
 int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
@@ -519,23 +613,24 @@ int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
   if (st) return st;
   for (int i = 0; i < n_atoms; ++i)
     if (species[i] < 0 || species[i] >= n_elements) return OR_E_INVALID;
-  double *rc2 = (double *)malloc(sizeof(double) * n_sigmas);
-  st = oracle_cutoffs(n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, rc2);
+  const int ns = n_slots(&P);
+  double *rc2 = (double *)malloc(sizeof(double) * ns);
+  st = slot_cutoffs(&P, rc2);
   double rcmax2 = 0.0;
-  for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  for (int s = 0; s < ns; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
   sys_t S; double *rw = NULL; int32_t *m = NULL;
   if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
   if (st) { free(rc2); return st; }
   int nc = total_comps(&P);
-  int nf = n_orders * n_sigmas;
+  int nf = total_feats(&P);
   memset(grad_pos, 0, sizeof(double) * 3 * n_atoms);
   memset(grad_cell, 0, sizeof(double) * 9);
-  double *mu = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
-  double *W = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
+  double *mu = (double *)malloc(sizeof(double) * (size_t)nc);
+  double *W = (double *)malloc(sizeof(double) * (size_t)nc);
   double *Fi = (double *)malloc(sizeof(double) * nf);
   for (int i = 0; i < n_atoms; ++i) {
     pair_t *pairs;
-    int64_t np = collect(&S, i, n_sigmas, rc2, &pairs);
+    int64_t np = collect(&S, i, ns, rc2, &pairs);
     centre_features(&P, pairs, np, rc2, mu, Fi);
     if (F_out) memcpy(F_out + (size_t)i * nf, Fi, sizeof(double) * nf);
     make_W(&P, mu, Fi, G + (size_t)i * nf, W);
@@ -560,7 +655,7 @@ int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
  * do not see cutoff crossings.  Pairs of centre i are
  * pj[po[i]..po[i+1]), with raw-position image shifts pn (3 ints each,
  * d = R_j - R_i + pn.cell) and base squared distances pq deciding which
- * sigmas use each pair (q_base <= rc2[s]).
+ * slots use each pair (q_base <= rc2 of the slot).
  */
 int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
                        const double *cell,
@@ -572,73 +667,46 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
   probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
   int st = check_probes(&P);
   if (st) return st;
-  double *rc2 = (double *)malloc(sizeof(double) * n_sigmas);
-  st = oracle_cutoffs(n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, rc2);
+  const int ns = n_slots(&P);
+  double *rc2 = (double *)malloc(sizeof(double) * ns);
+  st = slot_cutoffs(&P, rc2);
   if (st) { free(rc2); return st; }
   int nc = total_comps(&P);
-  int nf = n_orders * n_sigmas;
+  int nf = total_feats(&P);
   double L = 0.0;
-  double *mu = (double *)malloc(sizeof(double) * (size_t)nc * n_sigmas);
+  double *mu = (double *)malloc(sizeof(double) * (size_t)nc);
   double *Fi = (double *)malloc(sizeof(double) * nf);
   for (int i = 0; i < n_atoms; ++i) {
-    int64_t np = po[i + 1] - po[i];
-    pair_t *pairs = (pair_t *)malloc(sizeof(pair_t) * (np > 0 ? np : 1));
-    for (int64_t p = 0; p < np; ++p) {
-      int64_t g = po[i] + p;
+    memset(mu, 0, sizeof(double) * (size_t)nc);
+    for (int64_t g = po[i]; g < po[i + 1]; ++g) {
       int j = pj[g];
-      pair_t *pp = pairs + p;
-      pp->j = j; pp->e = species[j];
+      pair_t pp;
+      pp.j = j; pp.e = species[j];
       for (int c = 0; c < 3; ++c) {
         double sh = (double)pn[3 * g] * cell[c] + (double)pn[3 * g + 1] * cell[3 + c] +
                     (double)pn[3 * g + 2] * cell[6 + c];
-        pp->d[c] = (pos[3 * j + c] - pos[3 * i + c]) + sh;
+        pp.d[c] = (pos[3 * j + c] - pos[3 * i + c]) + sh;
       }
-      double qq = (pp->d[0] * pp->d[0] + pp->d[1] * pp->d[1]) + pp->d[2] * pp->d[2];
-      /* membership from the base configuration: rc2 test on pq, value from qq */
-      pp->q = qq;
-      pp->shell = 0;
-      for (int s = 0; s < n_sigmas; ++s) if (rc2[s] < pq[g]) ++pp->shell;
+      pp.q = (pp.d[0] * pp.d[0] + pp.d[1] * pp.d[1]) + pp.d[2] * pp.d[2];
+      /* membership from the base configuration, value from the current one */
+      pair_terms(&P, &pp, pq[g], rc2, mu);
     }
-    /* evaluate with the frozen membership: a sigma uses the pair when pq <= rc2 */
-    memset(mu, 0, sizeof(double) * (size_t)nc * n_sigmas);
-    for (int64_t p = 0; p < np; ++p) {
-      const pair_t *pp = pairs + p;
-      double qb = pq[po[i] + p];
-      dual x = dconst(pp->d[0]), y = dconst(pp->d[1]), z = dconst(pp->d[2]);
-      dual q = dconst(pp->q);
-      int off = 0;
-      for (int o = 0; o < n_orders; ++o) {
-        int l = orders[o];
-        for (int s = 0; s < n_sigmas; ++s) {
-          if (!(qb <= rc2[s])) continue;
-          double c = radial(&P, l, s, pp->e, q).v;
-          for (int k = 0; k < ncomp(l); ++k) {
-            int a, b, cc; comp_abc(l, k, &a, &b, &cc);
-            mu[off + s * ncomp(l) + k] += c * solid_harmonic(a, b, cc, x, y, z).v;
-          }
-        }
-        off += n_sigmas * ncomp(l);
-      }
-    }
-    int off = 0;
-    for (int o = 0; o < n_orders; ++o) {
-      int l = orders[o];
-      for (int s = 0; s < n_sigmas; ++s) {
-        double acc = 0.0;
-        for (int k = 0; k < ncomp(l); ++k) {
-          int a, b, cc; comp_abc(l, k, &a, &b, &cc);
-          double v = mu[off + s * ncomp(l) + k];
-          acc += comp_weight(a, b, cc) * v * v;
-        }
-        L += G[(size_t)i * nf + o * n_sigmas + s] * sqrt(acc);
-      }
-      off += n_sigmas * ncomp(l);
-    }
-    free(pairs);
+    norms(&P, mu, Fi);
+    for (int f = 0; f < nf; ++f) L += G[(size_t)i * nf + f] * Fi[f];
   }
   free(mu); free(Fi); free(rc2);
   *L_out = L;
   return OR_OK;
+}
+
+/* rc^2 of every slot (the sigmas, then the density when order -1 is requested) */
+int oracle_slot_cutoffs(int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                        int n_elements, const int32_t *prim_offsets, const double *B,
+                        const double *beta, double tau, double *rc2) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  int st = check_probes(&P);
+  if (st) return st;
+  return slot_cutoffs(&P, rc2);
 }
 
 /* P_abc and its gradient at npts points (pts [npts*3]); out_g [npts*3] */
