@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--sample-centres", type=int, default=48)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads (512 structures, 1e5 atoms)")
+    ap.add_argument("--no-density", action="store_true", help="skip the order -1 (local density) variant")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
@@ -120,6 +121,44 @@ def other_workloads(g, gs, torch, steps=5, warmup=2):
               f"fwd+bwd {t_fb:.2f} ms, fwd {t_fo:.2f} ms", file=sys.stderr, flush=True)
         del fb, fo, nb, nbf, ws, db, G
         torch.cuda.empty_cache()
+    return out
+
+
+def density_variant(g, gs, torch, batch, probes, db, steps=10, warmup=3):
+    """The same 4096-atom cell with order -1 (the local density, one feature
+    without a width) added in front of the orders: graph-replayed fwd+bwd
+    and fwd steps in FP32 compensated mode, and the FP64 oracle on sampled
+    centres for the accuracy of the density feature."""
+    import oracle
+    pd = gs.Probes(np.concatenate([[-1], probes.orders]).astype(np.int32), probes.sigmas, probes.prim_offsets,
+                   probes.B, probes.beta, probes.tau)
+    N, nf = batch.n_atoms, pd.n_features
+    plan = g.GMPPlan.from_probes(pd, "fp32c")
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    nbf = g.build_neighbors(plan, db, ws, reverse=False)
+    G = torch.as_tensor(np.random.default_rng(7).standard_normal((N, nf)), device="cuda")
+    fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
+    fo = g.CapturedStep(plan, db, ws, nbf, backward=False)
+    for _ in range(warmup):
+        fb.replay()
+        fo.replay()
+    t_fb = _median_ms(fb.replay, steps, torch)
+    t_fo = _median_ms(fo.replay, steps, torch)
+    g.check_status(ws)
+    cs = np.sort(np.random.default_rng(13).choice(N, size=min(24, N), replace=False))
+    Fref = oracle.features(batch.structure(0), pd, centres=cs)
+    Fg = fb.F.double().cpu().numpy()[cs]
+    big = Fref > pd.tau
+    out = {"orders": [int(x) for x in pd.orders], "features_per_atom": nf, "n_slots": plan.n_slots,
+           "density_rc2": float(plan.rc2[-1]), "pairs": int(nb.n_pairs), "fwd_bwd_ms": t_fb, "fwd_ms": t_fo,
+           "atoms_features_per_s_fwd_bwd": N * nf / (t_fb * 1e-3), "atoms_features_per_s_fwd": N * nf / (t_fo * 1e-3),
+           "density_max_rel_err": float(np.max(np.abs(Fg[:, 0] - Fref[:, 0]) / Fref[:, 0])),
+           "all_max_rel_err": float(np.max(np.abs(Fg[big] - Fref[big]) / Fref[big])), "sampled_centres": len(cs)}
+    print(f"[bench] order -1 added: fwd+bwd {t_fb:.3f} ms, fwd {t_fo:.3f} ms, density max rel err "
+          f"{out['density_max_rel_err']:.2e}", file=sys.stderr, flush=True)
+    del fb, fo, nb, nbf, ws, G
+    torch.cuda.empty_cache()
     return out
 
 
@@ -399,6 +438,8 @@ def main():
     if not args.no_fp64:
         out["kernels_fp64_ms_per_step"] = {k: round(v["ms_per_step"], 5) for k, v in kernel_profile("fp64", True).items()}
     out["kernels_fp32w_ms_per_step"] = {k: round(v["ms_per_step"], 5) for k, v in kernel_profile("fp32w", True).items()}
+    if not args.no_density:
+        out["density_variant"] = density_variant(g, gs, torch, batch, probes, db)
     if not args.no_batched:
         del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()

@@ -11,7 +11,15 @@
  * root-sum-square F_{i,l,sigma} = sqrt(sum_abc l!/(a!b!c!) mu^2)
  * ("Examples": probe set = Cartesian product of orders and sigmas, order-major;
  * cutoff inferred from the overlap threshold; derivatives with respect to the
- * atom positions on request).
+ * atom positions on request).  Order -1 is the local density at the centre,
+ * rho_i = sum_j sum_k B_k exp(-beta_k |d|^2) ("Examples": it takes no sigma
+ * and gives one feature), the sigma -> 0 limit of the order-0 probe; its
+ * feature is |rho_i|.
+ *
+ * Cutoff slots: every sigma has its own cutoff, and order -1 adds one more
+ * slot after the sigmas, rc_{-1}^2 = max_{e,k} ln(|B|/tau)/beta (the
+ * sigma -> 0 limit of the per-sigma rule).  n_slots = n_sigmas, plus 1 when
+ * order -1 is requested; per-sigma arrays below are per slot.
  *
  * Conventions for every entry point:
  *  - Pointers are DEVICE pointers owned by the caller unless marked [host].
@@ -41,7 +49,7 @@ extern "C" {
 
 typedef enum {
   GMP_OK = 0,
-  GMP_E_INVALID = 1,      /* bad argument: null pointer, order outside 0..4, sigma <= 0, beta <= 0, ... */
+  GMP_E_INVALID = 1,      /* bad argument: null pointer, order outside -1..4, sigma <= 0, beta <= 0, ... */
   GMP_E_UNSUPPORTED = 2,  /* valid but outside what the kernels handle (documented limits) */
   GMP_E_CELL = 3,         /* singular lattice for a structure with a periodic axis */
   GMP_E_CAPACITY = 4,     /* neighbour capacity too small; required count returned */
@@ -73,9 +81,9 @@ typedef struct gmp_plan gmp_plan; /* opaque, immutable after creation */
  * hyper-parameter dictionary ("Examples": orders, sigmas, pseudopotential
  * primitives, overlap_threshold).  Copied by gmp_plan_create. */
 typedef struct {
-  int32_t n_orders;              /* 1..5 */
-  const int32_t *orders;         /* distinct, each in 0..4; output order as given */
-  int32_t n_sigmas;              /* 1..16 */
+  int32_t n_orders;              /* 1..6 */
+  const int32_t *orders;         /* distinct, each in -1..4 (-1: local density); output order as given */
+  int32_t n_sigmas;              /* 1..16 (1..15 with order -1: at most 16 cutoff slots) */
   const double *sigmas;          /* Angstrom, > 0; output order as given */
   int32_t n_elements;            /* 1..64 */
   const int32_t *prim_offsets;   /* [n_elements+1], ascending, prim_offsets[0] = 0; <= 16 per element */
@@ -99,8 +107,8 @@ typedef struct {
 
 /* Neighbour lists in canonical order.  For centre i, entries
  * [offsets[i], offsets[i+1]) are sorted by (shell, species of j, j, n1, n2, n3)
- * where shell(q) = number of sigmas with rc(sigma)^2 < q, so the pairs each
- * sigma uses (q <= rc(sigma)^2) are a prefix of the list.  Bucket
+ * where shell(q) = number of cutoff slots with rc^2 < q, so the pairs each
+ * slot uses (q <= its rc^2) are a prefix of the list.  Bucket
  * b = shell * n_elements + species holds the entries of one (shell, species). */
 typedef struct {
   int64_t capacity;              /* [host] entries allocated in j, shift, reverse */
@@ -109,9 +117,9 @@ typedef struct {
   int32_t *j;                    /* [capacity] neighbour atom (global index) */
   int32_t *shift;                /* [capacity] bytes (n1, n2, n3, species_j), n_k signed, little endian;
                                     d = (Rw_j - Rw_i) + n1 a1 + n2 a2 + n3 a3 with wrapped positions */
-  int32_t *bucket_start;         /* [n_atoms*(n_sigmas*n_elements+1)] bucket starts, local to offsets[i];
+  int32_t *bucket_start;         /* [n_atoms*(n_slots*n_elements+1)] bucket starts, local to offsets[i];
                                     the last entry is the list length */
-  int32_t *sigma_end;            /* [n_atoms*n_sigmas] length of the prefix sigma s uses, local */
+  int32_t *sigma_end;            /* [n_atoms*n_slots] length of the prefix cutoff slot s uses, local */
   int32_t *wrap;                 /* [n_atoms*3] m_i: Rw_i = R_i - (m1 a1 + m2 a2 + m3 a3) */
   double *rw;                    /* [3*n_atoms] wrapped positions, SoA (x block, y block, z block) */
   int32_t *reverse;              /* [capacity] or NULL: local index of (j, i, -n) in j's list;
@@ -128,17 +136,19 @@ typedef struct {
 gmp_status gmp_plan_create(const gmp_probe_desc *desc, gmp_precision precision, gmp_plan **out);
 void gmp_plan_destroy(gmp_plan *plan);
 
-/* [host] rc(sigma)^2 for every sigma of a probe set, without creating a
- * plan (host only, no device needed): the squared distance beyond which
- * every primitive's l = 0 overlap |B| (alpha/lambda)^(3/2) exp(-gamma q)
+/* [host] rc^2 of every cutoff slot of a probe set, without creating a
+ * plan (host only, no device needed): for sigma, the squared distance beyond
+ * which every primitive's l = 0 overlap |B| (alpha/lambda)^(3/2) exp(-gamma q)
  * falls below overlap_threshold ("Examples": the cutoff is inferred from the
- * threshold).  rc2: [n_sigmas]. */
+ * threshold); for the density slot, the distance beyond which every
+ * primitive's |B| exp(-beta q) does.  rc2: [n_slots]. */
 gmp_status gmp_probe_cutoffs(const gmp_probe_desc *desc, double *rc2);
 
-/* [host] outputs: n_features = n_orders*n_sigmas; n_components =
- * n_sigmas * sum_o (l_o+1)(l_o+2)/2; rc2 [n_sigmas] (may be NULL). */
+/* [host] outputs (each may be NULL): n_features = sum over orders of
+ * n_sigmas (1 for order -1); n_components = sum over orders of
+ * n_sigmas (l+1)(l+2)/2 (1 for order -1); n_slots; rc2 [n_slots]. */
 gmp_status gmp_plan_info(const gmp_plan *plan, int32_t *n_features, int32_t *n_components,
-                         double *rc2);
+                         int32_t *n_slots, double *rc2);
 
 /* Tuning knobs (autotuned by the caller or left at defaults).
  *  chunk_pairs:   a centre's list is processed in work items of this many
@@ -199,7 +209,9 @@ gmp_status gmp_build_reverse(const gmp_plan *plan, const gmp_batch *batch, gmp_n
                              size_t ws_bytes, void *stream);
 
 /* Features [n_atoms * n_features] (float for the FP32 modes, double for
- * GMP_FP64), order-major: features[i*n_features + o*n_sigmas + s].
+ * GMP_FP64), order-major: features[i*n_features + f_o + s] with
+ * f_o = sum over the orders before o of n_sigmas (1 for order -1), and the
+ * single feature of order -1 at f_o.
  * The pair set is the one in nbrs; displacements are evaluated at the
  * batch's current coordinates and lattice with the wrap indices of the
  * build (d = R_j - R_i + (n - m_j + m_i) . cell), so moving atoms or the
@@ -207,7 +219,8 @@ gmp_status gmp_build_reverse(const gmp_plan *plan, const gmp_batch *batch, gmp_n
  * geometry (bitwise the build's geometry when nothing moved).
  * components (optional, FP64) [n_atoms * n_components] laid out
  * (order, sigma, component) with components of order l in the order
- * (a descending, then b descending); required later by the backward. */
+ * (a descending, then b descending), and the signed density rho_i as the
+ * one component of order -1; required later by the backward. */
 gmp_status gmp_features(const gmp_plan *plan, const gmp_batch *batch, const gmp_neighbors *nbrs,
                         void *features, double *components, void *ws, size_t ws_bytes,
                         void *stream);

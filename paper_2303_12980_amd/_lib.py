@@ -72,7 +72,7 @@ def load():
     L.gmp_probe_cutoffs.restype = c_i32
     L.gmp_plan_destroy.argtypes = [c_vp]
     L.gmp_plan_destroy.restype = None
-    L.gmp_plan_info.argtypes = [c_vp, P_i32, P_i32, P_dbl]
+    L.gmp_plan_info.argtypes = [c_vp, P_i32, P_i32, P_i32, P_dbl]
     L.gmp_plan_info.restype = c_i32
     L.gmp_plan_get_tuning.argtypes = [c_vp, ctypes.POINTER(Tuning)]
     L.gmp_plan_get_tuning.restype = c_i32

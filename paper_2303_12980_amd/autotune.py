@@ -43,7 +43,7 @@ def tuning_key(plan, batch, nb) -> str:
     dev = torch.cuda.get_device_name(batch.species.device)
     avg = nb.n_pairs / max(1, batch.n_atoms)
     kmax = int(max(int(b) - int(a) for a, b in zip(plan._poff[:-1], plan._poff[1:])))
-    return (f"{dev}|{plan.precision}|L{int(max(plan.orders))}|S{len(plan.sigmas)}|E{plan.n_elements}|K{kmax}"
+    return (f"{dev}|{plan.precision}|L{int(max(plan.orders))}|S{plan.n_slots}|E{plan.n_elements}|K{kmax}"
             f"|N{_bucket(batch.n_atoms)}|avg{_bucket(avg)}")
 
 

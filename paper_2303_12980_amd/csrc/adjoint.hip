@@ -9,6 +9,9 @@
 //   v_{ijn} = grad_d sum_{s,l} c_{l,s}(q) Q_{i,s,l}(d)
 //          = sum_{s,l} [ 2 c'_{l,s}(q) Q_{i,s,l}(d) d + c_{l,s}(q) grad Q_{i,s,l}(d) ].
 //   dL/dR_j += v, dL/dR_i -= v, dL/da_m += (n_m - m_{j,m} + m_{i,m}) v.
+//   The local density of order -1 (F = |rho|) has W = G rho / |rho| on the
+//   degree-0 coefficient of its own cutoff slot, whose radial factor is
+//   sum_k B exp(-beta q).
 //
 // Determinism without atomics: every centre writes the v of its own pairs
 // into a per-pair buffer; each atom then gathers, in list order, -v of its
@@ -65,12 +68,19 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   const double *mu = components + (size_t)i * P.ncomp_total;
   if (live) {
     for (int t = lane; t < P.nf; t += kWave) {
-      const int o = t / S, s = t - o * S;
-      const int l = P.orders[o], nc = ncomp(l);
-      const double *mv = mu + P.comp_off[o] + s * nc;
-      double a = 0.0;
-      for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
-      const double F = sqrt(a);
+      int o = 0;
+      while (o + 1 < P.n_orders && P.feat_off[o + 1] <= t) ++o;
+      const int l = P.orders[o];
+      double F;
+      if (l < 0) {
+        F = fabs(mu[P.comp_off[o]]);
+      } else {
+        const int s = t - P.feat_off[o], nc = ncomp(l);
+        const double *mv = mu + P.comp_off[o] + s * nc;
+        double a = 0.0;
+        for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
+        F = sqrt(a);
+      }
       const double G = (double)((const T *)grad_features)[(size_t)i * P.nf + t];
       scale[t] = F > 0.0 ? G / F : 0.0;
     }
@@ -82,13 +92,18 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
       const int s = t / NM, m = t - s * NM;
       const int l = kMT.deg[m];
       double v = 0.0;
-      int o = -1;
-      for (int oo = 0; oo < P.n_orders; ++oo) if (P.orders[oo] == l) o = oo;
-      if (o >= 0) {
-        const int nc = ncomp(l), mm = m - doff(l);
-        const double *mv = mu + P.comp_off[o] + s * nc;
-        for (int cc = 0; cc < nc; ++cc) v += P.weight[doff(l) + cc] * mv[cc] * P.T[P.toff[l] + cc * nc + mm];
-        v *= scale[o * S + s];
+      if (s == P.dens_slot) {
+        const int o = P.dens_order;
+        if (m == 0) v = mu[P.comp_off[o]] * scale[P.feat_off[o]];
+      } else {
+        int o = -1;
+        for (int oo = 0; oo < P.n_orders; ++oo) if (P.orders[oo] == l) o = oo;
+        if (o >= 0) {
+          const int nc = ncomp(l), mm = m - doff(l);
+          const double *mv = mu + P.comp_off[o] + s * nc;
+          for (int cc = 0; cc < nc; ++cc) v += P.weight[doff(l) + cc] * mv[cc] * P.T[P.toff[l] + cc * nc + mm];
+          v *= scale[P.feat_off[o] + s];
+        }
       }
       M[t] = v;
     }
@@ -142,7 +157,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
   __syncthreads();
   const int lane = lane_id();
   T *vbuf = (T *)vbuf_;
-  const int mask = P.order_mask;
+  const int mask = P.order_mask, dens = P.dens_slot;
   T *bcoef = tabl + tab_n + (size_t)(threadIdx.x / kWave) * S * NB;
   for (;;) {
     const int64_t item = next_item(counter);
@@ -203,6 +218,23 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
         if (!(act && p < ends)) continue;
         const size_t roff = ((size_t)(s * E + e) * KB) * kCoefStride;
         const T *bc = (const T *)__builtin_assume_aligned(bcoef + (size_t)s * NB, 16);
+        if (s == dens) {  // local density: v = 2 rho'(q) W d, rho'(q) = sum_k B (-beta) e_k
+          T cp0 = (T)0;
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            if (k < K) {
+              const size_t o = roff + k * kCoefStride;
+              const T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+              cp0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], (LDS ? tabl[o + 6] : tabg[o + 6]) * ek, cp0);
+            }
+          }
+          const T A = cp0 * bc[0];
+          const T A2 = A + A;
+          vx += (double)(A2 * xv);
+          vy += (double)(A2 * yv);
+          vz += (double)(A2 * zv);
+          continue;
+        }
         // c_l = sum_k A e_k and c'_l = sum_k A (-gamma_k e_k)
         T cl[LMAX + 1], cp[LMAX + 1];
 #pragma unroll

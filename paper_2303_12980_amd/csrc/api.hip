@@ -203,24 +203,30 @@ extern "C" {
 
 const char *gmp_last_error(void) { return g_err.c_str(); }
 
-static gmp_status validate_desc(const gmp_probe_desc *d, int *mask_out, int *kmax_out) {
+static gmp_status validate_desc(const gmp_probe_desc *d, int *mask_out, int *kmax_out, int *dens_out) {
   if (!d) return set_error(GMP_E_INVALID, "null argument");
   if (d->n_orders < 1 || d->n_orders > kMaxOrders || !d->orders)
-    return set_error(GMP_E_INVALID, "n_orders must be 1..5");
+    return set_error(GMP_E_INVALID, "n_orders must be 1..6");
   if (d->n_sigmas < 1 || d->n_sigmas > kMaxSigmas || !d->sigmas)
     return set_error(GMP_E_INVALID, "n_sigmas must be 1..16");
   if (d->n_elements < 1 || d->n_elements > kMaxElements || !d->prim_offsets)
     return set_error(GMP_E_INVALID, "n_elements must be 1..64");
   if (!(d->overlap_threshold > 0.0) || !isfinite(d->overlap_threshold))
     return set_error(GMP_E_INVALID, "overlap_threshold must be positive and finite");
-  int mask = 0;
+  int mask = 0, dens = 0;
   for (int o = 0; o < d->n_orders; ++o) {
     int l = d->orders[o];
-    if (l == -1) return set_error(GMP_E_UNSUPPORTED, "order -1 (local density) is not implemented");
-    if (l < 0 || l > kMaxL) return set_error(GMP_E_INVALID, "orders must be in 0..4");
+    if (l < -1 || l > kMaxL) return set_error(GMP_E_INVALID, "orders must be in -1..4");
+    if (l == -1) {
+      if (dens) return set_error(GMP_E_INVALID, "orders must be distinct");
+      dens = 1;
+      continue;
+    }
     if (mask & (1 << l)) return set_error(GMP_E_INVALID, "orders must be distinct");
     mask |= 1 << l;
   }
+  if (d->n_sigmas + dens > kMaxSigmas)
+    return set_error(GMP_E_INVALID, "n_sigmas must be 1..15 with order -1 (at most 16 cutoff slots)");
   for (int s = 0; s < d->n_sigmas; ++s)
     if (!(d->sigmas[s] > 0.0) || !isfinite(d->sigmas[s])) return set_error(GMP_E_INVALID, "sigmas must be > 0");
   if (d->prim_offsets[0] != 0) return set_error(GMP_E_INVALID, "prim_offsets[0] must be 0");
@@ -239,6 +245,7 @@ static gmp_status validate_desc(const gmp_probe_desc *d, int *mask_out, int *kma
   }
   if (mask_out) *mask_out = mask;
   if (kmax_out) *kmax_out = kmax;
+  if (dens_out) *dens_out = dens;
   return GMP_OK;
 }
 
@@ -261,11 +268,28 @@ static double cutoff2(const gmp_probe_desc *d, int s) {
   return best;
 }
 
+// Cutoff of the local density (order -1): rc_{-1}^2 = max over (e, k) with
+// |B| > tau of ln(|B| / tau) / beta, where every primitive's density
+// |B| exp(-beta q) has fallen below the threshold (the sigma -> 0 limit of
+// cutoff2: A0 -> |B|, gamma -> beta).
+static double density_cutoff2(const gmp_probe_desc *d) {
+  double best = 0.0;
+  for (int k = 0; k < d->prim_offsets[d->n_elements]; ++k) {
+    const double b = fabs(d->B[k]);
+    if (!(b > d->overlap_threshold)) continue;
+    const double r2 = log(b / d->overlap_threshold) / d->beta[k];
+    if (r2 > best) best = r2;
+  }
+  return best;
+}
+
 gmp_status gmp_probe_cutoffs(const gmp_probe_desc *d, double *rc2) {
-  gmp_status st = validate_desc(d, nullptr, nullptr);
+  int dens = 0;
+  gmp_status st = validate_desc(d, nullptr, nullptr, &dens);
   if (st) return st;
   if (!rc2) return set_error(GMP_E_INVALID, "null rc2");
   for (int s = 0; s < d->n_sigmas; ++s) rc2[s] = cutoff2(d, s);
+  if (dens) rc2[d->n_sigmas] = density_cutoff2(d);
   return GMP_OK;
 }
 
@@ -274,18 +298,21 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   *out = nullptr;
   if (precision != GMP_FP64 && precision != GMP_FP32_COMPENSATED && precision != GMP_FP32_WIDE)
     return set_error(GMP_E_INVALID, "unknown precision");
-  int mask = 0, kmax = 1;
-  gmp_status vst = validate_desc(d, &mask, &kmax);
+  int mask = 0, kmax = 1, dens = 0;
+  gmp_status vst = validate_desc(d, &mask, &kmax, &dens);
   if (vst) return vst;
 
   gmp_plan *p = new gmp_plan();
   memset(&p->dev, 0, sizeof(p->dev));
   p->prec = precision;
-  p->S = d->n_sigmas;
+  p->S = d->n_sigmas + dens;
   p->E = d->n_elements;
   p->n_orders = d->n_orders;
   PlanDev &P = p->dev;
   P.S = p->S;
+  P.n_sig = d->n_sigmas;
+  P.dens_slot = dens ? d->n_sigmas : -1;
+  P.dens_order = -1;
   P.E = p->E;
   P.n_orders = p->n_orders;
   P.order_mask = mask;
@@ -293,21 +320,46 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   const int kb = kmax <= 4 ? 4 : (kmax <= 8 ? 8 : 16);
   P.kb = kb;
   P.lmax = 0;
-  int coff = 0;
+  int coff = 0, foff = 0;
   for (int o = 0; o < p->n_orders; ++o) {
-    p->orders[o] = d->orders[o];
-    P.orders[o] = d->orders[o];
+    const int l = d->orders[o];
+    p->orders[o] = l;
+    P.orders[o] = l;
     P.comp_off[o] = coff;
-    coff += p->S * ncomp(d->orders[o]);
-    if (d->orders[o] > P.lmax) P.lmax = d->orders[o];
+    P.feat_off[o] = foff;
+    if (l < 0) {  // the density: one component, one feature
+      P.dens_order = o;
+      coff += 1;
+      foff += 1;
+      continue;
+    }
+    coff += P.n_sig * ncomp(l);
+    foff += P.n_sig;
+    if (l > P.lmax) P.lmax = l;
   }
   P.ncomp_total = coff;
-  P.nf = p->n_orders * p->S;
+  P.nf = foff;
 
   std::vector<float> c32((size_t)p->S * p->E * kb * kCoefStride, 0.0f);
   std::vector<double> c64((size_t)p->S * p->E * kb * kCoefStride, 0.0);
   double rcmax2 = 0.0;
-  for (int s = 0; s < p->S; ++s) {
+  if (dens) {  // density slot: exp(-beta q) with weights B for degree 0 only
+    const int s = P.dens_slot;
+    for (int e = 0; e < p->E; ++e)
+      for (int k = d->prim_offsets[e]; k < d->prim_offsets[e + 1]; ++k) {
+        const int kk = k - d->prim_offsets[e];
+        const size_t idx = (((size_t)s * p->E + e) * kb + kk) * kCoefStride;
+        c64[idx] = -d->beta[k];
+        c32[idx] = (float)(-d->beta[k] * 1.4426950408889634);
+        c64[idx + 1] = d->B[k];
+        c32[idx + 1] = (float)d->B[k];
+        c64[idx + 6] = -d->beta[k];
+        c32[idx + 6] = (float)(-d->beta[k]);
+      }
+    p->rc2[s] = P.rc2[s] = density_cutoff2(d);
+    rcmax2 = P.rc2[s];
+  }
+  for (int s = 0; s < P.n_sig; ++s) {
     const double sg = d->sigmas[s];
     p->sigmas[s] = sg;
     const double alpha = 1.0 / (2.0 * sg * sg);
@@ -394,10 +446,12 @@ void gmp_plan_destroy(gmp_plan *p) {
   delete p;
 }
 
-gmp_status gmp_plan_info(const gmp_plan *p, int32_t *n_features, int32_t *n_components, double *rc2) {
+gmp_status gmp_plan_info(const gmp_plan *p, int32_t *n_features, int32_t *n_components, int32_t *n_slots,
+                         double *rc2) {
   if (!p) return set_error(GMP_E_INVALID, "null plan");
   if (n_features) *n_features = p->dev.nf;
   if (n_components) *n_components = p->dev.ncomp_total;
+  if (n_slots) *n_slots = p->S;
   if (rc2) for (int s = 0; s < p->S; ++s) rc2[s] = p->rc2[s];
   return GMP_OK;
 }

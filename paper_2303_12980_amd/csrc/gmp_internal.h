@@ -16,8 +16,8 @@
 
 namespace gmp {
 
-constexpr int kMaxOrders = 5;
-constexpr int kMaxSigmas = 16;
+constexpr int kMaxOrders = 6;    // -1 (local density) and 0..4
+constexpr int kMaxSigmas = 16;   // cutoff slots: the sigmas plus the density slot of order -1
 constexpr int kMaxElements = 64;
 constexpr int kMaxL = 4;
 constexpr int kCoefStride = 8;    // per (sigma, element, primitive): -g', A0..A4, -gamma, pad
@@ -79,12 +79,17 @@ struct StructInfo {
   double lam_lo;      // lower bound of the smallest eigenvalue of the lattice metric (0: no bin culling)
 };
 
-// Device view of a plan (passed by value to kernels).
+// Device view of a plan (passed by value to kernels).  S counts cutoff
+// slots: the n_sig sigmas, then (dens_slot = n_sig) the local density of
+// order -1 when requested (dens_slot = -1 otherwise).  The density slot's
+// coefficient rows hold -beta (scaled), A_0 = B, A_1..A_4 = 0, -beta.
 struct PlanDev {
   int S, E, n_orders, lmax, order_mask, kmax, kb, nf, ncomp_total;  // kb: primitive stride of the tables (4/8/16)
+  int n_sig, dens_slot, dens_order;  // sigmas, density slot, index of order -1 in orders (-1: none)
   int orders[kMaxOrders];
   int comp_off[kMaxOrders];       // offset of order o's (sigma, component) block in one centre's components
-  int sig_order[kMaxSigmas];      // sigmas sorted by rc^2 ascending (stable)
+  int feat_off[kMaxOrders];       // first feature of order o (n_sig features per order, 1 for order -1)
+  int sig_order[kMaxSigmas];      // slots sorted by rc^2 ascending (stable)
   int rank_lt[kMaxSigmas];        // #{s': rc2[s'] < rc2[s]}
   double rc2[kMaxSigmas];
   double rcmax2;
@@ -111,8 +116,8 @@ struct NbrDev {
   int64_t *offsets;
   int32_t *j;
   int32_t *shift;
-  int32_t *bucket_start;   // [N][S*E+1] local starts of buckets (shell h, species e) = h*E + e
-  int32_t *sigma_end;      // [N][S] end of each sigma's prefix
+  int32_t *bucket_start;   // [N][S*E+1] local starts of buckets (shell h, species e) = h*E + e (S slots)
+  int32_t *sigma_end;      // [N][S] end of each cutoff slot's prefix
   int32_t *wrap;
   double *rw;
   int32_t *reverse;
@@ -206,7 +211,7 @@ __device__ inline int shift_species(int32_t w) { return (int)((uint32_t)w >> 24)
 struct gmp_plan {
   gmp_precision prec;
   gmp::PlanDev dev;
-  int S, E, n_orders;
+  int S, E, n_orders;  // S: cutoff slots (sigmas, plus the density slot of order -1)
   int orders[gmp::kMaxOrders];
   double sigmas[gmp::kMaxSigmas];
   double rc2[gmp::kMaxSigmas];

@@ -16,7 +16,9 @@
 // list is ordered by cutoff shell first, so the pairs a sigma uses form a
 // prefix and each sigma is one pass over its own prefix, without testing q.
 // Lanes read the coefficient row of their own neighbour's species from the
-// LDS copy of the plan table.
+// LDS copy of the plan table.  The local density of order -1 is one more
+// cutoff slot whose pass accumulates only the degree-0 moment
+// rho = sum_j sum_k B exp(-beta q).
 //
 // Precision policies (template MODE):
 //   FP32 compensated: displacement rounded to FP32; monomials, exp2, radial
@@ -240,10 +242,31 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         advance(tc, pc);
         if (tc < S && pc + lane < pass_end(tc)) { jc = nb.j[base + pc + lane]; wc = nb.shift[base + pc + lane]; }
       }
-      // current step: sigma sig_order[ta], pairs pa + lane
+      // current step: slot sig_order[ta], pairs pa + lane
       const int sgm = __builtin_amdgcn_readlane(so_lane, ta);
       const int p = pa + lane;
-      if (p < pass_end(ta)) {
+      if (p < pass_end(ta) && sgm == P.dens_slot) {
+        // local density (order -1): the degree-0 moment of sum_k B exp(-beta q)
+        double shx = 0.0, shy = 0.0, shz = 0.0;
+        if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
+        const double dx = (rjx - rix) + shx;
+        const double dy = (rjy - riy) + shy;
+        const double dz = (rjz - riz) + shz;
+        const TR qv = (TR)((dx * dx + dy * dy) + dz * dz);
+        const int e = shift_species(w);
+        const int K = lds_k[e];
+        const size_t roff = ((size_t)(sgm * E + e) * KB) * kCoefStride;
+        TR c0 = (TR)0;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          if (k < K) {
+            const size_t o = roff + k * kCoefStride;
+            c0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], exp_scaled(LDS ? tabl[o] : tabg[o], qv), c0);
+          }
+        }
+        if constexpr (MODE == ACC_TWOSUM) acc.add(0, c0);
+        else acc.v[0] += (double)c0;
+      } else if (p < pass_end(ta)) {
         double shx = 0.0, shy = 0.0, shz = 0.0;
         if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
         const double dx = (rjx - rix) + shx;
@@ -287,7 +310,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
           for (int m = 0; m < NM; ++m) acc.v[m] = fma(cd[kMT.deg[m]], mono[m], acc.v[m]);
         }
       }
-      if (tb != ta) {  // the pass of sigma sgm is complete: FP64 cross-lane reduction, store, restart
+      if (tb != ta) {  // the pass of slot sgm is complete: FP64 cross-lane reduction, store, restart
         double vals[NM];
 #pragma unroll
         for (int m = 0; m < NM; ++m) vals[m] = acc.value(m);
@@ -300,7 +323,8 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
 
 // One wavefront per centre: sum chunk partials in order, map moments to
 // components with the exact integer matrices, then the weighted norm
-// F_{l,s} = sqrt(sum_abc l!/(a!b!c!) mu_abc^2).
+// F_{l,s} = sqrt(sum_abc l!/(a!b!c!) mu_abc^2).  Order -1 takes the degree-0
+// moment of the density slot as its component rho and |rho| as its feature.
 template <bool F64OUT>
 __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const double *partial,
                                                 const int64_t *chunk_off, void *features, double *components) {
@@ -315,7 +339,7 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
     for (int t = lane; t < S * NM; t += kWave) {
       const int s = t / NM, m = t - s * NM;
       double a = 0.0;
-      if ((P.order_mask >> kMT.deg[m]) & 1) {
+      if (s == P.dens_slot ? m == 0 : ((P.order_mask >> kMT.deg[m]) & 1)) {
         const int64_t q1 = chunk_off[i + 1];
         for (int64_t q = chunk_off[i]; q < q1; ++q) a += partial[((size_t)q * S + s) * NM + m];
       }
@@ -327,13 +351,18 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
     for (int t = lane; t < P.ncomp_total; t += kWave) {
       int o = 0;
       while (o + 1 < P.n_orders && P.comp_off[o + 1] <= t) ++o;
-      const int l = P.orders[o], nc = ncomp(l);
-      const int r = t - P.comp_off[o];
-      const int s = r / nc, cc = r - s * nc;
-      const double *Tl = P.T + P.toff[l] + cc * nc;
-      const double *ms = mom + s * NM + doff(l);
+      const int l = P.orders[o];
       double v = 0.0;
-      for (int mm = 0; mm < nc; ++mm) v += Tl[mm] * ms[mm];
+      if (l < 0) {
+        v = mom[P.dens_slot * NM];
+      } else {
+        const int nc = ncomp(l);
+        const int r = t - P.comp_off[o];
+        const int s = r / nc, cc = r - s * nc;
+        const double *Tl = P.T + P.toff[l] + cc * nc;
+        const double *ms = mom + s * NM + doff(l);
+        for (int mm = 0; mm < nc; ++mm) v += Tl[mm] * ms[mm];
+      }
       mu[t] = v;
       if (components) components[(size_t)i * P.ncomp_total + t] = v;
     }
@@ -341,12 +370,19 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
   wave_lds_sync();
   if (live) {
     for (int t = lane; t < P.nf; t += kWave) {
-      const int o = t / S, s = t - o * S;
-      const int l = P.orders[o], nc = ncomp(l);
-      const double *mv = mu + P.comp_off[o] + s * nc;
-      double a = 0.0;
-      for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
-      const double F = sqrt(a);
+      int o = 0;
+      while (o + 1 < P.n_orders && P.feat_off[o + 1] <= t) ++o;
+      const int l = P.orders[o];
+      double F;
+      if (l < 0) {
+        F = fabs(mu[P.comp_off[o]]);
+      } else {
+        const int s = t - P.feat_off[o], nc = ncomp(l);
+        const double *mv = mu + P.comp_off[o] + s * nc;
+        double a = 0.0;
+        for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
+        F = sqrt(a);
+      }
       if (F64OUT) ((double *)features)[(size_t)i * P.nf + t] = F;
       else ((float *)features)[(size_t)i * P.nf + t] = (float)F;
     }

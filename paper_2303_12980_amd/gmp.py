@@ -5,8 +5,9 @@ memory and the current stream; every step of the path (wrap, cell list,
 neighbour lists, overlaps, norms, adjoint) runs in libgmp.so.
 
 Feature layout follows the featurizer's enumeration (paper, "Examples"):
-the probe set is the Cartesian product orders x sigmas, order-major, so
-feature o*n_sigmas + s is (orders[o], sigmas[s]).
+the probe set is the Cartesian product orders x sigmas, order-major and
+sigma-minor; order -1 (the local density) takes no sigma and contributes a
+single feature where it stands in the orders.
 """
 from __future__ import annotations
 
@@ -69,10 +70,12 @@ class GMPPlan:
         h = ctypes.c_void_p(0)
         check(L.gmp_plan_create(ctypes.byref(d), prec, ctypes.byref(h)))
         self._h = h
-        nf, nc = _lib.c_i32(0), _lib.c_i32(0)
-        rc2 = np.zeros(len(self._sigmas))
-        check(L.gmp_plan_info(h, ctypes.byref(nf), ctypes.byref(nc), rc2.ctypes.data_as(_lib.P_dbl)))
-        self.n_features, self.n_components, self.rc2 = nf.value, nc.value, rc2
+        nf, nc, ns = _lib.c_i32(0), _lib.c_i32(0), _lib.c_i32(0)
+        check(L.gmp_plan_info(h, ctypes.byref(nf), ctypes.byref(nc), ctypes.byref(ns), None))
+        rc2 = np.zeros(ns.value)
+        check(L.gmp_plan_info(h, None, None, None, rc2.ctypes.data_as(_lib.P_dbl)))
+        # cutoff slots: the sigmas, then the local density when order -1 is requested
+        self.n_features, self.n_components, self.n_slots, self.rc2 = nf.value, nc.value, ns.value, rc2
         self.n_elements = len(self._poff) - 1
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
 
@@ -176,7 +179,7 @@ class Neighbors:
     def __init__(self, plan: GMPPlan, batch: DeviceBatch, capacity: int, reverse: bool = True):
         dev = batch.species.device
         N = batch.n_atoms
-        E, S = plan.n_elements, len(plan.sigmas)
+        E, S = plan.n_elements, plan.n_slots
         self.capacity = int(capacity)
         self.n_pairs = 0
         self.max_list = 0  # longest list of the last synchronous build (sizes no-sync rebuilds)

@@ -51,7 +51,7 @@ def check_neighbors(nb, batch_np, probes, centres=None):
     offs = nb.offsets.cpu().numpy()
     P = int(offs[-1])
     assert P == nb.n_pairs
-    E, S = probes.n_elements, len(probes.sigmas)
+    E, S = probes.n_elements, oracle.n_slots(probes)
     if nb.reverse is not None:
         check_reverse(nb)
     wrap_all = nb.wrap.view(-1, 3)

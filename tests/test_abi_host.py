@@ -49,18 +49,22 @@ def _desc(probes):
 
 
 @pytest.mark.parametrize("name", ["C1", "C2", "C4"])
-def test_cutoffs_bit_exact_vs_oracle(lib, name):
+@pytest.mark.parametrize("density", [False, True])
+def test_cutoffs_bit_exact_vs_oracle(lib, name, density):
     kw = dict(n_atoms=64) if name == "C2" else (dict(n_structs=2) if name == "C4" else {})
     _, probes = gs.config(name, **kw)
+    if density:  # order -1 adds the density cutoff slot after the sigmas
+        probes.orders = np.concatenate([[-1], probes.orders]).astype(np.int32)
     d, keep = _desc(probes)
-    rc2 = np.zeros(len(probes.sigmas))
+    rc2 = np.zeros(oracle.n_slots(probes))
     assert lib.gmp_probe_cutoffs(ctypes.byref(d), rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
     assert rc2.tobytes() == oracle.cutoffs(probes).tobytes()
+    assert len(rc2) == len(probes.sigmas) + int(density)
 
 
 def _status(lib, probes):
     d, keep = _desc(probes)
-    rc2 = np.zeros(max(1, len(probes.sigmas)))
+    rc2 = np.zeros(max(1, len(probes.sigmas)) + 1)
     return lib.gmp_probe_cutoffs(ctypes.byref(d), rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
 
 
@@ -75,7 +79,12 @@ def _probes(**kw):
 @pytest.mark.parametrize("bad,code", [
     (dict(orders=np.array([0, 5], np.int32)), 1),
     (dict(orders=np.array([1, 1], np.int32)), 1),
-    (dict(orders=np.array([-1, 0], np.int32)), 2),
+    (dict(orders=np.array([-1, 0], np.int32)), 0),
+    (dict(orders=np.array([-1], np.int32)), 0),
+    (dict(orders=np.array([0, -1, -1], np.int32)), 1),
+    (dict(orders=np.array([-2, 0], np.int32)), 1),
+    (dict(orders=np.array([-1, 0], np.int32), sigmas=np.linspace(0.2, 1.0, 16)), 1),
+    (dict(orders=np.array([0], np.int32), sigmas=np.linspace(0.2, 1.0, 16)), 0),
     (dict(sigmas=np.array([0.5, 0.0])), 1),
     (dict(sigmas=np.array([np.nan])), 1),
     (dict(beta=np.array([0.5, -1.0])), 1),
