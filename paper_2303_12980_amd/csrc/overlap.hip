@@ -147,7 +147,7 @@ template <int MODE, int NM> __device__ inline double acc_value(const Acc<MODE, N
 // The coefficient table [sigma][element][KB][8] (exponent scale, A_0..A_4,
 // -gamma) is copied into LDS once per workgroup when it fits; lanes read
 // the row of their own neighbour's species.
-template <int LMAX, int KB, int MODE, bool LDS>
+template <int LMAX, int KB, int MODE, bool LDS, bool DENS>
 __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
                                                  const int32_t *astruct, double *partial, const int64_t *chunk_off,
                                                  int kc, unsigned long long *counter, const void *tab_global) {
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
       // current step: slot sig_order[ta], pairs pa + lane
       const int sgm = __builtin_amdgcn_readlane(so_lane, ta);
       const int p = pa + lane;
-      if (p < pass_end(ta) && sgm == P.dens_slot) {
+      if (DENS && p < pass_end(ta) && sgm == P.dens_slot) {
         // local density (order -1): the degree-0 moment of sum_k B exp(-beta q)
         double shx = 0.0, shy = 0.0, shz = 0.0;
         if (pbc) image_shift(cell, shift_n(w, 0), shift_n(w, 1), shift_n(w, 2), shx, shy, shz);
@@ -392,26 +392,32 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
 using OverlapFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const int32_t *, double *, const int64_t *,
                            int, unsigned long long *, const void *);
 
-template <int L, int MODE, bool LDS> OverlapFn pick_k(int kb) {
-  if (kb <= 4) return k_overlap<L, 4, MODE, LDS>;
-  if (kb <= 8) return k_overlap<L, 8, MODE, LDS>;
-  return k_overlap<L, 16, MODE, LDS>;
+// DENS: the plan has the density slot of order -1 (a separate instantiation
+// keeps that branch out of the loop of plans without it)
+template <int L, int MODE, bool LDS, bool DENS> OverlapFn pick_k(int kb) {
+  if (kb <= 4) return k_overlap<L, 4, MODE, LDS, DENS>;
+  if (kb <= 8) return k_overlap<L, 8, MODE, LDS, DENS>;
+  return k_overlap<L, 16, MODE, LDS, DENS>;
 }
 
-template <int MODE, bool LDS> OverlapFn pick_l(int lmax, int kb) {
+template <int MODE, bool LDS, bool DENS> OverlapFn pick_l(int lmax, int kb) {
   switch (lmax) {
-    case 0: return pick_k<0, MODE, LDS>(kb);
-    case 1: return pick_k<1, MODE, LDS>(kb);
-    case 2: return pick_k<2, MODE, LDS>(kb);
-    case 3: return pick_k<3, MODE, LDS>(kb);
-    default: return pick_k<4, MODE, LDS>(kb);
+    case 0: return pick_k<0, MODE, LDS, DENS>(kb);
+    case 1: return pick_k<1, MODE, LDS, DENS>(kb);
+    case 2: return pick_k<2, MODE, LDS, DENS>(kb);
+    case 3: return pick_k<3, MODE, LDS, DENS>(kb);
+    default: return pick_k<4, MODE, LDS, DENS>(kb);
   }
 }
 
-template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb) {
-  if (prec == GMP_FP64) return pick_l<ACC_F64, LDS>(lmax, kb);
-  if (prec == GMP_FP32_WIDE) return pick_l<ACC_WIDE, LDS>(lmax, kb);
-  return pick_l<ACC_TWOSUM, LDS>(lmax, kb);
+template <bool LDS, bool DENS> OverlapFn pick_d(gmp_precision prec, int lmax, int kb) {
+  if (prec == GMP_FP64) return pick_l<ACC_F64, LDS, DENS>(lmax, kb);
+  if (prec == GMP_FP32_WIDE) return pick_l<ACC_WIDE, LDS, DENS>(lmax, kb);
+  return pick_l<ACC_TWOSUM, LDS, DENS>(lmax, kb);
+}
+
+template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb, bool dens) {
+  return dens ? pick_d<LDS, true>(prec, lmax, kb) : pick_d<LDS, false>(prec, lmax, kb);
 }
 
 }  // namespace
@@ -466,7 +472,9 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
   const bool use_lds = tab_bytes <= 48 * 1024;
   const size_t smem = use_lds ? tab_bytes : 0;
   const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
-  OverlapFn fn = use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb) : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb);
+  const bool dens = p->dev.dens_slot >= 0;
+  OverlapFn fn = use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb, dens)
+                         : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb, dens);
   const int64_t items_bound = max_chunks(p, N, pairs_bound);
   int64_t blocks = persistent_blocks((const void *)fn, smem, p->tuning.blocks_per_cu);
   const int64_t need = (items_bound + 3) / 4;
