@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "Probes", "Batch", "density_tables", "rsa_periodic", "rsa_cluster",
     "triclinic_cell", "make_batch", "config", "CONFIG_NAMES", "small_periodic",
-    "small_cluster", "upstream_gradient",
+    "small_cluster", "upstream_gradient", "disorder",
 ]
 
 
@@ -66,12 +66,14 @@ class Batch:
     species:      int32 [n_atoms]
     cell:         float64 [n_structs, 3, 3]; row m is lattice vector a_m
     pbc:          uint8 [n_structs]; bit k set = periodic along a_k
+    occupancy:    float64 [n_atoms] fractional site occupancies, or None (all 1)
     """
     atom_offsets: np.ndarray
     pos: np.ndarray
     species: np.ndarray
     cell: np.ndarray
     pbc: np.ndarray
+    occupancy: Optional[np.ndarray] = None
 
     @property
     def n_structs(self) -> int:
@@ -282,15 +284,42 @@ def _species_uniform(rng, n, n_elements):
     return rng.integers(0, n_elements, size=n).astype(np.int32)
 
 
-def make_batch(structs: Sequence) -> Batch:
-    """Pack a list of (pos, species, cell, pbc) into a CSR batch."""
+def make_batch(structs: Sequence, occupancy=None) -> Batch:
+    """Pack a list of (pos, species, cell, pbc) into a CSR batch; occupancy
+    (optional) is one array per structure."""
     offs = np.zeros(len(structs) + 1, dtype=np.int64)
     offs[1:] = np.cumsum([len(s[0]) for s in structs])
     pos = np.concatenate([np.asarray(s[0], dtype=np.float64).reshape(-1, 3) for s in structs], axis=0)
     spec = np.concatenate([np.asarray(s[1], dtype=np.int32) for s in structs])
     cell = np.stack([np.asarray(s[2], dtype=np.float64).reshape(3, 3) for s in structs])
     pbc = np.array([int(s[3]) for s in structs], dtype=np.uint8)
-    return Batch(offs, np.ascontiguousarray(pos), spec, cell, pbc)
+    occ = None
+    if occupancy is not None:
+        occ = np.concatenate([np.asarray(o, dtype=np.float64).reshape(-1) for o in occupancy])
+        assert len(occ) == len(spec)
+    return Batch(offs, np.ascontiguousarray(pos), spec, cell, pbc, occ)
+
+
+def disorder(rng, struct, n_elements: int, mixed: float = 0.3, vacant: float = 0.2):
+    """A disordered version of (pos, species, cell, pbc): a fraction `mixed`
+    of the sites become shared by two species (one entry per species at the
+    same position, occupancies w and 1 - w), a fraction `vacant` keep one
+    species with occupancy in (0.3, 1); returns (struct, occupancy)."""
+    rng = _rng(rng)
+    pos, spec, cell, pbc = struct
+    pos_out, spec_out, occ_out = [], [], []
+    for r, e in zip(np.asarray(pos), np.asarray(spec)):
+        u = rng.random()
+        if u < mixed and n_elements > 1:
+            w = rng.uniform(0.1, 0.9)
+            e2 = (int(e) + 1 + int(rng.integers(n_elements - 1))) % n_elements
+            pos_out += [r, r]; spec_out += [int(e), e2]; occ_out += [w, 1.0 - w]
+        elif u < mixed + vacant:
+            pos_out.append(r); spec_out.append(int(e)); occ_out.append(rng.uniform(0.3, 1.0))
+        else:
+            pos_out.append(r); spec_out.append(int(e)); occ_out.append(1.0)
+    return ((np.asarray(pos_out, np.float64).reshape(-1, 3), np.asarray(spec_out, np.int32), cell, pbc),
+            np.asarray(occ_out, np.float64))
 
 
 def scatter_images(rng, pos, cell, reach=1):

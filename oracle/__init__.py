@@ -64,11 +64,11 @@ def lib():
             probe_args = [c_int, ip, c_int, dp, c_int, ip, dp, dp, c_dbl]
             L.oracle_slot_cutoffs.argtypes = [*probe_args, dp]
             L.oracle_slot_cutoffs.restype = c_int
-            L.oracle_features.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp]
+            L.oracle_features.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp, dp]
             L.oracle_features.restype = c_int
-            L.oracle_grad.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, dp, dp, dp, dp]
+            L.oracle_grad.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, dp, dp, dp, dp, dp]
             L.oracle_grad.restype = c_int
-            L.oracle_loss_frozen.argtypes = [c_int, dp, ip, dp, *probe_args, lp, ip, ip, dp, dp, dp]
+            L.oracle_loss_frozen.argtypes = [c_int, dp, ip, dp, *probe_args, lp, ip, ip, dp, dp, dp, dp]
             L.oracle_loss_frozen.restype = c_int
             L.oracle_solid_harmonic.argtypes = [c_int, c_int, c_int, c_int, dp, dp, dp]
             L.oracle_solid_harmonic.restype = None
@@ -190,9 +190,20 @@ def neighbors(struct, rc2, centre: int):
         cap = int(cnt)
 
 
-def features(struct, probes, centres: Optional[Sequence[int]] = None, with_mu: bool = False):
+def _occ(occupancy, n):
+    """(keep-alive array, pointer) of the per-atom occupancies, or (None, None)."""
+    if occupancy is None:
+        return None, None
+    o = np.ascontiguousarray(occupancy, dtype=np.float64)
+    assert o.shape == (n,)
+    return o, o.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def features(struct, probes, centres: Optional[Sequence[int]] = None, with_mu: bool = False,
+             occupancy=None):
     """F [n_centres, nf] (order-major, sigma-minor; one feature for order -1)
-    and optionally mu [n_centres, nc] laid out (order, sigma, component)."""
+    and optionally mu [n_centres, nc] laid out (order, sigma, component).
+    occupancy: per-atom fractional occupancies (None: all 1)."""
     pos, spec, cell, pbc = struct
     pos, pp = _d(pos)
     spec, sp = _i(spec)
@@ -208,16 +219,20 @@ def features(struct, probes, centres: Optional[Sequence[int]] = None, with_mu: b
     F = np.zeros((ncent, nf))
     ncomp = n_components(probes.orders, len(probes.sigmas))
     mu = np.zeros((ncent, ncomp)) if with_mu else None
+    occ, op = _occ(occupancy, len(pos))
     _check(lib().oracle_features(len(pos), pp, sp, cp, int(pbc), *a, nc, cptr,
                                  F.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                 mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if with_mu else None))
+                                 mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if with_mu else None, op))
     return (F, mu) if with_mu else F
 
 
 def features_batch(batch, probes, with_mu=False):
     Fs, mus = [], []
+    occ = getattr(batch, "occupancy", None)
     for s in range(batch.n_structs):
-        r = features(batch.structure(s), probes, with_mu=with_mu)
+        a0, a1 = int(batch.atom_offsets[s]), int(batch.atom_offsets[s + 1])
+        r = features(batch.structure(s), probes, with_mu=with_mu,
+                     occupancy=None if occ is None else occ[a0:a1])
         if with_mu:
             Fs.append(r[0]); mus.append(r[1])
         else:
@@ -226,7 +241,7 @@ def features_batch(batch, probes, with_mu=False):
     return (F, np.concatenate(mus, axis=0)) if with_mu else F
 
 
-def grad(struct, probes, G):
+def grad(struct, probes, G, occupancy=None):
     """Analytic dL/dR [n,3] and dL/dcell [3,3] of L = sum G*F, plus F."""
     pos, spec, cell, pbc = struct
     pos, pp = _d(pos)
@@ -237,10 +252,11 @@ def grad(struct, probes, G):
     n = len(pos)
     gpos = np.zeros((n, 3)); gcell = np.zeros((3, 3))
     F = np.zeros((n, n_features(probes.orders, len(probes.sigmas))))
+    occ, op = _occ(occupancy, n)
     _check(lib().oracle_grad(n, pp, sp, cp, int(pbc), *a, gp,
                              gpos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              gcell.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                             F.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+                             F.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), op))
     return gpos, gcell, F
 
 
@@ -261,7 +277,7 @@ def frozen_pairs(struct, probes):
             np.concatenate(pn).astype(np.int32), np.concatenate(pq))
 
 
-def loss_frozen(struct, probes, G, pairs):
+def loss_frozen(struct, probes, G, pairs, occupancy=None):
     pos, spec, cell, pbc = struct
     pos, pp = _d(pos)
     spec, sp = _i(spec)
@@ -270,7 +286,8 @@ def loss_frozen(struct, probes, G, pairs):
     po, pop = _l(pairs[0]); pj, pjp = _i(pairs[1]); pn, pnp = _i(pairs[2]); pq, pqp = _d(pairs[3])
     G, gp = _d(G)
     out = ctypes.c_double(0.0)
-    _check(lib().oracle_loss_frozen(len(pos), pp, sp, cp, *a, pop, pjp, pnp, pqp, gp, ctypes.byref(out)))
+    occ, op = _occ(occupancy, len(pos))
+    _check(lib().oracle_loss_frozen(len(pos), pp, sp, cp, *a, pop, pjp, pnp, pqp, gp, ctypes.byref(out), op))
     return out.value
 
 

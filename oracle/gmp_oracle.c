@@ -31,6 +31,14 @@
  * extra cutoff slot after the sigmas ("slots" below are the sigmas plus,
  * when order -1 is requested, the density).
  *
+ * Disordered structures (section "Overview": fractional site occupancy):
+ * atom j carries an occupancy w_j (1 when none is given) that scales its
+ * density, w_j sum_k B exp(-beta r^2), so every term of pair (j, n) is
+ * multiplied by w_j; a site shared by several species is one atom entry per
+ * species at the same position.  Cutoffs and neighbour sets do not depend on
+ * the occupancies, and a centre's own occupancy enters only through its self
+ * term.
+ *
  * The closed form follows from the Gaussian product theorem and the mean
  * value property of harmonic polynomials; the test suite pins it against
  * brute-force quadrature of the integral.
@@ -303,7 +311,7 @@ int oracle_wrap(int n_atoms, const double *pos, const double *cell, int pbc,
 /* ------------------------------------------------------------------ */
 /* neighbours of one centre, by brute force over atoms and images      */
 /* ------------------------------------------------------------------ */
-typedef struct { int32_t e, shell, j, n[3]; double q, d[3]; } pair_t;
+typedef struct { int32_t e, shell, j, n[3]; double q, d[3], w; } pair_t;  /* w: occupancy of j */
 
 static int pair_cmp(const void *pa, const void *pb) {
   const pair_t *x = (const pair_t *)pa, *y = (const pair_t *)pb;
@@ -318,6 +326,7 @@ static int pair_cmp(const void *pa, const void *pb) {
 typedef struct {
   int n_atoms; const double *rw; const int32_t *species; const double *cell; int pbc;
   int nimg[3];
+  const double *occ;  /* [n_atoms] occupancies or NULL (all 1) */
 } sys_t;
 
 static int image_reach(const double *cell, int pbc, double rcmax, int nimg[3]) {
@@ -364,7 +373,7 @@ static int64_t collect(const sys_t *S, int i, int n_sigmas, const double *rc2, p
           if (!(q <= rcmax2)) continue;
           if (n == cap) { cap *= 2; buf = (pair_t *)realloc(buf, sizeof(pair_t) * cap); }
           pair_t *p = buf + n++;
-          p->e = S->species[j]; p->j = j;
+          p->e = S->species[j]; p->j = j; p->w = S->occ ? S->occ[j] : 1.0;
           p->n[0] = n1; p->n[1] = n2; p->n[2] = n3;
           p->q = q; p->d[0] = d[0]; p->d[1] = d[1]; p->d[2] = d[2];
           int sh_ = 0;
@@ -384,7 +393,7 @@ static int make_sys(sys_t *S, int n_atoms, const double *pos, const int32_t *spe
   int st = oracle_wrap(n_atoms, pos, cell, pbc, rw, m);
   if (!st) st = image_reach(cell, pbc, sqrt(rcmax2), S->nimg);
   if (st) { free(rw); free(m); return st; }
-  S->n_atoms = n_atoms; S->rw = rw; S->species = species; S->cell = cell; S->pbc = pbc;
+  S->n_atoms = n_atoms; S->rw = rw; S->species = species; S->cell = cell; S->pbc = pbc; S->occ = NULL;
   *rw_out = rw; *m_out = m;
   return OR_OK;
 }
@@ -450,7 +459,7 @@ static void pair_terms(const probes_t *P, const pair_t *pp, double use, const do
   for (int o = 0; o < P->n_orders; ++o) {
     int l = P->orders[o];
     if (l < 0) {
-      if (use <= rc2[P->n_sigmas]) mu[off] += density(P, pp->e, q).v;
+      if (use <= rc2[P->n_sigmas]) mu[off] += pp->w * density(P, pp->e, q).v;
       off += 1;
       continue;
     }
@@ -459,7 +468,7 @@ static void pair_terms(const probes_t *P, const pair_t *pp, double use, const do
       double c = radial(P, l, s, pp->e, q).v;
       for (int k = 0; k < ncomp(l); ++k) {
         int a, b, cc; comp_abc(l, k, &a, &b, &cc);
-        mu[(size_t)(off + s * ncomp(l) + k)] += c * solid_harmonic(a, b, cc, x, y, z).v;
+        mu[(size_t)(off + s * ncomp(l) + k)] += pp->w * (c * solid_harmonic(a, b, cc, x, y, z).v);
       }
     }
     off += order_comps(P, l);
@@ -502,13 +511,15 @@ static void centre_features(const probes_t *P, const pair_t *pairs, int64_t np,
  * n_centres < 0).  F is [n_centres][nf], nf = sum over orders of n_sigmas
  * (1 for order -1); mu (optional) is [n_centres][nc], nc = sum over orders
  * of n_sigmas*ncomp(l) (1 for order -1), in (order, sigma, component) order.
+ * occ: [n_atoms] occupancies, or NULL for all 1.
  */
 int oracle_features(int n_atoms, const double *pos, const int32_t *species,
                     const double *cell, int pbc,
                     int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                     int n_elements, const int32_t *prim_offsets, const double *B,
                     const double *beta, double tau,
-                    int n_centres, const int32_t *centres, double *F, double *mu) {
+                    int n_centres, const int32_t *centres, double *F, double *mu,
+                    const double *occ) {
   probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
   int st = check_probes(&P);
   if (st) return st;
@@ -522,6 +533,7 @@ int oracle_features(int n_atoms, const double *pos, const int32_t *species,
   sys_t S; double *rw = NULL; int32_t *m = NULL;
   if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
   if (st) { free(rc2); return st; }
+  S.occ = occ;
   int nc = total_comps(&P);
   int ncent = n_centres < 0 ? n_atoms : n_centres;
   int nf = total_feats(&P);
@@ -572,6 +584,7 @@ static void pair_v(const probes_t *P, const pair_t *pp, const double *rc2, const
     }
     off += order_comps(P, l);
   }
+  for (int k = 0; k < 3; ++k) v[k] *= pp->w;
 }
 
 /* W = dL/dmu = G dF/dmu: G w mu / F per component (0 when F = 0); for
@@ -600,14 +613,15 @@ static void make_W(const probes_t *P, const double *mu, const double *F, const d
 /*
  * Analytic gradient of L = sum_{i,f} G[i][f] F[i][f] for one structure.
  * grad_pos [n_atoms*3], grad_cell [9] (row m = d/d a_m).
- * Also returns F [n_atoms*nf] when F_out is not NULL.
+ * Also returns F [n_atoms*nf] when F_out is not NULL.  occ as in oracle_features.
  */
 int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
                 const double *cell, int pbc,
                 int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                 int n_elements, const int32_t *prim_offsets, const double *B,
                 const double *beta, double tau,
-                const double *G, double *grad_pos, double *grad_cell, double *F_out) {
+                const double *G, double *grad_pos, double *grad_cell, double *F_out,
+                const double *occ) {
   probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
   int st = check_probes(&P);
   if (st) return st;
@@ -621,6 +635,7 @@ int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
   sys_t S; double *rw = NULL; int32_t *m = NULL;
   if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
   if (st) { free(rc2); return st; }
+  S.occ = occ;
   int nc = total_comps(&P);
   int nf = total_feats(&P);
   memset(grad_pos, 0, sizeof(double) * 3 * n_atoms);
@@ -655,7 +670,7 @@ int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
  * do not see cutoff crossings.  Pairs of centre i are
  * pj[po[i]..po[i+1]), with raw-position image shifts pn (3 ints each,
  * d = R_j - R_i + pn.cell) and base squared distances pq deciding which
- * slots use each pair (q_base <= rc2 of the slot).
+ * slots use each pair (q_base <= rc2 of the slot).  occ as in oracle_features.
  */
 int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
                        const double *cell,
@@ -663,7 +678,7 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
                        int n_elements, const int32_t *prim_offsets, const double *B,
                        const double *beta, double tau,
                        const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
-                       const double *G, double *L_out) {
+                       const double *G, double *L_out, const double *occ) {
   probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
   int st = check_probes(&P);
   if (st) return st;
@@ -681,7 +696,7 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
     for (int64_t g = po[i]; g < po[i + 1]; ++g) {
       int j = pj[g];
       pair_t pp;
-      pp.j = j; pp.e = species[j];
+      pp.j = j; pp.e = species[j]; pp.w = occ ? occ[j] : 1.0;
       for (int c = 0; c < 3; ++c) {
         double sh = (double)pn[3 * g] * cell[c] + (double)pn[3 * g + 1] * cell[3 + c] +
                     (double)pn[3 * g + 2] * cell[6 + c];
