@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--sample-centres", type=int, default=48)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads (512 structures, 1e5 atoms)")
-    ap.add_argument("--no-density", action="store_true", help="skip the order -1 (local density) variant")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the order -1 (local density) and occupancy (disordered) variants")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
@@ -158,6 +159,43 @@ def density_variant(g, gs, torch, batch, probes, db, steps=10, warmup=3):
     print(f"[bench] order -1 added: fwd+bwd {t_fb:.3f} ms, fwd {t_fo:.3f} ms, density max rel err "
           f"{out['density_max_rel_err']:.2e}", file=sys.stderr, flush=True)
     del fb, fo, nb, nbf, ws, G
+    torch.cuda.empty_cache()
+    return out
+
+
+def occupancy_variant(g, gs, torch, batch, probes, steps=10, warmup=3):
+    """The same 4096-atom cell as a disordered structure: every atom given a
+    fractional occupancy in [0.5, 1] (same pair set): graph-replayed fwd+bwd
+    and fwd steps in FP32 compensated mode, and the FP64 oracle on sampled
+    centres."""
+    import oracle
+    occ = np.random.default_rng(17).uniform(0.5, 1.0, batch.n_atoms)
+    bo = gs.Batch(batch.atom_offsets, batch.pos, batch.species, batch.cell, batch.pbc, occ)
+    N, nf = batch.n_atoms, probes.n_features
+    db = g.DeviceBatch.from_batch(bo)
+    plan = g.GMPPlan.from_probes(probes, "fp32c")
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    nbf = g.build_neighbors(plan, db, ws, reverse=False)
+    G = torch.as_tensor(np.random.default_rng(7).standard_normal((N, nf)), device="cuda")
+    fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
+    fo = g.CapturedStep(plan, db, ws, nbf, backward=False)
+    for _ in range(warmup):
+        fb.replay()
+        fo.replay()
+    t_fb = _median_ms(fb.replay, steps, torch)
+    t_fo = _median_ms(fo.replay, steps, torch)
+    g.check_status(ws)
+    cs = np.sort(np.random.default_rng(19).choice(N, size=min(24, N), replace=False))
+    Fref = oracle.features(batch.structure(0), probes, centres=cs, occupancy=occ)
+    Fg = fb.F.double().cpu().numpy()[cs]
+    big = Fref > probes.tau
+    out = {"occupancy": "uniform [0.5, 1] on every atom", "pairs": int(nb.n_pairs), "fwd_bwd_ms": t_fb,
+           "fwd_ms": t_fo, "atoms_features_per_s_fwd_bwd": N * nf / (t_fb * 1e-3),
+           "max_rel_err": float(np.max(np.abs(Fg[big] - Fref[big]) / Fref[big])), "sampled_centres": len(cs)}
+    print(f"[bench] occupancies: fwd+bwd {t_fb:.3f} ms, fwd {t_fo:.3f} ms, max rel err {out['max_rel_err']:.2e}",
+          file=sys.stderr, flush=True)
+    del fb, fo, nb, nbf, ws, G, db
     torch.cuda.empty_cache()
     return out
 
@@ -440,6 +478,7 @@ def main():
     out["kernels_fp32w_ms_per_step"] = {k: round(v["ms_per_step"], 5) for k, v in kernel_profile("fp32w", True).items()}
     if not args.no_density:
         out["density_variant"] = density_variant(g, gs, torch, batch, probes, db)
+        out["occupancy_variant"] = occupancy_variant(g, gs, torch, batch, probes)
     if not args.no_batched:
         del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()

@@ -103,6 +103,11 @@ typedef struct {
   const double *cell;            /* [n_structs*9]; row m (entries 3m..3m+2) is lattice vector a_m */
   const uint8_t *pbc;            /* [n_structs]; bit k set = periodic along a_k; 0 = isolated
                                     (then the cell is ignored and may be zero) */
+  const double *occupancy;       /* [n_atoms] fractional site occupancies, or NULL (all 1):
+                                    disordered structures ("Overview"); atom j's density is
+                                    scaled by occupancy[j], a site shared by several species is
+                                    one entry per species at the same position; cutoffs and
+                                    neighbour lists do not depend on it; must be finite */
 } gmp_batch;
 
 /* Neighbour lists in canonical order.  For centre i, entries

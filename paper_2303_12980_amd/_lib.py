@@ -35,7 +35,7 @@ class ProbeDesc(ctypes.Structure):
 
 class BatchDesc(ctypes.Structure):
     _fields_ = [("n_structs", c_i32), ("n_atoms", c_i64), ("atom_offsets", c_vp), ("x", c_vp), ("y", c_vp),
-                ("z", c_vp), ("species", c_vp), ("cell", c_vp), ("pbc", c_vp)]
+                ("z", c_vp), ("species", c_vp), ("cell", c_vp), ("pbc", c_vp), ("occupancy", c_vp)]
 
 
 class NbrDesc(ctypes.Structure):

@@ -8,7 +8,8 @@
 //   coefficients of its gradient (Dx, Dy, Dz), so per pair
 //   v_{ijn} = grad_d sum_{s,l} c_{l,s}(q) Q_{i,s,l}(d)
 //          = sum_{s,l} [ 2 c'_{l,s}(q) Q_{i,s,l}(d) d + c_{l,s}(q) grad Q_{i,s,l}(d) ].
-//   dL/dR_j += v, dL/dR_i -= v, dL/da_m += (n_m - m_{j,m} + m_{i,m}) v.
+//   dL/dR_j += v, dL/dR_i -= v, dL/da_m += (n_m - m_{j,m} + m_{i,m}) v,
+//   v carrying the neighbour's occupancy factor (disordered structures).
 //   The local density of order -1 (F = |rho|) has W = G rho / |rho| on the
 //   degree-0 coefficient of its own cutoff slot, whose radial factor is
 //   sum_k B exp(-beta q).
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
       const int p = p0 + lane;
       const bool act = p < chi;
       const int32_t w = wb;
-      const double rjx = rb.x, rjy = rb.y, rjz = rb.z;
+      const double rjx = rb.x, rjy = rb.y, rjz = rb.z, occj = rb.w;  // w: occupancy of j
       rb = rw4[jc];
       wb = wc;
       jc = ii;
@@ -282,9 +283,9 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
       }
       if (act) {
         T *dst = vbuf + (size_t)(base + p) * 4;
-        dst[0] = (T)vx;
-        dst[1] = (T)vy;
-        dst[2] = (T)vz;
+        dst[0] = (T)(vx * occj);
+        dst[1] = (T)(vy * occj);
+        dst[2] = (T)(vz * occj);
         dst[3] = (T)0;
       }
     }

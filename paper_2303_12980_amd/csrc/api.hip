@@ -518,6 +518,7 @@ BatchDev to_dev(const gmp_batch *b) {
   d.species = b->species;
   d.cell = b->cell;
   d.pbc = b->pbc;
+  d.occ = b->occupancy;
   return d;
 }
 

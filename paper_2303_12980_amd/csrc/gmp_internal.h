@@ -109,6 +109,7 @@ struct BatchDev {
   const int32_t *species;
   const double *cell;
   const uint8_t *pbc;
+  const double *occ;       // [n_atoms] occupancies or null (all 1)
 };
 
 struct NbrDev {
@@ -188,6 +189,7 @@ __device__ inline void image_shift(const Cell9 &c, int n1, int n2, int n3, doubl
 // Wrapped position Rw_i = R_i - ((m1 a1 + m2 a2) + m3 a3) from the current
 // positions and lattice and the wrap indices of the neighbour build; the
 // same operation order as the build, so unchanged inputs give the same bits.
+// The fourth component carries the atom's occupancy (1 when none is given).
 __device__ inline double4 wrapped_position(const BatchDev &bt, const NbrDev &nb, int64_t i, int s) {
   double r[3] = {bt.x[i], bt.y[i], bt.z[i]};
   if (bt.pbc[s] & 7) {
@@ -199,7 +201,7 @@ __device__ inline double4 wrapped_position(const BatchDev &bt, const NbrDev &nb,
       r[c] = r[c] - t;
     }
   }
-  return make_double4(r[0], r[1], r[2], 0.0);
+  return make_double4(r[0], r[1], r[2], bt.occ ? bt.occ[i] : 1.0);
 }
 
 __device__ inline int shift_n(int32_t w, int k) { return (int)(int8_t)((uint32_t)w >> (8 * k)); }

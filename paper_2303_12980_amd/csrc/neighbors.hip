@@ -120,6 +120,7 @@ __global__ void k_wrap(BatchDev bt, const StructInfo *info, NbrDev nb, double *f
   const StructInfo &I = info[s];
   const double R[3] = {bt.x[i], bt.y[i], bt.z[i]};
   if (!(isfinite(R[0]) && isfinite(R[1]) && isfinite(R[2]))) atomicOr(status, ST_NONFINITE);
+  if (bt.occ && !isfinite(bt.occ[i])) atomicOr(status, ST_NONFINITE);
   int m[3] = {0, 0, 0};
   int b[3] = {0, 0, 0};
   double f3[3] = {0.0, 0.0, 0.0};

@@ -5,7 +5,10 @@
 // defines the probe as an MCSH angular probe times a Gaussian radial probe
 // and the density as per-element Gaussian primitives):
 //   mu_{i,l,s,abc} += c_{l,s,e_j}(q) P_abc(d),
-//   c_{l,s,e}(q) = sum_k A_{l,s,e,k} exp(-gamma_{s,e,k} q).
+//   c_{l,s,e}(q) = sum_k A_{l,s,e,k} exp(-gamma_{s,e,k} q),
+// each pair term scaled by the neighbour's occupancy (disordered structures;
+// 1 when none is given), which rides in the fourth component of its packed
+// wrapped position and multiplies the monomial recursion's seed.
 // P_abc is a homogeneous polynomial of degree l, so the kernel accumulates
 // the Cartesian moments  M_{i,s,m} = sum_j c_{deg m,s,e_j}(q_j) x^a y^b z^c
 // of every monomial m of each requested degree, and the norm kernel maps
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
     while (tb < S) {
       const int ta = tb, pa = pb;
       const int32_t w = wb;
-      const double rjx = rb.x, rjy = rb.y, rjz = rb.z;
+      const double rjx = rb.x, rjy = rb.y, rjz = rb.z, occj = rb.w;  // w: occupancy of j
       // advance the pipeline
       tb = tc; pb = pc; wb = wc;
       rb = rw4[jc];
@@ -264,6 +267,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
             c0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], exp_scaled(LDS ? tabl[o] : tabg[o], qv), c0);
           }
         }
+        c0 = c0 * (TR)occj;
         if constexpr (MODE == ACC_TWOSUM) acc.add(0, c0);
         else acc.v[0] += (double)c0;
       } else if (p < pass_end(ta)) {
@@ -292,7 +296,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         TM mono[NM];
         {
           const TM xv = (TM)dx, yv = (TM)dy, zv = (TM)dz;
-          mono[0] = (TM)1;
+          mono[0] = (TM)occj;  // the occupancy scales every monomial of the pair
 #pragma unroll
           for (int m = 1; m < NM; ++m) {
             const TM v = kMT.var[m] == 0 ? xv : (kMT.var[m] == 1 ? yv : zv);

@@ -125,7 +125,9 @@ class GMPPlan:
 class DeviceBatch:
     """Packed CSR batch resident on the GPU (wraps gmp_batch)."""
 
-    def __init__(self, atom_offsets, pos, species, cell, pbc, device="cuda"):
+    def __init__(self, atom_offsets, pos, species, cell, pbc, device="cuda", occupancy=None):
+        """occupancy: per-atom fractional site occupancies (disordered
+        structures), or None for all 1."""
         self.atom_offsets = torch.as_tensor(np.asarray(atom_offsets, np.int64), device=device)
         pos = torch.as_tensor(np.asarray(pos, np.float64), device=device)
         self.xyz = pos.t().contiguous()  # [3, N] SoA
@@ -134,10 +136,15 @@ class DeviceBatch:
         self.pbc = torch.as_tensor(np.asarray(pbc, np.uint8), device=device)
         self.n_structs = int(self.atom_offsets.numel() - 1)
         self.n_atoms = int(self.species.numel())
+        self.occupancy = None
+        if occupancy is not None:
+            self.occupancy = torch.as_tensor(np.asarray(occupancy, np.float64), device=device).contiguous()
+            if self.occupancy.shape != (self.n_atoms,):
+                raise ValueError("occupancy must have one entry per atom")
 
     @classmethod
     def from_batch(cls, b, device="cuda"):
-        return cls(b.atom_offsets, b.pos, b.species, b.cell, b.pbc, device)
+        return cls(b.atom_offsets, b.pos, b.species, b.cell, b.pbc, device, getattr(b, "occupancy", None))
 
     def structure(self, s: int, a0: int, a1: int) -> "DeviceBatch":
         """One-structure batch viewing this batch's memory (atoms a0:a1 of
@@ -149,6 +156,7 @@ class DeviceBatch:
         v.species = self.species[a0:a1]
         v.cell = self.cell[s:s + 1]
         v.pbc = self.pbc[s:s + 1]
+        v.occupancy = None if self.occupancy is None else self.occupancy[a0:a1]
         v.n_structs, v.n_atoms = 1, a1 - a0
         return v
 
@@ -157,7 +165,8 @@ class DeviceBatch:
         cell = self.cell if cell is None else cell
         return _lib.BatchDesc(self.n_structs, self.n_atoms, self.atom_offsets.data_ptr(), xyz[0].data_ptr(),
                               xyz[1].data_ptr(), xyz[2].data_ptr(), self.species.data_ptr(), cell.data_ptr(),
-                              self.pbc.data_ptr())
+                              self.pbc.data_ptr(),
+                              self.occupancy.data_ptr() if self.occupancy is not None else 0)
 
 
 class Workspace:
@@ -364,7 +373,8 @@ class CapturedStep:
             self._run()
         # the graph holds raw addresses: keep every buffer it touches alive
         self._held = (ws.buf, nb.offsets, nb.j, nb.shift, nb.bucket_start, nb.sigma_end, nb.wrap, nb.rw,
-                      nb.reverse, batch.xyz, batch.cell, batch.species, batch.atom_offsets, batch.pbc)
+                      nb.reverse, batch.xyz, batch.cell, batch.species, batch.atom_offsets, batch.pbc,
+                      batch.occupancy)
 
     def _run(self):
         L = _lib.load()
