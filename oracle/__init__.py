@@ -70,6 +70,17 @@ def lib():
             L.oracle_grad.restype = c_int
             L.oracle_loss_frozen.argtypes = [c_int, dp, ip, dp, *probe_args, lp, ip, ip, dp, dp, dp, dp]
             L.oracle_loss_frozen.restype = c_int
+            L.oracle_point_neighbors.argtypes = [c_int, dp, ip, dp, c_int, c_int, dp, dp, c_i64,
+                                                 ip, ip, dp, ip, ip]
+            L.oracle_point_neighbors.restype = c_i64
+            L.oracle_point_features.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, dp, dp, dp, dp]
+            L.oracle_point_features.restype = c_int
+            L.oracle_point_grad.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, dp, dp, dp, dp, dp,
+                                            dp, dp]
+            L.oracle_point_grad.restype = c_int
+            L.oracle_point_loss_frozen.argtypes = [c_int, dp, ip, dp, *probe_args, c_int, dp, lp, ip, ip, dp,
+                                                   dp, dp, dp]
+            L.oracle_point_loss_frozen.restype = c_int
             L.oracle_solid_harmonic.argtypes = [c_int, c_int, c_int, c_int, dp, dp, dp]
             L.oracle_solid_harmonic.restype = None
             L.oracle_radial.argtypes = [c_int, c_dbl, c_int, dp, dp, c_int, dp, dp]
@@ -314,3 +325,116 @@ def components(l: int):
         for b in range(l - a, -1, -1):
             out.append((a, b, l - a - b))
     return out
+
+
+# ---------------------------------------------------------------- reference points
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def point_neighbors(struct, rc2, point):
+    """Canonical neighbour list of one reference point (same dict as neighbors())."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    rc2, rp = _d(rc2)
+    pt, ptp = _d(np.asarray(point).reshape(3))
+    st = ctypes.c_int32(0)
+    cap = 1024
+    while True:
+        j = np.zeros(cap, np.int32); n = np.zeros((cap, 3), np.int32)
+        q = np.zeros(cap); sh = np.zeros(cap, np.int32)
+        cnt = lib().oracle_point_neighbors(len(pos), pp, sp, cp, int(pbc), len(rc2), rp, ptp, cap,
+                                           j.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(q),
+                                           sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(st))
+        _check(st.value)
+        if cnt <= cap:
+            return dict(j=j[:cnt], n=n[:cnt], q=q[:cnt], shell=sh[:cnt], e=np.asarray(spec)[j[:cnt]])
+        cap = int(cnt)
+
+
+def point_features(struct, probes, points, with_mu: bool = False, occupancy=None):
+    """F [n_points, nf] (and mu [n_points, nc]) at reference points [n_points, 3]."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    pts, ptp = _d(np.asarray(points, np.float64).reshape(-1, 3))
+    keep, a = _probe_args(probes)
+    nf = n_features(probes.orders, len(probes.sigmas))
+    F = np.zeros((len(pts), nf))
+    mu = np.zeros((len(pts), n_components(probes.orders, len(probes.sigmas)))) if with_mu else None
+    occ, op = _occ(occupancy, len(pos))
+    _check(lib().oracle_point_features(len(pos), pp, sp, cp, int(pbc), *a, len(pts), ptp, _dp(F),
+                                       _dp(mu) if with_mu else None, op))
+    return (F, mu) if with_mu else F
+
+
+def point_features_batch(batch, probes, point_offsets, points, with_mu=False):
+    """Features at the reference points of every structure of a batch
+    (points of structure s: points[point_offsets[s]:point_offsets[s+1]])."""
+    Fs, mus = [], []
+    occ = getattr(batch, "occupancy", None)
+    for s in range(batch.n_structs):
+        a0, a1 = int(batch.atom_offsets[s]), int(batch.atom_offsets[s + 1])
+        r = point_features(batch.structure(s), probes, points[point_offsets[s]:point_offsets[s + 1]],
+                           with_mu=with_mu, occupancy=None if occ is None else occ[a0:a1])
+        if with_mu:
+            Fs.append(r[0]); mus.append(r[1])
+        else:
+            Fs.append(r)
+    F = np.concatenate(Fs, axis=0)
+    return (F, np.concatenate(mus, axis=0)) if with_mu else F
+
+
+def point_grad(struct, probes, points, G, occupancy=None):
+    """dL/dR [n,3], dL/dP [n_points,3], dL/dcell [3,3] of L = sum G*F(points), plus F."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    pts, ptp = _d(np.asarray(points, np.float64).reshape(-1, 3))
+    keep, a = _probe_args(probes)
+    G, gp = _d(G)
+    gpos = np.zeros((len(pos), 3)); gpts = np.zeros((len(pts), 3)); gcell = np.zeros((3, 3))
+    F = np.zeros((len(pts), n_features(probes.orders, len(probes.sigmas))))
+    occ, op = _occ(occupancy, len(pos))
+    _check(lib().oracle_point_grad(len(pos), pp, sp, cp, int(pbc), *a, len(pts), ptp, gp, _dp(gpos), _dp(gpts),
+                                   _dp(gcell), _dp(F), op))
+    return gpos, gpts, gcell, F
+
+
+def point_frozen_pairs(struct, probes, points):
+    """Pair lists of the reference points in raw-position form (j, n~, q)."""
+    pos, spec, cell, pbc = struct
+    rc2 = cutoffs(probes)
+    _, m = wrap(pos, cell, pbc)
+    pts = np.asarray(points, np.float64).reshape(-1, 3)
+    _, pm = wrap(pts, cell, pbc)
+    po = [0]; pj = []; pn = []; pq = []
+    for r in range(len(pts)):
+        nb = point_neighbors(struct, rc2, pts[r])
+        pj.append(nb["j"])
+        pn.append(nb["n"] - m[nb["j"]] + pm[r])
+        pq.append(nb["q"])
+        po.append(po[-1] + len(nb["j"]))
+    return (np.asarray(po, np.int64), np.concatenate(pj).astype(np.int32),
+            np.concatenate(pn).reshape(-1, 3).astype(np.int32), np.concatenate(pq))
+
+
+def point_loss_frozen(struct, probes, points, G, pairs, occupancy=None):
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    pts, ptp = _d(np.asarray(points, np.float64).reshape(-1, 3))
+    keep, a = _probe_args(probes)
+    po, pop = _l(pairs[0]); pj, pjp = _i(pairs[1]); pn, pnp = _i(pairs[2]); pq, pqp = _d(pairs[3])
+    G, gp = _d(G)
+    out = ctypes.c_double(0.0)
+    occ, op = _occ(occupancy, len(pos))
+    _check(lib().oracle_point_loss_frozen(len(pos), pp, sp, cp, *a, len(pts), ptp, pop, pjp, pnp, pqp, gp,
+                                          ctypes.byref(out), op))
+    return out.value

@@ -345,13 +345,13 @@ static int image_reach(const double *cell, int pbc, double rcmax, int nimg[3]) {
   return OR_OK;
 }
 
-/* collect the sorted neighbour list of centre i into a malloc'd array */
-static int64_t collect(const sys_t *S, int i, int n_sigmas, const double *rc2, pair_t **out) {
+/* sorted neighbour list of a centre at wrapped position Ri (an atom's or a
+ * reference point's) into a malloc'd array */
+static int64_t collect_at(const sys_t *S, const double *Ri, int n_sigmas, const double *rc2, pair_t **out) {
   double rcmax2 = 0.0;
   for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
   int64_t cap = 256, n = 0;
   pair_t *buf = (pair_t *)malloc(sizeof(pair_t) * cap);
-  const double *Ri = S->rw + 3 * i;
   const double *a1 = S->cell, *a2 = S->cell + 3, *a3 = S->cell + 6;
   for (int n1 = -S->nimg[0]; n1 <= S->nimg[0]; ++n1)
     for (int n2 = -S->nimg[1]; n2 <= S->nimg[1]; ++n2)
@@ -384,6 +384,10 @@ static int64_t collect(const sys_t *S, int i, int n_sigmas, const double *rc2, p
   qsort(buf, (size_t)n, sizeof(pair_t), pair_cmp);
   *out = buf;
   return n;
+}
+
+static int64_t collect(const sys_t *S, int i, int n_sigmas, const double *rc2, pair_t **out) {
+  return collect_at(S, S->rw + 3 * i, n_sigmas, rc2, out);
 }
 
 static int make_sys(sys_t *S, int n_atoms, const double *pos, const int32_t *species,
@@ -672,14 +676,11 @@ int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
  * d = R_j - R_i + pn.cell) and base squared distances pq deciding which
  * slots use each pair (q_base <= rc2 of the slot).  occ as in oracle_features.
  */
-int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
-                       const double *cell,
-                       int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
-                       int n_elements, const int32_t *prim_offsets, const double *B,
-                       const double *beta, double tau,
-                       const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
-                       const double *G, double *L_out, const double *occ) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+static int loss_frozen_impl(const probes_t *Pp, const double *pos, const int32_t *species,
+                            const double *cell, int n_centres, const double *cpos,
+                            const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
+                            const double *G, double *L_out, const double *occ) {
+  probes_t P = *Pp;
   int st = check_probes(&P);
   if (st) return st;
   const int ns = n_slots(&P);
@@ -691,7 +692,7 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
   double L = 0.0;
   double *mu = (double *)malloc(sizeof(double) * (size_t)nc);
   double *Fi = (double *)malloc(sizeof(double) * nf);
-  for (int i = 0; i < n_atoms; ++i) {
+  for (int i = 0; i < n_centres; ++i) {
     memset(mu, 0, sizeof(double) * (size_t)nc);
     for (int64_t g = po[i]; g < po[i + 1]; ++g) {
       int j = pj[g];
@@ -700,7 +701,7 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
       for (int c = 0; c < 3; ++c) {
         double sh = (double)pn[3 * g] * cell[c] + (double)pn[3 * g + 1] * cell[3 + c] +
                     (double)pn[3 * g + 2] * cell[6 + c];
-        pp.d[c] = (pos[3 * j + c] - pos[3 * i + c]) + sh;
+        pp.d[c] = (pos[3 * j + c] - cpos[3 * i + c]) + sh;
       }
       pp.q = (pp.d[0] * pp.d[0] + pp.d[1] * pp.d[1]) + pp.d[2] * pp.d[2];
       /* membership from the base configuration, value from the current one */
@@ -712,6 +713,170 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
   free(mu); free(Fi); free(rc2);
   *L_out = L;
   return OR_OK;
+}
+
+int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
+                       const double *cell,
+                       int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                       int n_elements, const int32_t *prim_offsets, const double *B,
+                       const double *beta, double tau,
+                       const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
+                       const double *G, double *L_out, const double *occ) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  return loss_frozen_impl(&P, pos, species, cell, n_atoms, pos, po, pj, pn, pq, G, L_out, occ);
+}
+
+/* ------------------------------------------------------------------ */
+/* reference points                                                    */
+/* ------------------------------------------------------------------ */
+/*
+ * Features at reference points instead of atoms (section "Overview": any set
+ * of positions inside the system).  A point r is a centre that is not an
+ * atom: its wrapped position Pw_r and wrap indices m_r follow the atoms'
+ * rule, its pairs are every atom image (j, n) with q <= max rc^2,
+ * d = (Rw_j - Pw_r) + s(n), in the canonical order, and its features follow
+ * the same formulas (a point has no self term of its own).  In the gradient
+ * the point is a variable of its own:
+ *   dL/dR_j += v,  dL/dP_r -= v,  dL/da_m += (n_m - m_j,m + m_r,m) v.
+ */
+typedef struct {
+  sys_t S; double *rw; int32_t *m;   /* atoms */
+  double *prw; int32_t *pm;          /* points, wrapped */
+  double *rc2; int ns;
+} point_sys_t;
+
+static void point_sys_free(point_sys_t *Q) {
+  free(Q->rw); free(Q->m); free(Q->prw); free(Q->pm); free(Q->rc2);
+}
+
+static int point_sys(point_sys_t *Q, const probes_t *P, int n_atoms, const double *pos,
+                     const int32_t *species, const double *cell, int pbc, int n_points,
+                     const double *points) {
+  memset(Q, 0, sizeof(*Q));
+  int st = check_probes(P);
+  if (st) return st;
+  for (int i = 0; i < n_atoms; ++i)
+    if (species[i] < 0 || species[i] >= P->n_elements) return OR_E_INVALID;
+  Q->ns = n_slots(P);
+  Q->rc2 = (double *)malloc(sizeof(double) * Q->ns);
+  st = slot_cutoffs(P, Q->rc2);
+  double rcmax2 = 0.0;
+  for (int s = 0; s < Q->ns; ++s) if (Q->rc2[s] > rcmax2) rcmax2 = Q->rc2[s];
+  if (!st) st = make_sys(&Q->S, n_atoms, pos, species, cell, pbc, rcmax2, &Q->rw, &Q->m);
+  if (st) { free(Q->rc2); Q->rc2 = NULL; return st; }
+  Q->prw = (double *)malloc(sizeof(double) * 3 * (n_points > 0 ? n_points : 1));
+  Q->pm = (int32_t *)malloc(sizeof(int32_t) * 3 * (n_points > 0 ? n_points : 1));
+  st = oracle_wrap(n_points, points, cell, pbc, Q->prw, Q->pm);
+  if (st) point_sys_free(Q);
+  return st;
+}
+
+/* canonical list of one reference point (n_slots, rc2 as in oracle_neighbors) */
+int64_t oracle_point_neighbors(int n_atoms, const double *pos, const int32_t *species,
+                               const double *cell, int pbc, int n_slots_, const double *rc2,
+                               const double *point, int64_t cap, int32_t *out_j, int32_t *out_n,
+                               double *out_q, int32_t *out_shell, int32_t *status) {
+  double rcmax2 = 0.0;
+  for (int s = 0; s < n_slots_; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw; int32_t *m;
+  *status = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (*status) return 0;
+  double prw[3]; int32_t pm[3];
+  *status = oracle_wrap(1, point, cell, pbc, prw, pm);
+  if (*status) { free(rw); free(m); return 0; }
+  pair_t *Pl;
+  int64_t n = collect_at(&S, prw, n_slots_, rc2, &Pl);
+  for (int64_t k = 0; k < n && k < cap; ++k) {
+    out_j[k] = Pl[k].j;
+    out_n[3 * k] = Pl[k].n[0]; out_n[3 * k + 1] = Pl[k].n[1]; out_n[3 * k + 2] = Pl[k].n[2];
+    out_q[k] = Pl[k].q; out_shell[k] = Pl[k].shell;
+  }
+  free(Pl); free(rw); free(m);
+  return n;
+}
+
+/* F [n_points][nf] and optionally mu [n_points][nc] at the reference points */
+int oracle_point_features(int n_atoms, const double *pos, const int32_t *species,
+                          const double *cell, int pbc,
+                          int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                          int n_elements, const int32_t *prim_offsets, const double *B,
+                          const double *beta, double tau,
+                          int n_points, const double *points, double *F, double *mu, const double *occ) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  point_sys_t Q;
+  int st = point_sys(&Q, &P, n_atoms, pos, species, cell, pbc, n_points, points);
+  if (st) return st;
+  Q.S.occ = occ;
+  const int nc = total_comps(&P), nf = total_feats(&P);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int r = 0; r < n_points; ++r) {
+    pair_t *pairs;
+    int64_t np = collect_at(&Q.S, Q.prw + 3 * r, Q.ns, Q.rc2, &pairs);
+    double *mu_r = (double *)malloc(sizeof(double) * (size_t)nc);
+    centre_features(&P, pairs, np, Q.rc2, mu_r, F + (size_t)r * nf);
+    if (mu) memcpy(mu + (size_t)r * nc, mu_r, sizeof(double) * (size_t)nc);
+    free(mu_r); free(pairs);
+  }
+  point_sys_free(&Q);
+  return OR_OK;
+}
+
+/* gradient of L = sum G F over the points' features: grad_pos [n_atoms*3],
+ * grad_points [n_points*3], grad_cell [9]; F_out [n_points*nf] optional */
+int oracle_point_grad(int n_atoms, const double *pos, const int32_t *species,
+                      const double *cell, int pbc,
+                      int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                      int n_elements, const int32_t *prim_offsets, const double *B,
+                      const double *beta, double tau,
+                      int n_points, const double *points, const double *G, double *grad_pos,
+                      double *grad_points, double *grad_cell, double *F_out, const double *occ) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  point_sys_t Q;
+  int st = point_sys(&Q, &P, n_atoms, pos, species, cell, pbc, n_points, points);
+  if (st) return st;
+  Q.S.occ = occ;
+  const int nc = total_comps(&P), nf = total_feats(&P);
+  memset(grad_pos, 0, sizeof(double) * 3 * n_atoms);
+  memset(grad_points, 0, sizeof(double) * 3 * n_points);
+  memset(grad_cell, 0, sizeof(double) * 9);
+  double *mu = (double *)malloc(sizeof(double) * (size_t)nc);
+  double *W = (double *)malloc(sizeof(double) * (size_t)nc);
+  double *Fr = (double *)malloc(sizeof(double) * nf);
+  for (int r = 0; r < n_points; ++r) {
+    pair_t *pairs;
+    int64_t np = collect_at(&Q.S, Q.prw + 3 * r, Q.ns, Q.rc2, &pairs);
+    centre_features(&P, pairs, np, Q.rc2, mu, Fr);
+    if (F_out) memcpy(F_out + (size_t)r * nf, Fr, sizeof(double) * nf);
+    make_W(&P, mu, Fr, G + (size_t)r * nf, W);
+    for (int64_t p = 0; p < np; ++p) {
+      double v[3];
+      pair_v(&P, pairs + p, Q.rc2, W, v);
+      int j = pairs[p].j;
+      for (int k = 0; k < 3; ++k) { grad_pos[3 * j + k] += v[k]; grad_points[3 * r + k] -= v[k]; }
+      for (int a = 0; a < 3; ++a) {
+        double nt = (double)(pairs[p].n[a] - Q.m[3 * j + a] + Q.pm[3 * r + a]);
+        for (int k = 0; k < 3; ++k) grad_cell[3 * a + k] += nt * v[k];
+      }
+    }
+    free(pairs);
+  }
+  free(mu); free(W); free(Fr);
+  point_sys_free(&Q);
+  return OR_OK;
+}
+
+/* L over a frozen pair set of reference points (pairs as in
+ * oracle_loss_frozen, d = R_j - P_r + pn.cell) */
+int oracle_point_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
+                             const double *cell,
+                             int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                             int n_elements, const int32_t *prim_offsets, const double *B,
+                             const double *beta, double tau, int n_points, const double *points,
+                             const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
+                             const double *G, double *L_out, const double *occ) {
+  (void)n_atoms;
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  return loss_frozen_impl(&P, pos, species, cell, n_points, points, po, pj, pn, pq, G, L_out, occ);
 }
 
 /* rc^2 of every slot (the sigmas, then the density when order -1 is requested) */
