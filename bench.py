@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads (512 structures, 1e5 atoms)")
     ap.add_argument("--no-density", action="store_true",
-                    help="skip the order -1 (local density) and occupancy (disordered) variants")
+                    help="skip the order -1 (local density), occupancy (disordered) and reference-point variants")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
@@ -196,6 +196,45 @@ def occupancy_variant(g, gs, torch, batch, probes, steps=10, warmup=3):
     print(f"[bench] occupancies: fwd+bwd {t_fb:.3f} ms, fwd {t_fo:.3f} ms, max rel err {out['max_rel_err']:.2e}",
           file=sys.stderr, flush=True)
     del fb, fo, nb, nbf, ws, G, db
+    torch.cuda.empty_cache()
+    return out
+
+
+def points_variant(g, gs, torch, batch, probes, steps=10, warmup=3):
+    """Features at reference points of the 4096-atom cell: a 16x16x16 grid
+    of points (cell centres of a regular fractional grid) as the centres;
+    graph-replayed fwd+bwd (gradients with respect to atoms, points and
+    cell) and fwd steps in FP32 compensated mode, and the FP64 oracle on
+    sampled points."""
+    import oracle
+    cell = batch.cell[0]
+    f = (np.stack(np.meshgrid(*[np.arange(16)] * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5) / 16.0
+    pts = f @ cell
+    M, nf = len(pts), probes.n_features
+    db = g.DeviceBatch.from_batch(batch).with_points(pts, [0, M])
+    plan = g.GMPPlan.from_probes(probes, "fp32c")
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    G = torch.as_tensor(np.random.default_rng(7).standard_normal((M, nf)), device="cuda")
+    fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
+    fo = g.CapturedStep(plan, db, ws, nb, backward=False)
+    for _ in range(warmup):
+        fb.replay()
+        fo.replay()
+    t_fb = _median_ms(fb.replay, steps, torch)
+    t_fo = _median_ms(fo.replay, steps, torch)
+    g.check_status(ws)
+    cs = np.sort(np.random.default_rng(23).choice(M, size=24, replace=False))
+    Fref = oracle.point_features(batch.structure(0), probes, pts[cs])
+    Fg = fb.F.double().cpu().numpy()[cs]
+    big = Fref > probes.tau
+    out = {"points": "16x16x16 grid in the 40 A cell", "n_points": M, "pairs": int(nb.n_pairs),
+           "fwd_bwd_ms": t_fb, "fwd_ms": t_fo, "points_features_per_s_fwd_bwd": M * nf / (t_fb * 1e-3),
+           "points_features_per_s_fwd": M * nf / (t_fo * 1e-3),
+           "max_rel_err": float(np.max(np.abs(Fg[big] - Fref[big]) / Fref[big])), "sampled_points": len(cs)}
+    print(f"[bench] reference points: fwd+bwd {t_fb:.3f} ms, fwd {t_fo:.3f} ms, max rel err {out['max_rel_err']:.2e}",
+          file=sys.stderr, flush=True)
+    del fb, fo, nb, ws, G, db
     torch.cuda.empty_cache()
     return out
 
@@ -479,6 +518,7 @@ def main():
     if not args.no_density:
         out["density_variant"] = density_variant(g, gs, torch, batch, probes, db)
         out["occupancy_variant"] = occupancy_variant(g, gs, torch, batch, probes)
+        out["points_variant"] = points_variant(g, gs, torch, batch, probes)
     if not args.no_batched:
         del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()

@@ -108,9 +108,20 @@ typedef struct {
                                     scaled by occupancy[j], a site shared by several species is
                                     one entry per species at the same position; cutoffs and
                                     neighbour lists do not depend on it; must be finite */
+  /* Reference points ("Overview": features at any set of positions inside
+   * each structure instead of at its atoms).  point_offsets == NULL: the
+   * centres are the atoms.  Otherwise the centres are the n_points points
+   * (points of structure s: [point_offsets[s], point_offsets[s+1])), every
+   * per-centre array below is per point, the neighbours are the atoms, a
+   * point has no self term of its own, and the backward differentiates
+   * with respect to atoms and points. */
+  int64_t n_points;
+  const int64_t *point_offsets;  /* [n_structs+1] or NULL */
+  const double *px, *py, *pz;    /* [n_points] Cartesian coordinates, Angstrom (SoA) */
 } gmp_batch;
 
-/* Neighbour lists in canonical order.  For centre i, entries
+/* Neighbour lists in canonical order; n_centres = n_atoms, or n_points
+ * with reference points, and n_total = n_atoms (+ n_points).  For centre i, entries
  * [offsets[i], offsets[i+1]) are sorted by (shell, species of j, j, n1, n2, n3)
  * where shell(q) = number of cutoff slots with rc^2 < q, so the pairs each
  * slot uses (q <= its rc^2) are a prefix of the list.  Bucket
@@ -118,17 +129,20 @@ typedef struct {
 typedef struct {
   int64_t capacity;              /* [host] entries allocated in j, shift, reverse */
   int64_t n_pairs;               /* [host] set by gmp_build_neighbors (sync mode) */
-  int64_t *offsets;              /* [n_atoms+1] */
+  int64_t *offsets;              /* [n_centres+1] */
   int32_t *j;                    /* [capacity] neighbour atom (global index) */
   int32_t *shift;                /* [capacity] bytes (n1, n2, n3, species_j), n_k signed, little endian;
                                     d = (Rw_j - Rw_i) + n1 a1 + n2 a2 + n3 a3 with wrapped positions */
-  int32_t *bucket_start;         /* [n_atoms*(n_slots*n_elements+1)] bucket starts, local to offsets[i];
-                                    the last entry is the list length */
-  int32_t *sigma_end;            /* [n_atoms*n_slots] length of the prefix cutoff slot s uses, local */
-  int32_t *wrap;                 /* [n_atoms*3] m_i: Rw_i = R_i - (m1 a1 + m2 a2 + m3 a3) */
-  double *rw;                    /* [3*n_atoms] wrapped positions, SoA (x block, y block, z block) */
-  int32_t *reverse;              /* [capacity] or NULL: local index of (j, i, -n) in j's list;
-                                    required by gmp_features_backward */
+  int32_t *bucket_start;         /* [n_centres*(n_slots*n_elements+1)] bucket starts, local to
+                                    offsets[i]; the last entry is the list length */
+  int32_t *sigma_end;            /* [n_centres*n_slots] length of the prefix cutoff slot s uses, local */
+  int32_t *wrap;                 /* [n_total*3] m_i: Rw_i = R_i - (m1 a1 + m2 a2 + m3 a3); atoms, then
+                                    points */
+  double *rw;                    /* [3*n_total] wrapped positions, SoA (x block, y block, z block) */
+  int32_t *reverse;              /* [capacity] or NULL; required by gmp_features_backward.  Atoms as
+                                    centres: local index of (j, i, -n) in j's list.  Reference
+                                    points: the pair indices ordered by neighbour atom (stable), the
+                                    order in which the backward gathers each atom's pairs */
   int64_t max_list;              /* [host] longest list of the last synchronous build (set by it); a
                                     no-sync build sizes its in-LDS sort for this many entries (0: the
                                     largest supported) and flags a longer list in the status word */
@@ -175,9 +189,9 @@ gmp_status gmp_plan_get_tuning(const gmp_plan *plan, gmp_tuning *out);
 gmp_status gmp_plan_set_tuning(gmp_plan *plan, const gmp_tuning *t);
 
 /* [host] bytes of workspace needed by every entry point for a batch of this
- * size and a neighbour capacity. */
+ * size (n_points: reference points, 0 without) and a neighbour capacity. */
 gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n_atoms,
-                              int64_t capacity, size_t *bytes);
+                              int64_t n_points, int64_t capacity, size_t *bytes);
 
 /* Lattice wrap, cell-list binning, neighbour count, fill and canonical
  * sort; also the reverse-pair index when nbrs->reverse is not NULL.
@@ -213,7 +227,7 @@ gmp_status gmp_build_lists(const gmp_plan *plan, const gmp_batch *batch, gmp_nei
 gmp_status gmp_build_reverse(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs, void *ws,
                              size_t ws_bytes, void *stream);
 
-/* Features [n_atoms * n_features] (float for the FP32 modes, double for
+/* Features [n_centres * n_features] (float for the FP32 modes, double for
  * GMP_FP64), order-major: features[i*n_features + f_o + s] with
  * f_o = sum over the orders before o of n_sigmas (1 for order -1), and the
  * single feature of order -1 at f_o.
@@ -222,7 +236,7 @@ gmp_status gmp_build_reverse(const gmp_plan *plan, const gmp_batch *batch, gmp_n
  * build (d = R_j - R_i + (n - m_j + m_i) . cell), so moving atoms or the
  * cell after the build gives the features of the same pairs at the new
  * geometry (bitwise the build's geometry when nothing moved).
- * components (optional, FP64) [n_atoms * n_components] laid out
+ * components (optional, FP64) [n_centres * n_components] laid out
  * (order, sigma, component) with components of order l in the order
  * (a descending, then b descending), and the signed density rho_i as the
  * one component of order -1; required later by the backward. */
@@ -230,11 +244,12 @@ gmp_status gmp_features(const gmp_plan *plan, const gmp_batch *batch, const gmp_
                         void *features, double *components, void *ws, size_t ws_bytes,
                         void *stream);
 
-/* Adjoint: given G = dL/dF [n_atoms * n_features] (same type as features),
- * writes grad_pos [3 * n_atoms] (FP64, SoA: x block, y block, z block) and,
- * when grad_cell is not NULL, grad_cell [n_structs * 9] (FP64, row m = dL/da_m),
- * with Cartesian input positions held fixed and the pair set held fixed.
- * Needs the components and features of the forward and nbrs->reverse. */
+/* Adjoint: given G = dL/dF [n_centres * n_features] (same type as features),
+ * writes grad_pos [3 * n_total] (FP64, SoA: x block, y block, z block; each
+ * block the atoms, then the reference points) and, when grad_cell is not
+ * NULL, grad_cell [n_structs * 9] (FP64, row m = dL/da_m), with Cartesian
+ * input positions held fixed and the pair set held fixed.  Needs the
+ * components and features of the forward and nbrs->reverse. */
 gmp_status gmp_features_backward(const gmp_plan *plan, const gmp_batch *batch,
                                  const gmp_neighbors *nbrs, const double *components,
                                  const void *features, const void *grad_features,

@@ -35,7 +35,8 @@ class ProbeDesc(ctypes.Structure):
 
 class BatchDesc(ctypes.Structure):
     _fields_ = [("n_structs", c_i32), ("n_atoms", c_i64), ("atom_offsets", c_vp), ("x", c_vp), ("y", c_vp),
-                ("z", c_vp), ("species", c_vp), ("cell", c_vp), ("pbc", c_vp), ("occupancy", c_vp)]
+                ("z", c_vp), ("species", c_vp), ("cell", c_vp), ("pbc", c_vp), ("occupancy", c_vp),
+                ("n_points", c_i64), ("point_offsets", c_vp), ("px", c_vp), ("py", c_vp), ("pz", c_vp)]
 
 
 class NbrDesc(ctypes.Structure):
@@ -78,7 +79,7 @@ def load():
     L.gmp_plan_get_tuning.restype = c_i32
     L.gmp_plan_set_tuning.argtypes = [c_vp, ctypes.POINTER(Tuning)]
     L.gmp_plan_set_tuning.restype = c_i32
-    L.gmp_workspace_size.argtypes = [c_vp, c_i32, c_i64, c_i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.gmp_workspace_size.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, ctypes.POINTER(ctypes.c_size_t)]
     L.gmp_workspace_size.restype = c_i32
     L.gmp_build_neighbors.argtypes = [c_vp, ctypes.POINTER(BatchDesc), ctypes.POINTER(NbrDesc),
                                       ctypes.POINTER(c_i64), c_vp, ctypes.c_size_t, c_vp]

@@ -86,7 +86,7 @@ def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backw
         return dict(cache[key], key=key, cached=True)
     if os.environ.get("GMP_AUTOTUNE", "1") == "0":
         return dict(tuning=plan.get_tuning(), ms=None, key=key, cached=False, tried=[])
-    G = torch.ones((batch.n_atoms, plan.n_features), dtype=plan.dtype, device=batch.species.device)
+    G = torch.ones((batch.n_centres, plan.n_features), dtype=plan.dtype, device=batch.species.device)
     tried = []
     best = None
     t0 = time.time()

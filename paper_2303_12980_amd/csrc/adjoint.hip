@@ -44,12 +44,13 @@ __host__ __device__ constexpr int coef_m(int lmax) { return round4(nmono(lmax));
 __host__ __device__ constexpr int coef_d(int lmax) { return round4(nmono(lmax - 1)); }
 __host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax) + 3 * coef_d(lmax); }
 
-// One wavefront per centre.
+// One wavefront per index: centres get their coefficients, every index
+// (atoms, and reference points) its structure and packed position.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev nb, const double *components,
                                                   const void *grad_features, void *bcoef, double4 *rw4,
                                                   int32_t *astruct, unsigned long long *counter) {
-  const int64_t N = bt.n_atoms;
+  const int64_t N = n_centres(bt);
   using T = typename Real<F64>::T;
   extern __shared__ double lds_b[];
   const int w = threadIdx.x / kWave, lane = lane_id();
@@ -61,8 +62,8 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   const bool live = i < N;
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0ull;  // work items of the pair kernel
   // AoS wrapped position (one 32-byte gather per neighbour in the pair kernel)
-  if (live && lane == 0) {
-    const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  if (i < n_total(bt) && lane == 0) {
+    const int st = struct_of_index(bt, i);
     astruct[i] = st;
     rw4[i] = wrapped_position(bt, nb, i, st);
   }
@@ -171,10 +172,11 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
       for (int t = lane; t < S * NB; t += kWave) bcoef[t] = src[t];
       wave_lds_sync();
     }
-    const int st = astruct[i];
+    const int64_t g = centre_base(bt) + i;  // index of the centre (atom, or reference point)
+    const int st = astruct[g];
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
-    const double4 ri4 = rw4[i];
+    const double4 ri4 = rw4[g];
     const double rix = ri4.x, riy = ri4.y, riz = ri4.z;
     const int64_t base = nb.offsets[i];
     const int cnt = (int)(nb.offsets[i + 1] - base);
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
     // sigma prefix ends, one per lane (lane s <-> sigma s)
     const int end_lane = lane < S ? nb.sigma_end[i * S + lane] : 0;
     // pipeline: (jb, wb, rb) current step, (jc, wc) the step after
-    const int32_t ii = (int32_t)i;
+    const int32_t ii = (int32_t)g;  // idle lanes read the centre's own packed position
     int32_t jb = ii, wb = 0, jc = ii, wc = 0;
     if (clo + lane < chi) { jb = nb.j[base + clo + lane]; wb = nb.shift[base + clo + lane]; }
     if (clo + kWave + lane < chi) { jc = nb.j[base + clo + kWave + lane]; wc = nb.shift[base + clo + kWave + lane]; }
@@ -348,12 +350,97 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BatchDev bt, NbrDev nb, cons
   }
 }
 
-// One wavefront per structure: fixed-order sum of per-atom cell partials.
-__global__ __launch_bounds__(256) void k_cell_reduce(BatchDev bt, const double *cellpart, double *grad_cell) {
+// Reference points, atoms' side: one wavefront per atom; its pairs (those
+// naming it as neighbour) in ascending pair order: dL/dR_a = sum v.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_bwd_gather_atoms(BatchDev bt, const void *vbuf_, const uint32_t *order,
+                                                          const int64_t *start, int64_t n_sorted, double *grad_pos) {
+  using T = typename Real<F64>::T;
+  const T *vbuf = (const T *)vbuf_;
+  const int lane = lane_id();
+  const int64_t a = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int64_t N = bt.n_atoms, NT = n_total(bt);
+  if (a >= N) return;
+  double g[3] = {0.0, 0.0, 0.0};
+  int64_t t0 = start[a], t1 = start[a + 1];
+  if (t0 < 0 || t1 > n_sorted || t0 > t1) t0 = t1 = 0;  // never for a consistent sort
+  for (int64_t t = t0 + lane; t < t1; t += kWave) {
+    const uint32_t p = order[t];
+    if ((int64_t)p >= n_sorted) continue;
+    const T *v = vbuf + (size_t)p * 4;
+    g[0] += (double)v[0];
+    g[1] += (double)v[1];
+    g[2] += (double)v[2];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[k] = wave_sum(g[k]);
+  if (lane == 0) {
+    grad_pos[a] = g[0];
+    grad_pos[NT + a] = g[1];
+    grad_pos[2 * NT + a] = g[2];
+  }
+}
+
+// Reference points, points' side: one wavefront per point, its own pairs in
+// list order: dL/dP = -sum v, and the point's cell partial
+// sum (n - m_j + m_P) (x) v.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_bwd_point_centres(BatchDev bt, NbrDev nb, const void *vbuf_,
+                                                           double *grad_pos, double *cellpart) {
+  using T = typename Real<F64>::T;
+  const T *vbuf = (const T *)vbuf_;
+  const int lane = lane_id();
+  const int64_t c = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (c >= n_centres(bt)) return;
+  const int64_t NT = n_total(bt), gi = bt.n_atoms + c;
+  const int64_t base = nb.offsets[c];
+  const int64_t end = nb.offsets[c + 1] > nb.capacity ? base : nb.offsets[c + 1];
+  const int mp0 = nb.wrap[3 * gi], mp1 = nb.wrap[3 * gi + 1], mp2 = nb.wrap[3 * gi + 2];
+  double g[3] = {0.0, 0.0, 0.0};
+  double cp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t p = base + lane; p < end; p += kWave) {
+    const int32_t j = nb.j[p];
+    const int32_t w = nb.shift[p];
+    const T *va = vbuf + (size_t)p * 4;
+    const double v0 = (double)va[0], v1 = (double)va[1], v2 = (double)va[2];
+    g[0] -= v0;
+    g[1] -= v1;
+    g[2] -= v2;
+    const double nt[3] = {(double)(shift_n(w, 0) - nb.wrap[3 * j] + mp0),
+                          (double)(shift_n(w, 1) - nb.wrap[3 * j + 1] + mp1),
+                          (double)(shift_n(w, 2) - nb.wrap[3 * j + 2] + mp2)};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      cp[3 * m] += nt[m] * v0;
+      cp[3 * m + 1] += nt[m] * v1;
+      cp[3 * m + 2] += nt[m] * v2;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[k] = wave_sum(g[k]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cp[k] = wave_sum(cp[k]);
+  if (lane == 0) {
+    grad_pos[gi] = g[0];
+    grad_pos[NT + gi] = g[1];
+    grad_pos[2 * NT + gi] = g[2];
+  }
+  if (lane < 9) {
+    double v = cp[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) v = lane == k ? cp[k] : v;
+    cellpart[(size_t)c * 9 + lane] = v;
+  }
+}
+
+// One wavefront per structure: fixed-order sum of the per-centre cell
+// partials (centres of structure s: [offs[s], offs[s+1])).
+__global__ __launch_bounds__(256) void k_cell_reduce(BatchDev bt, const int64_t *offs, const double *cellpart,
+                                                     double *grad_cell) {
   const int lane = lane_id();
   const int64_t s = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (s >= bt.n_structs) return;
-  const int64_t a0 = bt.atom_offsets[s], a1 = bt.atom_offsets[s + 1];
+  const int64_t a0 = offs[s], a1 = offs[s + 1];
   double cp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t a = a0 + lane; a < a1; a += kWave)
 #pragma unroll
@@ -393,21 +480,30 @@ size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms) {
 
 int persistent_blocks(const void *fn, size_t smem, int blocks_per_cu);
 
+void transpose_by_neighbour(const NbrDev &nb, int64_t n_centres, int64_t n_atoms, int64_t n, uint32_t *key_a,
+                            uint32_t *key_b, uint32_t *val_a, uint32_t *val_b, int32_t *hist, int64_t *off,
+                            int64_t *scan_aux, int64_t *start, uint32_t **vals_out, hipStream_t s);
+
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
-                     const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
-                     double *grad_cell, unsigned long long *counter, double4 *rw4, int32_t *astruct, int C,
-                     hipStream_t s) {
-  const int64_t N = bt.n_atoms;
+                     const void *grad_features, double *grad_pos, double *grad_cell, const WsLayout &L, int C,
+                     int64_t pairs_bound, hipStream_t s) {
+  const int64_t N = n_centres(bt), NT = n_total(bt);
   if (N == 0) return;
+  void *bcoef = L.bcoef, *vbuf = L.vbuf;
+  double *cellpart = L.cellpart;
+  unsigned long long *counter = L.counter;
+  double4 *rw4 = L.rw4;
+  int32_t *astruct = L.astruct;
   const bool f64 = p->prec == GMP_FP64;
   const int64_t blocks = (N + 3) / 4;
+  const int64_t blocks_all = (NT + 3) / 4;
   size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
   if (f64)
-    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, components,
-               grad_features, bcoef, rw4, astruct, counter);
+    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
+               components, grad_features, bcoef, rw4, astruct, counter);
   else
-    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, components,
-               grad_features, bcoef, rw4, astruct, counter);
+    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
+               components, grad_features, bcoef, rw4, astruct, counter);
   const int64_t n_items = N * (int64_t)C;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;
@@ -422,15 +518,38 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   if (pb < 1) pb = 1;
   GMP_LAUNCH("adj_pairs", fn, dim3((unsigned)pb), dim3(256), tsm, s, p->dev, bt, nb, (const double4 *)rw4,
              (const int32_t *)astruct, bcoef, vbuf, C, n_items, counter, tab);
-  if (f64)
-    GMP_LAUNCH("adj_gather", k_bwd_gather<true>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
-               cellpart);
-  else
-    GMP_LAUNCH("adj_gather", k_bwd_gather<false>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
-               cellpart);
+  if (!point_mode(bt)) {
+    if (f64)
+      GMP_LAUNCH("adj_gather", k_bwd_gather<true>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
+                 cellpart);
+    else
+      GMP_LAUNCH("adj_gather", k_bwd_gather<false>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf, grad_pos,
+                 cellpart);
+  } else {
+    // reference points: atoms gather the pairs that name them, in pair order
+    uint32_t *order = nullptr;
+    transpose_by_neighbour(nb, N, bt.n_atoms, pairs_bound, L.tr_key_in, L.tr_key_out, L.tr_val_in, L.tr_val_out,
+                           L.tr_hist, L.tr_off, L.scan_aux, L.tr_start, &order, s);
+    const int64_t ab = (bt.n_atoms + 3) / 4;
+    if (ab > 0) {
+      if (f64)
+        GMP_LAUNCH("adj_gather", k_bwd_gather_atoms<true>, dim3((unsigned)ab), dim3(256), 0, s, bt, vbuf, order,
+                   L.tr_start, pairs_bound, grad_pos);
+      else
+        GMP_LAUNCH("adj_gather", k_bwd_gather_atoms<false>, dim3((unsigned)ab), dim3(256), 0, s, bt, vbuf, order,
+                   L.tr_start, pairs_bound, grad_pos);
+    }
+    if (f64)
+      GMP_LAUNCH("adj_points", k_bwd_point_centres<true>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf,
+                 grad_pos, cellpart);
+    else
+      GMP_LAUNCH("adj_points", k_bwd_point_centres<false>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf,
+                 grad_pos, cellpart);
+  }
   if (grad_cell) {
     const int64_t sb = (bt.n_structs + 3) / 4;
-    GMP_LAUNCH("adj_cell", k_cell_reduce, dim3((unsigned)sb), dim3(256), 0, s, bt, cellpart, grad_cell);
+    GMP_LAUNCH("adj_cell", k_cell_reduce, dim3((unsigned)sb), dim3(256), 0, s, bt,
+               point_mode(bt) ? bt.point_offsets : bt.atom_offsets, cellpart, grad_cell);
   }
 }
 

@@ -29,9 +29,8 @@ void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const in
                    double *components, hipStream_t s);
 size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms);
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
-                     const void *grad_features, void *bcoef, void *vbuf, double *cellpart, double *grad_pos,
-                     double *grad_cell, unsigned long long *counter, double4 *rw4, int32_t *astruct, int C,
-                     hipStream_t s);
+                     const void *grad_features, double *grad_pos, double *grad_cell, const WsLayout &L, int C,
+                     int64_t pairs_bound, hipStream_t s);
 void fill_zero3(void *p0, size_t b0, void *p1, size_t b1, void *p2, size_t b2, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
@@ -91,37 +90,51 @@ int64_t partial_slots(const gmp_plan *p, int64_t n_atoms, int64_t capacity) {
   return max_chunks(p, n_atoms, capacity) * p->dev.S * nmono(p->dev.lmax);
 }
 
-WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t capacity, void *ws, size_t ws_bytes) {
+// N atoms, M reference points (0 without): per-index arrays cover N + M,
+// per-centre arrays max(N, M) (enough for either kind of centre).
+WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t M, int64_t capacity, void *ws,
+               size_t ws_bytes) {
   Carver c(ws, ws_bytes);
   WsLayout L;
-  const int64_t NB = N + n_structs;
+  const int64_t NB = N + n_structs, NT = N + M, NC = N > M ? N : M;
+  const int64_t tiles = M > 0 ? transpose_tiles(capacity) : 0;
+  int64_t scan_n = NB > NC ? NB : NC;
+  if (256 * tiles > scan_n) scan_n = 256 * tiles;
   const size_t tsz = p->prec == GMP_FP64 ? sizeof(double) : sizeof(float);
   L.status = c.take<uint32_t>(64);
   L.sinfo = c.take<StructInfo>((size_t)n_structs);
   L.bin_of = c.take<int32_t>(N);
-  L.astruct = c.take<int32_t>(N);
+  L.astruct = c.take<int32_t>(NT);
   L.bin_count = c.take<int32_t>(NB);
   L.bin_fill = c.take<int32_t>(NB);
   L.bin_start = c.take<int64_t>(NB + 1);
-  L.fw = c.take<double>(3 * N);
+  L.fw = c.take<double>(3 * NT);
   L.sx = c.take<double>(N);
   L.sy = c.take<double>(N);
   L.sz = c.take<double>(N);
   L.sid = c.take<int32_t>(N);
   L.ssp = c.take<int32_t>(N);
-  L.cnt = c.take<int32_t>((size_t)N * p->dev.E * p->dev.S);
-  L.ptotal = c.take<int64_t>(N);
-  L.scan_aux = c.take<int64_t>(scan_aux_size(NB > N ? NB : N));
-  L.partial = c.take<double>(partial_slots(p, N, capacity));
-  L.nch = c.take<int64_t>(N);
-  L.chunk_off = c.take<int64_t>(N + 1);
+  L.cnt = c.take<int32_t>((size_t)NC * p->dev.E * p->dev.S);
+  L.ptotal = c.take<int64_t>(NC);
+  L.scan_aux = c.take<int64_t>(scan_aux_size(scan_n));
+  L.partial = c.take<double>(partial_slots(p, NC, capacity));
+  L.nch = c.take<int64_t>(NC);
+  L.chunk_off = c.take<int64_t>(NC + 1);
   L.counter = c.take<unsigned long long>(32);
-  L.rw4 = c.take<double4>(N);
-  L.bcoef = c.take<char>(bwd_coef_elems(p, N) * tsz);
+  L.rw4 = c.take<double4>(NT);
+  L.bcoef = c.take<char>(bwd_coef_elems(p, NC) * tsz);
   L.vbuf = c.take<char>((size_t)capacity * 4 * tsz);
-  L.pair_key = c.take<uint64_t>((size_t)capacity);
-  L.pair_centre = c.take<int32_t>((size_t)capacity);
-  L.cellpart = c.take<double>((size_t)N * 9);
+  L.pair_key = c.take<uint64_t>(M > 0 ? 0 : (size_t)capacity);
+  L.pair_centre = c.take<int32_t>(M > 0 ? 0 : (size_t)capacity);
+  L.cellpart = c.take<double>((size_t)NC * 9);
+  const size_t trn = M > 0 ? (size_t)capacity : 0;
+  L.tr_key_in = c.take<uint32_t>(trn);
+  L.tr_key_out = c.take<uint32_t>(trn);
+  L.tr_val_in = c.take<uint32_t>(trn);
+  L.tr_val_out = c.take<uint32_t>(trn);
+  L.tr_hist = c.take<int32_t>((size_t)(256 * tiles));
+  L.tr_off = c.take<int64_t>(M > 0 ? (size_t)(256 * tiles + 1) : 0);
+  L.tr_start = c.take<int64_t>(M > 0 ? (size_t)(N + 1) : 0);
   L.bytes = c.off + 256;
   return L;
 }
@@ -472,11 +485,11 @@ gmp_status gmp_plan_set_tuning(gmp_plan *p, const gmp_tuning *t) {
   return GMP_OK;
 }
 
-gmp_status gmp_workspace_size(const gmp_plan *p, int32_t n_structs, int64_t n_atoms, int64_t capacity,
-                              size_t *bytes) {
+gmp_status gmp_workspace_size(const gmp_plan *p, int32_t n_structs, int64_t n_atoms, int64_t n_points,
+                              int64_t capacity, size_t *bytes) {
   if (!p || !bytes) return set_error(GMP_E_INVALID, "null argument");
-  if (n_structs < 0 || n_atoms < 0 || capacity < 0) return set_error(GMP_E_INVALID, "negative size");
-  *bytes = carve(p, n_structs, n_atoms, capacity, nullptr, 0).bytes;
+  if (n_structs < 0 || n_atoms < 0 || n_points < 0 || capacity < 0) return set_error(GMP_E_INVALID, "negative size");
+  *bytes = carve(p, n_structs, n_atoms, n_points, capacity, nullptr, 0).bytes;
   return GMP_OK;
 }
 
@@ -494,15 +507,25 @@ gmp_status check_batch(const gmp_plan *p, const gmp_batch *b) {
     return set_error(GMP_E_INVALID, "null structure arrays");
   if (b->n_atoms > 0 && (!b->x || !b->y || !b->z || !b->species))
     return set_error(GMP_E_INVALID, "null atom arrays");
+  if (b->point_offsets) {
+    if (b->n_points < 0) return set_error(GMP_E_INVALID, "negative point count");
+    if (b->n_atoms + b->n_points > 0x7ffffff0LL)
+      return set_error(GMP_E_UNSUPPORTED, "at most 2^31-16 atoms and points per batch");
+    if (b->n_points > 0 && (!b->px || !b->py || !b->pz)) return set_error(GMP_E_INVALID, "null point arrays");
+    if (b->n_points > 0 && b->n_structs == 0) return set_error(GMP_E_INVALID, "points without structures");
+  }
   return GMP_OK;
 }
+
+int64_t batch_points(const gmp_batch *b) { return b->point_offsets ? b->n_points : 0; }
+int64_t batch_centres(const gmp_batch *b) { return b->point_offsets ? b->n_points : b->n_atoms; }
 
 gmp_status check_nbrs(const gmp_plan *p, const gmp_batch *b, const gmp_neighbors *n, bool need_lists) {
   if (!n) return set_error(GMP_E_INVALID, "null neighbour lists");
   if (n->capacity < 0) return set_error(GMP_E_INVALID, "negative capacity");
   if (n->max_list < 0) return set_error(GMP_E_INVALID, "negative max_list");
   if (!n->offsets) return set_error(GMP_E_INVALID, "null neighbour offsets");
-  if (b->n_atoms > 0 && (!n->bucket_start || !n->sigma_end || !n->wrap || !n->rw))
+  if (batch_centres(b) > 0 && (!n->bucket_start || !n->sigma_end || !n->wrap || !n->rw))
     return set_error(GMP_E_INVALID, "null neighbour arrays");
   if (need_lists && n->capacity > 0 && (!n->j || !n->shift)) return set_error(GMP_E_INVALID, "null j/shift");
   (void)p;
@@ -519,6 +542,9 @@ BatchDev to_dev(const gmp_batch *b) {
   d.cell = b->cell;
   d.pbc = b->pbc;
   d.occ = b->occupancy;
+  d.n_points = b->point_offsets ? b->n_points : 0;
+  d.point_offsets = b->point_offsets;
+  d.px = b->px; d.py = b->py; d.pz = b->pz;
   return d;
 }
 
@@ -568,12 +594,12 @@ gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, i
   if (st) return st;
   if (!ws) return set_error(GMP_E_INVALID, "null workspace");
   hipStream_t s = (hipStream_t)stream;
-  WsLayout L = carve(p, b->n_structs, b->n_atoms, n->capacity, ws, ws_bytes);
+  WsLayout L = carve(p, b->n_structs, b->n_atoms, batch_points(b), n->capacity, ws, ws_bytes);
   if (L.bytes > ws_bytes) return set_error(GMP_E_NOMEM, "workspace too small");
-  const int64_t N = b->n_atoms;
+  const int64_t N = b->n_atoms, NC = batch_centres(b);
   BatchDev bt = to_dev(b);
   NbrDev nb = to_dev(n);
-  if (N == 0) {
+  if (NC == 0) {
     fill_zero(L.status, 64 * sizeof(uint32_t), s);
     fill_zero(n->offsets, sizeof(int64_t), s);
     n->n_pairs = 0;
@@ -587,12 +613,12 @@ gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, i
   scan_i32_to_i64(L.bin_count, L.bin_start, NB, L.scan_aux, s);
   launch_scatter(bt, nb, L, p->dev.E, s);
   launch_count(p, bt, nb, L, s);
-  scan_i64(L.ptotal, n->offsets, N, L.scan_aux, s);
+  scan_i64(L.ptotal, n->offsets, NC, L.scan_aux, s);
   int lds_keys;
   if (n_pairs) {
     int64_t total = 0;
     uint32_t stw[8];
-    hipError_t e = hipMemcpyAsync(&total, n->offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(&total, n->offsets + NC, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(stw, L.status, sizeof(stw), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_error(e, "neighbour count readback");
@@ -614,7 +640,10 @@ gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, i
     lds_keys = lds_keys_for(p, n->max_list > 0 ? n->max_list : kSortMax);
   }
   launch_fill(p, bt, nb, L, lds_keys, s);
-  if (n->reverse && with_reverse) launch_reverse(p, bt, nb, L, n_pairs ? *n_pairs : n->capacity, s);
+  // the reverse index pairs mirror entries of atom-centred lists; with
+  // reference points the backward orders pairs by neighbour itself
+  if (n->reverse && with_reverse && !b->point_offsets)
+    launch_reverse(p, bt, nb, L, n_pairs ? *n_pairs : n->capacity, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "neighbour kernels");
   return GMP_OK;
@@ -642,9 +671,9 @@ gmp_status gmp_build_reverse(const gmp_plan *p, const gmp_batch *b, gmp_neighbor
   if (st) return st;
   if (!n->reverse) return set_error(GMP_E_INVALID, "null reverse index");
   if (!ws) return set_error(GMP_E_INVALID, "null workspace");
-  WsLayout L = carve(p, b->n_structs, b->n_atoms, n->capacity, ws, ws_bytes);
+  WsLayout L = carve(p, b->n_structs, b->n_atoms, batch_points(b), n->capacity, ws, ws_bytes);
   if (L.bytes > ws_bytes) return set_error(GMP_E_NOMEM, "workspace too small");
-  if (b->n_atoms == 0) return GMP_OK;
+  if (b->n_atoms == 0 || b->point_offsets) return GMP_OK;  // no mirror pairs with reference points
   const int64_t bound = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
   launch_reverse(p, to_dev(b), to_dev(n), L, bound, (hipStream_t)stream);
   hipError_t e = hipGetLastError();
@@ -669,14 +698,13 @@ gmp_status gmp_features(const gmp_plan *p, const gmp_batch *b, const gmp_neighbo
   if (st) return st;
   st = check_nbrs(p, b, n, true);
   if (st) return st;
-  if (b->n_atoms == 0) return GMP_OK;
+  const int64_t N = batch_centres(b);
+  if (N == 0) return GMP_OK;
   if (!features) return set_error(GMP_E_INVALID, "null features");
   if (!ws) return set_error(GMP_E_INVALID, "null workspace");
   hipStream_t s = (hipStream_t)stream;
-  WsLayout L = carve(p, b->n_structs, b->n_atoms, n->capacity, ws, ws_bytes);
+  WsLayout L = carve(p, b->n_structs, b->n_atoms, batch_points(b), n->capacity, ws, ws_bytes);
   if (L.bytes > ws_bytes) return set_error(GMP_E_NOMEM, "workspace too small");
-  const int64_t N = b->n_atoms;
-  if (N == 0) return GMP_OK;
   BatchDev bt = to_dev(b);
   NbrDev nb = to_dev(n);
   const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
@@ -695,30 +723,31 @@ gmp_status gmp_features_backward(const gmp_plan *p, const gmp_batch *b, const gm
   if (st) return st;
   st = check_nbrs(p, b, n, true);
   if (st) return st;
-  if (b->n_atoms == 0) {  // structures without atoms have a zero cell gradient
+  const int64_t N = batch_centres(b), NT = b->n_atoms + batch_points(b);
+  if (N == 0) {  // no centres: zero gradients
+    if (grad_pos && NT > 0) fill_zero(grad_pos, (size_t)NT * 3 * sizeof(double), (hipStream_t)stream);
     if (grad_cell && b->n_structs > 0)
       fill_zero(grad_cell, (size_t)b->n_structs * 9 * sizeof(double), (hipStream_t)stream);
     return GMP_OK;
   }
   if (!components || !grad_features || !grad_pos) return set_error(GMP_E_INVALID, "null backward argument");
-  if (!n->reverse) return set_error(GMP_E_INVALID, "backward needs the reverse-pair index");
+  if (!n->reverse && !b->point_offsets) return set_error(GMP_E_INVALID, "backward needs the reverse-pair index");
   if (!ws) return set_error(GMP_E_INVALID, "null workspace");
   hipStream_t s = (hipStream_t)stream;
-  WsLayout L = carve(p, b->n_structs, b->n_atoms, n->capacity, ws, ws_bytes);
+  WsLayout L = carve(p, b->n_structs, b->n_atoms, batch_points(b), n->capacity, ws, ws_bytes);
   if (L.bytes > ws_bytes) return set_error(GMP_E_NOMEM, "workspace too small");
-  const int64_t N = b->n_atoms;
-  if (N == 0) return GMP_OK;
   BatchDev bt = to_dev(b);
   NbrDev nb = to_dev(n);
-  const int64_t pairs = n->n_pairs > 0 ? n->n_pairs : n->capacity;
+  const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
+  if (b->point_offsets && pairs > 0xffffffffLL)
+    return set_error(GMP_E_UNSUPPORTED, "at most 2^32-1 pairs in the backward of reference points");
   int64_t chunk = p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 256;
   int64_t by_pairs = (pairs / N) / chunk;
   if (by_pairs < 1) by_pairs = 1;
   int64_t want = (8192 + N - 1) / N;
   int64_t C = want < by_pairs ? want : by_pairs;
   if (C < 1) C = 1;
-  launch_backward(p, bt, nb, components, grad_features, L.bcoef, L.vbuf, L.cellpart, grad_pos, grad_cell,
-                  L.counter, L.rw4, L.astruct, (int)C, s);
+  launch_backward(p, bt, nb, components, grad_features, grad_pos, grad_cell, L, (int)C, pairs, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "adjoint kernels");
   return GMP_OK;

@@ -101,6 +101,10 @@ struct PlanDev {
   double weight[35];              // l!/(a!b!c!) by global monomial index (same (a,b,c) ordering)
 };
 
+// Atoms and (optional) reference points share one index space g: atoms
+// 0..N-1, then points N..N+M-1.  The centres are the atoms (centre c is g = c)
+// or, with reference points, the points (centre c is g = N + c); neighbours
+// are always atoms.
 struct BatchDev {
   int n_structs;
   int64_t n_atoms;
@@ -110,7 +114,16 @@ struct BatchDev {
   const double *cell;
   const uint8_t *pbc;
   const double *occ;       // [n_atoms] occupancies or null (all 1)
+  int64_t n_points;        // reference points (0 without)
+  const int64_t *point_offsets;  // [n_structs+1], null: the centres are the atoms
+  const double *px, *py, *pz;
 };
+
+__host__ __device__ inline bool point_mode(const BatchDev &b) { return b.point_offsets != nullptr; }
+__host__ __device__ inline int64_t n_points_of(const BatchDev &b) { return point_mode(b) ? b.n_points : 0; }
+__host__ __device__ inline int64_t n_total(const BatchDev &b) { return b.n_atoms + n_points_of(b); }
+__host__ __device__ inline int64_t n_centres(const BatchDev &b) { return point_mode(b) ? b.n_points : b.n_atoms; }
+__host__ __device__ inline int64_t centre_base(const BatchDev &b) { return point_mode(b) ? b.n_atoms : 0; }
 
 struct NbrDev {
   int64_t capacity;
@@ -186,12 +199,22 @@ __device__ inline void image_shift(const Cell9 &c, int n1, int n2, int n3, doubl
   image_shift(c.a, n1, n2, n3, sx, sy, sz);
 }
 
-// Wrapped position Rw_i = R_i - ((m1 a1 + m2 a2) + m3 a3) from the current
-// positions and lattice and the wrap indices of the neighbour build; the
-// same operation order as the build, so unchanged inputs give the same bits.
-// The fourth component carries the atom's occupancy (1 when none is given).
+// Structure of index g (atom or reference point).
+__device__ inline int struct_of_index(const BatchDev &bt, int64_t g) {
+  return g < bt.n_atoms ? struct_of_atom(bt.atom_offsets, bt.n_structs, g)
+                        : struct_of_atom(bt.point_offsets, bt.n_structs, g - bt.n_atoms);
+}
+
+// Wrapped position Rw_i = R_i - ((m1 a1 + m2 a2) + m3 a3) of index i (atom or
+// reference point) from the current positions and lattice and the wrap
+// indices of the neighbour build; the same operation order as the build, so
+// unchanged inputs give the same bits.  The fourth component carries the
+// atom's occupancy (1 when none is given, and for points).
 __device__ inline double4 wrapped_position(const BatchDev &bt, const NbrDev &nb, int64_t i, int s) {
-  double r[3] = {bt.x[i], bt.y[i], bt.z[i]};
+  const bool atom = i < bt.n_atoms;
+  const int64_t k = atom ? i : i - bt.n_atoms;
+  const double *X = atom ? bt.x : bt.px, *Y = atom ? bt.y : bt.py, *Z = atom ? bt.z : bt.pz;
+  double r[3] = {X[k], Y[k], Z[k]};
   if (bt.pbc[s] & 7) {
     const double *a = bt.cell + 9 * (int64_t)s;
     const double m0 = (double)nb.wrap[3 * i], m1 = (double)nb.wrap[3 * i + 1], m2 = (double)nb.wrap[3 * i + 2];
@@ -201,7 +224,7 @@ __device__ inline double4 wrapped_position(const BatchDev &bt, const NbrDev &nb,
       r[c] = r[c] - t;
     }
   }
-  return make_double4(r[0], r[1], r[2], bt.occ ? bt.occ[i] : 1.0);
+  return make_double4(r[0], r[1], r[2], (atom && bt.occ) ? bt.occ[i] : 1.0);
 }
 
 __device__ inline int shift_n(int32_t w, int k) { return (int)(int8_t)((uint32_t)w >> (8 * k)); }
@@ -264,13 +287,19 @@ struct WsLayout {
   double4 *rw4;           // [N] AoS copy of the wrapped positions
   uint64_t *pair_key;     // [capacity] packed (j, n) of every pair (reverse search)
   int32_t *pair_centre;   // [capacity] centre of every pair (reverse search)
+  // reference points: pairs sorted by neighbour atom (adjoint gather order)
+  uint32_t *tr_key_in, *tr_key_out, *tr_val_in, *tr_val_out;  // [capacity] radix-sort ping-pong buffers
+  int32_t *tr_hist;       // [256 * tiles] per-tile digit counts
+  int64_t *tr_off;        // [256 * tiles + 1] their exclusive scan
+  int64_t *tr_start;      // [n_atoms + 1] first sorted pair of every atom
   void *bcoef;            // adjoint per-centre polynomial coefficients
   void *vbuf;             // adjoint per-pair vectors [capacity][4]
   double *cellpart;       // [N][9]
   size_t bytes;
 };
-WsLayout carve(const gmp_plan *p, int n_structs, int64_t n_atoms, int64_t capacity, void *ws,
+WsLayout carve(const gmp_plan *p, int n_structs, int64_t n_atoms, int64_t n_points, int64_t capacity, void *ws,
                size_t ws_bytes);
+int64_t transpose_tiles(int64_t n);  // tiles of the by-neighbour sort of n pairs
 int64_t partial_slots(const gmp_plan *p, int64_t n_atoms, int64_t capacity);
 
 // device scans (exclusive, writes n+1 outputs)

@@ -106,21 +106,27 @@ __global__ void k_struct_setup(BatchDev bt, StructInfo *info, double rcmax, int 
   info[s] = I;
 }
 
+// One thread per index g: atoms (wrapped, binned) and reference points
+// (wrapped only; they are centres, never neighbours).  rw, wrap and fw are
+// over the n_total indices.
 __global__ void k_wrap(BatchDev bt, const StructInfo *info, NbrDev nb, double *fw, int32_t *bin_of,
                        int32_t *bin_count, int32_t *astruct, int n_elements, uint32_t *status) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= bt.n_atoms) return;
-  {
+  const int64_t N = n_total(bt);
+  if (i >= N) return;
+  const bool atom = i < bt.n_atoms;
+  if (atom) {
     const int sp = bt.species[i];
     if (sp < 0 || sp >= n_elements) atomicOr(status, ST_SPECIES);
   }
-  const int64_t N = bt.n_atoms;
-  const int s = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
+  const int s = struct_of_index(bt, i);
   astruct[i] = s;
   const StructInfo &I = info[s];
-  const double R[3] = {bt.x[i], bt.y[i], bt.z[i]};
+  const int64_t k = atom ? i : i - bt.n_atoms;
+  const double *X = atom ? bt.x : bt.px, *Y = atom ? bt.y : bt.py, *Z = atom ? bt.z : bt.pz;
+  const double R[3] = {X[k], Y[k], Z[k]};
   if (!(isfinite(R[0]) && isfinite(R[1]) && isfinite(R[2]))) atomicOr(status, ST_NONFINITE);
-  if (bt.occ && !isfinite(bt.occ[i])) atomicOr(status, ST_NONFINITE);
+  if (atom && bt.occ && !isfinite(bt.occ[i])) atomicOr(status, ST_NONFINITE);
   int m[3] = {0, 0, 0};
   int b[3] = {0, 0, 0};
   double f3[3] = {0.0, 0.0, 0.0};
@@ -155,6 +161,7 @@ __global__ void k_wrap(BatchDev bt, const StructInfo *info, NbrDev nb, double *f
   fw[i] = f3[0];
   fw[N + i] = f3[1];
   fw[2 * N + i] = f3[2];
+  if (!atom) return;
   int64_t bin = I.bin_base + ((int64_t)b[0] * I.nb[1] + b[1]) * I.nb[2] + b[2];
   bin_of[i] = (int32_t)bin;
   atomicAdd(&bin_count[bin], 1);
@@ -165,7 +172,7 @@ __global__ void k_scatter(BatchDev bt, NbrDev nb, const int32_t *bin_of, const i
                           int32_t *ssp, int n_elements) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= bt.n_atoms) return;
-  const int64_t N = bt.n_atoms;
+  const int64_t N = n_total(bt);  // stride of rw
   int32_t b = bin_of[i];
   int64_t p = bin_start[b] + atomicAdd(&bin_fill[b], 1);
   sx[p] = nb.rw[i];
@@ -194,7 +201,7 @@ struct Cand {
 
 __device__ inline void cand_setup(Cand &C, const StructInfo *info, const BatchDev &bt, int s,
                                   const double *fw, int64_t i) {
-  const int64_t N = bt.n_atoms;
+  const int64_t N = n_total(bt);  // stride of fw
   C.I = info + s;
   C.cell = bt.cell + 9 * (int64_t)s;
   C.f[0] = fw[i]; C.f[1] = fw[N + i]; C.f[2] = fw[2 * N + i];
@@ -325,14 +332,17 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
   const int w = threadIdx.x / kWave, nw = blockDim.x / kWave, lane = lane_id();
   const int nbk = P.E * P.S;
   int32_t *c = lds_cnt;
-  const int64_t N = bt.n_atoms;
-  const int64_t i = sid[xcd_contiguous(blockIdx.x, gridDim.x)];
+  const int64_t N = n_total(bt);  // stride of rw
+  // centre ci (atoms: in cell-list order; reference points: in index order), index g
+  const int64_t k = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t i = point_mode(bt) ? k : sid[k];
+  const int64_t g = centre_base(bt) + i;
   for (int t = threadIdx.x; t < nbk; t += blockDim.x) c[t] = 0;
   __syncthreads();
-  const int s = astruct[i];
+  const int s = astruct[g];
   Cand C;
-  cand_setup(C, info, bt, s, fw, i);
-  const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+  cand_setup(C, info, bt, s, fw, g);
+  const double rix = nb.rw[g], riy = nb.rw[N + g], riz = nb.rw[2 * N + g];
   for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
                      [&](int t, const int *n, double shx, double shy, double shz) {
                        const double dx = (sx[t] - rix) + shx;
@@ -425,8 +435,11 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   uint64_t *keys = lds_u64;
   int32_t *bstart = (int32_t *)(lds_u64 + lds_keys);  // [nbk+1]
   int32_t *cursor = bstart + nbk + 1;                 // [nbk]
-  const int64_t i = sid[xcd_contiguous(blockIdx.x, gridDim.x)];  // centres in cell-list order
-  const int64_t N = bt.n_atoms;
+  // centre i (atoms: in cell-list order; reference points: in index order), index g
+  const int64_t kb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t i = point_mode(bt) ? kb : sid[kb];
+  const int64_t g = centre_base(bt) + i;
+  const int64_t N = n_total(bt);  // stride of rw
   const int tid = threadIdx.x, w = tid / kWave, nw = blockDim.x / kWave, lane = lane_id();
   const int64_t base = nb.offsets[i];
   const int64_t total = nb.offsets[i + 1] - base;
@@ -459,12 +472,13 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   if (overflow) return;  // consumers skip centres whose list ends past the capacity
   if (too_big) {
     // the list does not fit the in-LDS sort: leave in-range placeholder
-    // entries (the centre itself, no shift) so no consumer reads outside
-    // its arrays; the status word reports the condition
-    int ei = bt.species[i];
+    // entries (the centre itself, or atom 0 for a reference point; no shift)
+    // so no consumer reads outside its arrays; the status word reports it
+    const int64_t jp = point_mode(bt) ? 0 : i;
+    int ei = bt.species[jp];
     ei = ei < 0 ? 0 : (ei >= P.E ? P.E - 1 : ei);
     for (int64_t t = tid; t < total; t += blockDim.x) {
-      nb.j[base + t] = (int32_t)i;
+      nb.j[base + t] = (int32_t)jp;
       nb.shift[base + t] = (int32_t)((uint32_t)ei << 24);
       if (pair_key) {
         pair_key[base + t] = make_key(i, 0, 0, 0);
@@ -476,10 +490,10 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   }
   for (int b = tid; b < nbk; b += blockDim.x) cursor[b] = bstart[b];
   __syncthreads();
-  const int s = astruct[i];
+  const int s = astruct[g];
   Cand C;
-  cand_setup(C, info, bt, s, fw, i);
-  const double rix = nb.rw[i], riy = nb.rw[N + i], riz = nb.rw[2 * N + i];
+  cand_setup(C, info, bt, s, fw, g);
+  const double rix = nb.rw[g], riy = nb.rw[N + g], riz = nb.rw[2 * N + g];
   for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
                      [&](int t, const int *n, double shx, double shy, double shz) {
                        const double dx = (sx[t] - rix) + shx;
@@ -573,19 +587,22 @@ void launch_struct_setup(const gmp_plan *p, const BatchDev &bt, const WsLayout &
 }
 
 void launch_wrap(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_elements, hipStream_t s) {
-  int64_t blocks = (bt.n_atoms + 255) / 256;
+  int64_t blocks = (n_total(bt) + 255) / 256;
+  if (blocks == 0) return;
   GMP_LAUNCH("nbr_wrap", k_wrap, dim3((unsigned)blocks), dim3(256), 0, s, bt, L.sinfo, nb, L.fw, L.bin_of,
              L.bin_count, L.astruct, n_elements, L.status);
 }
 
 void launch_scatter(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_elements, hipStream_t s) {
   int64_t blocks = (bt.n_atoms + 255) / 256;
+  if (blocks == 0) return;
   GMP_LAUNCH("nbr_scatter", k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, L.bin_of,
              L.bin_start, L.bin_fill, L.sx, L.sy, L.sz, L.sid, L.ssp, n_elements);
 }
 
 void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, hipStream_t s) {
-  int64_t blocks = bt.n_atoms;
+  int64_t blocks = n_centres(bt);
+  if (blocks == 0) return;
   size_t smem = sizeof(int32_t) * p->dev.E * p->dev.S;
   GMP_LAUNCH("nbr_count", k_count, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo, L.fw,
              L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, L.ptotal, L.status);
@@ -595,9 +612,10 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
                  hipStream_t s) {
   int nbk = p->dev.E * p->dev.S;
   size_t smem = sizeof(uint64_t) * lds_keys + sizeof(int32_t) * (2 * nbk + 2);
-  GMP_LAUNCH("nbr_fill_sort", k_fill, dim3((unsigned)bt.n_atoms), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
+  if (n_centres(bt) == 0) return;
+  GMP_LAUNCH("nbr_fill_sort", k_fill, dim3((unsigned)n_centres(bt)), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
              L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, lds_keys,
-             nb.reverse ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.status);
+             (nb.reverse && !point_mode(bt)) ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.status);
 }
 
 void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,

@@ -54,18 +54,23 @@ __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c
 // structure), its structure, and its wrapped position as an AoS double4 (one
 // 32-byte gather per neighbour).  The first thread also clears the work-item
 // counter.
-__global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int64_t N, int kc, int64_t *nch, double4 *rw4,
+// Indices g < n_total get their structure and packed position; centres
+// c < n_centres their chunk count.
+__global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int kc, int64_t *nch, double4 *rw4,
                                int32_t *astruct, unsigned long long *counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *counter = 0ull;
-  if (i >= N) return;
-  const int64_t cnt = nb.offsets[i + 1] - nb.offsets[i];
-  // a list that ends past the capacity was not written (overflowed no-sync
-  // build, reported in the status word): no work items, zero moments
-  nch[i] = nb.offsets[i + 1] > nb.capacity ? 0 : (kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1);
-  const int st = struct_of_atom(bt.atom_offsets, bt.n_structs, i);
-  astruct[i] = st;
-  rw4[i] = wrapped_position(bt, nb, i, st);
+  if (i < n_centres(bt)) {
+    const int64_t cnt = nb.offsets[i + 1] - nb.offsets[i];
+    // a list that ends past the capacity was not written (overflowed no-sync
+    // build, reported in the status word): no work items, zero moments
+    nch[i] = nb.offsets[i + 1] > nb.capacity ? 0 : (kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1);
+  }
+  if (i < n_total(bt)) {
+    const int st = struct_of_index(bt, i);
+    astruct[i] = st;
+    rw4[i] = wrapped_position(bt, nb, i, st);
+  }
 }
 
 __device__ inline int64_t centre_of_chunk(const int64_t *chunk_off, int64_t N, int64_t q) {
@@ -173,17 +178,17 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
 
   const int lane = lane_id();
   const int wv = threadIdx.x / kWave;
-  const int64_t N = bt.n_atoms;
+  const int64_t N = n_centres(bt), cb = centre_base(bt);
   const int64_t n_items = chunk_off[N];
   for (;;) {
     const int64_t qc = next_item(counter);
     if (qc >= n_items) break;
     const int64_t i = centre_of_chunk(chunk_off, N, qc);
     const int c = (int)(qc - chunk_off[i]);
-    const int st = astruct[i];
+    const int st = astruct[cb + i];
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
-    const double4 ri4 = rw4[i];
+    const double4 ri4 = rw4[cb + i];
     const double rix = ri4.x, riy = ri4.y, riz = ri4.z;
     const int64_t base = nb.offsets[i];
     const int cnt = (int)(nb.offsets[i + 1] - base);
@@ -220,7 +225,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
       p = uni(p);
     };
     advance(tc, pc);
-    const int32_t ii = (int32_t)i;
+    const int32_t ii = (int32_t)(cb + i);  // idle lanes read the centre's own packed position
     // stage b: positions gathered; stage c: (j, shift) loaded
     int32_t wb = 0, jc = ii, wc = 0;
     double4 rb;
@@ -466,9 +471,9 @@ int persistent_blocks(const void *fn, size_t smem, int blocks_per_cu) {
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
                     int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
                     int32_t *astruct, int64_t pairs_bound, hipStream_t s) {
-  const int64_t N = bt.n_atoms;
+  const int64_t N = n_centres(bt), NT = n_total(bt);  // NT >= N
   const int kc = chunk_size(p);
-  GMP_LAUNCH("overlap_prep", k_overlap_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, bt, nb, N, kc, nch,
+  GMP_LAUNCH("overlap_prep", k_overlap_prep, dim3((unsigned)((NT + 255) / 256)), dim3(256), 0, s, bt, nb, kc, nch,
              rw4, astruct, counter);
   scan_i64(nch, chunk_off, N, scan_aux, s);
   const bool f64 = p->prec == GMP_FP64;

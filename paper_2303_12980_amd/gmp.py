@@ -110,10 +110,14 @@ class GMPPlan:
         t = _lib.Tuning(cur["chunk_pairs"], cur["bin_divisor"], cur["blocks_per_cu"], 0)
         check(_lib.load().gmp_plan_set_tuning(self._h, ctypes.byref(t)))
 
-    def workspace_bytes(self, n_structs, n_atoms, capacity) -> int:
+    def workspace_bytes(self, n_structs, n_atoms, capacity, n_points=0) -> int:
         b = ctypes.c_size_t(0)
-        check(_lib.load().gmp_workspace_size(self._h, int(n_structs), int(n_atoms), int(capacity), ctypes.byref(b)))
+        check(_lib.load().gmp_workspace_size(self._h, int(n_structs), int(n_atoms), int(n_points), int(capacity),
+                                             ctypes.byref(b)))
         return int(b.value)
+
+    def batch_workspace_bytes(self, batch: "DeviceBatch", capacity) -> int:
+        return self.workspace_bytes(batch.n_structs, batch.n_atoms, capacity, batch.n_points)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -125,9 +129,12 @@ class GMPPlan:
 class DeviceBatch:
     """Packed CSR batch resident on the GPU (wraps gmp_batch)."""
 
-    def __init__(self, atom_offsets, pos, species, cell, pbc, device="cuda", occupancy=None):
+    def __init__(self, atom_offsets, pos, species, cell, pbc, device="cuda", occupancy=None, points=None,
+                 point_offsets=None):
         """occupancy: per-atom fractional site occupancies (disordered
-        structures), or None for all 1."""
+        structures), or None for all 1.  points [M, 3] with point_offsets
+        [n_structs+1]: reference points, which then are the centres (features
+        at those positions instead of at the atoms)."""
         self.atom_offsets = torch.as_tensor(np.asarray(atom_offsets, np.int64), device=device)
         pos = torch.as_tensor(np.asarray(pos, np.float64), device=device)
         self.xyz = pos.t().contiguous()  # [3, N] SoA
@@ -141,10 +148,42 @@ class DeviceBatch:
             self.occupancy = torch.as_tensor(np.asarray(occupancy, np.float64), device=device).contiguous()
             if self.occupancy.shape != (self.n_atoms,):
                 raise ValueError("occupancy must have one entry per atom")
+        self.point_offsets, self.pxyz, self.n_points = None, None, 0
+        if point_offsets is not None:
+            po = np.asarray(point_offsets, np.int64)
+            pts = np.asarray(points, np.float64).reshape(-1, 3)
+            if len(po) != self.n_structs + 1 or po[0] != 0 or po[-1] != len(pts) or np.any(np.diff(po) < 0):
+                raise ValueError("point_offsets must be a CSR over the structures' points")
+            self.point_offsets = torch.as_tensor(po, device=device)
+            self.pxyz = torch.as_tensor(pts, device=device).t().contiguous()  # [3, M] SoA
+            self.n_points = len(pts)
+
+    @property
+    def n_centres(self) -> int:
+        """Atoms, or the reference points when they are given."""
+        return self.n_points if self.point_offsets is not None else self.n_atoms
+
+    @property
+    def n_total(self) -> int:
+        return self.n_atoms + self.n_points
 
     @classmethod
     def from_batch(cls, b, device="cuda"):
         return cls(b.atom_offsets, b.pos, b.species, b.cell, b.pbc, device, getattr(b, "occupancy", None))
+
+    def with_points(self, points, point_offsets) -> "DeviceBatch":
+        """The same atoms (sharing memory) with reference points as the centres."""
+        v = DeviceBatch.__new__(DeviceBatch)
+        v.__dict__.update(self.__dict__)
+        dev = self.species.device
+        po = np.asarray(point_offsets, np.int64)
+        pts = np.asarray(points, np.float64).reshape(-1, 3)
+        if len(po) != self.n_structs + 1 or po[0] != 0 or po[-1] != len(pts) or np.any(np.diff(po) < 0):
+            raise ValueError("point_offsets must be a CSR over the structures' points")
+        v.point_offsets = torch.as_tensor(po, device=dev)
+        v.pxyz = torch.as_tensor(pts, device=dev).t().contiguous()
+        v.n_points = len(pts)
+        return v
 
     def structure(self, s: int, a0: int, a1: int) -> "DeviceBatch":
         """One-structure batch viewing this batch's memory (atoms a0:a1 of
@@ -157,6 +196,7 @@ class DeviceBatch:
         v.cell = self.cell[s:s + 1]
         v.pbc = self.pbc[s:s + 1]
         v.occupancy = None if self.occupancy is None else self.occupancy[a0:a1]
+        v.point_offsets, v.pxyz, v.n_points = None, None, 0
         v.n_structs, v.n_atoms = 1, a1 - a0
         return v
 
@@ -166,7 +206,9 @@ class DeviceBatch:
         return _lib.BatchDesc(self.n_structs, self.n_atoms, self.atom_offsets.data_ptr(), xyz[0].data_ptr(),
                               xyz[1].data_ptr(), xyz[2].data_ptr(), self.species.data_ptr(), cell.data_ptr(),
                               self.pbc.data_ptr(),
-                              self.occupancy.data_ptr() if self.occupancy is not None else 0)
+                              self.occupancy.data_ptr() if self.occupancy is not None else 0,
+                              self.n_points, self.point_offsets.data_ptr() if self.point_offsets is not None else 0,
+                              *((self.pxyz[k].data_ptr() for k in range(3)) if self.n_points > 0 else (0, 0, 0)))
 
 
 class Workspace:
@@ -187,7 +229,7 @@ class Neighbors:
 
     def __init__(self, plan: GMPPlan, batch: DeviceBatch, capacity: int, reverse: bool = True):
         dev = batch.species.device
-        N = batch.n_atoms
+        N, NT = batch.n_centres, batch.n_total  # lists per centre; wrap / rw per atom and point
         E, S = plan.n_elements, plan.n_slots
         self.capacity = int(capacity)
         self.n_pairs = 0
@@ -197,8 +239,10 @@ class Neighbors:
         self.shift = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
         self.bucket_start = torch.empty(N * (S * E + 1), dtype=torch.int32, device=dev)
         self.sigma_end = torch.empty(N * S, dtype=torch.int32, device=dev)
-        self.wrap = torch.empty(N * 3, dtype=torch.int32, device=dev)
-        self.rw = torch.empty(3 * N, dtype=torch.float64, device=dev)
+        self.wrap = torch.empty(NT * 3, dtype=torch.int32, device=dev)
+        self.rw = torch.empty(3 * NT, dtype=torch.float64, device=dev)
+        # reference points need no reverse index (the backward orders pairs by neighbour itself)
+        reverse = reverse and batch.point_offsets is None
         self.reverse = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev) if reverse else None
 
     def desc(self):
@@ -224,13 +268,14 @@ def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: 
     L = _lib.load()
     call = L.gmp_build_lists if defer_reverse else L.gmp_build_neighbors
     if capacity is None:
-        capacity = out.capacity if out is not None else max(1024, batch.n_atoms * 64)
+        capacity = out.capacity if out is not None else max(1024, batch.n_centres * 64)
     for _ in range(2):
-        if out is not None and out.capacity >= capacity and (out.reverse is not None) == reverse:
+        if out is not None and out.capacity >= capacity and (out.reverse is not None) == (
+                reverse and batch.point_offsets is None):
             nb = out
         else:
             nb = Neighbors(plan, batch, capacity, reverse)
-        nbytes = plan.workspace_bytes(batch.n_structs, batch.n_atoms, nb.capacity)
+        nbytes = plan.batch_workspace_bytes(batch, nb.capacity)
         buf = ws.get(nbytes)
         bd, nd = batch.desc(), nb.desc()
         npairs = ctypes.c_int64(0)
@@ -253,7 +298,7 @@ def rebuild_neighbors_nosync(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, n
     device-side error is reported later by check_status()."""
     L = _lib.load()
     call = L.gmp_build_lists if defer_reverse else L.gmp_build_neighbors
-    nbytes = plan.workspace_bytes(batch.n_structs, batch.n_atoms, nb.capacity)
+    nbytes = plan.batch_workspace_bytes(batch, nb.capacity)
     buf = ws.get(nbytes)
     bd, nd = batch.desc(), nb.desc()
     check(call(plan.handle, ctypes.byref(bd), ctypes.byref(nd), None, _ptr(buf), buf.numel(), _stream_ptr(stream)))
@@ -276,14 +321,14 @@ def check_status(ws: Workspace, stream=None):
 def features(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Workspace, with_components=True,
              xyz=None, cell=None, out=None, comp_out=None, stream=None):
     L = _lib.load()
-    N = batch.n_atoms
+    N = batch.n_centres
     dev = batch.species.device
     F = out if out is not None else torch.empty((N, plan.n_features), dtype=plan.dtype, device=dev)
     mu = None
     if with_components:
         mu = comp_out if comp_out is not None else torch.empty((N, plan.n_components), dtype=torch.float64,
                                                                device=dev)
-    nbytes = plan.workspace_bytes(batch.n_structs, N, nb.capacity)
+    nbytes = plan.batch_workspace_bytes(batch, nb.capacity)
     buf = ws.get(nbytes)
     bd, nd = batch.desc(xyz, cell), nb.desc()
     check(L.gmp_features(plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(F), _ptr(mu), _ptr(buf),
@@ -293,13 +338,15 @@ def features(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Workspace, wi
 
 def features_backward(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Workspace, mu, F, G,
                       want_cell=True, xyz=None, cell=None, stream=None):
+    """dL/dpositions [n_total, 3] (atoms, then reference points) and
+    dL/dcell [n_structs, 3, 3] for L = sum G*F."""
     L = _lib.load()
-    N = batch.n_atoms
+    N = batch.n_total
     dev = batch.species.device
     G = G.to(dtype=plan.dtype).contiguous()
     gpos = torch.empty(3 * N, dtype=torch.float64, device=dev)
     gcell = torch.empty(batch.n_structs * 9, dtype=torch.float64, device=dev) if want_cell else None
-    nbytes = plan.workspace_bytes(batch.n_structs, N, nb.capacity)
+    nbytes = plan.batch_workspace_bytes(batch, nb.capacity)
     buf = ws.get(nbytes)
     bd, nd = batch.desc(xyz, cell), nb.desc()
     check(L.gmp_features_backward(plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(mu), _ptr(F), _ptr(G),
@@ -327,7 +374,7 @@ class GMPFunction(torch.autograd.Function):
         xyz, cell, F, mu = ctx.saved_tensors
         gp, gc = features_backward(ctx.plan, ctx.batch, ctx.nb, ctx.ws, mu, F, gF.contiguous(), True,
                                    xyz=xyz.contiguous(), cell=cell.contiguous())
-        return gp.t().contiguous(), gc.reshape(-1, 9), None, None, None, None
+        return gp[:ctx.batch.n_atoms].t().contiguous(), gc.reshape(-1, 9), None, None, None, None
 
 
 class CapturedStep:
@@ -346,8 +393,8 @@ class CapturedStep:
                  concurrent_reverse=False):
         self.plan, self.batch, self.ws, self.nb = plan, batch, ws, nb
         dev = batch.species.device
-        N = batch.n_atoms
-        ws.get(plan.workspace_bytes(batch.n_structs, N, nb.capacity))  # grow before capture
+        N = batch.n_centres
+        ws.get(plan.batch_workspace_bytes(batch, nb.capacity))  # grow before capture
         self.F = torch.empty((N, plan.n_features), dtype=plan.dtype, device=dev)
         self.mu = torch.empty((N, plan.n_components), dtype=torch.float64, device=dev)
         self.backward = backward
@@ -360,7 +407,7 @@ class CapturedStep:
             self.G = torch.zeros((N, plan.n_features), dtype=plan.dtype, device=dev)
             if G is not None:
                 self.G.copy_(G)
-            self.gpos = torch.empty(3 * N, dtype=torch.float64, device=dev)
+            self.gpos = torch.empty(3 * batch.n_total, dtype=torch.float64, device=dev)
             self.gcell = torch.empty(batch.n_structs * 9, dtype=torch.float64, device=dev)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -374,7 +421,7 @@ class CapturedStep:
         # the graph holds raw addresses: keep every buffer it touches alive
         self._held = (ws.buf, nb.offsets, nb.j, nb.shift, nb.bucket_start, nb.sigma_end, nb.wrap, nb.rw,
                       nb.reverse, batch.xyz, batch.cell, batch.species, batch.atom_offsets, batch.pbc,
-                      batch.occupancy)
+                      batch.occupancy, batch.point_offsets, batch.pxyz)
 
     def _run(self):
         L = _lib.load()
