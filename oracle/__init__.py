@@ -81,6 +81,8 @@ def lib():
             L.oracle_point_loss_frozen.argtypes = [c_int, dp, ip, dp, *probe_args, c_int, dp, lp, ip, ip, dp,
                                                    dp, dp, dp]
             L.oracle_point_loss_frozen.restype = c_int
+            L.oracle_jacobian.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_i64, dp, dp, ip]
+            L.oracle_jacobian.restype = c_i64
             L.oracle_solid_harmonic.argtypes = [c_int, c_int, c_int, c_int, dp, dp, dp]
             L.oracle_solid_harmonic.restype = None
             L.oracle_radial.argtypes = [c_int, c_dbl, c_int, dp, dp, c_int, dp, dp]
@@ -438,3 +440,27 @@ def point_loss_frozen(struct, probes, points, G, pairs, occupancy=None):
     _check(lib().oracle_point_loss_frozen(len(pos), pp, sp, cp, *a, len(pts), ptp, pop, pjp, pnp, pqp, gp,
                                           ctypes.byref(out), op))
     return out.value
+
+
+def jacobian(struct, probes, occupancy=None):
+    """Per-pair feature Jacobian J [P, nf, 3] (dF_{i,f}/dd_p, pairs of every
+    centre in canonical order, centres in index order) and the list offsets
+    [n_atoms+1]."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    keep, a = _probe_args(probes)
+    nf = n_features(probes.orders, len(probes.sigmas))
+    occ, op = _occ(occupancy, len(pos))
+    st = ctypes.c_int32(0)
+    rc2 = cutoffs(probes)
+    counts = [len(neighbors(struct, rc2, i)["j"]) for i in range(len(pos))]
+    total = int(sum(counts))
+    jac = np.zeros((max(total, 1), nf, 3))
+    n = lib().oracle_jacobian(len(pos), pp, sp, cp, int(pbc), *a, total, _dp(jac), op, ctypes.byref(st))
+    _check(st.value)
+    assert n == total
+    offs = np.zeros(len(pos) + 1, np.int64)
+    offs[1:] = np.cumsum(counts)
+    return jac[:total], offs

@@ -726,6 +726,65 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
   return loss_frozen_impl(&P, pos, species, cell, n_atoms, pos, po, pj, pn, pq, G, L_out, occ);
 }
 
+/*
+ * Full feature Jacobian (the paper's feature derivatives with respect to
+ * the atom positions, "Examples"), per pair: for centre i and pair p = (j, n)
+ * of its canonical list, J[p][f][k] = dF_{i,f} / d d_p,k, the derivative with
+ * respect to the pair's displacement d_p = R_j + n.cell - R_i.  Then
+ *   dF_{i,f}/dR_j = sum over pairs p of i with neighbour j of J[p][f]
+ *                   minus, for j = i, the sum over all pairs of i,
+ * and dF_{i,f}/da_m = sum_p (n_m - m_j,m + m_i,m) J[p][f].  Pairs of centre
+ * i start at the running sum of the list lengths of the centres before it;
+ * writes at most cap pairs and returns the total pair count.
+ */
+int64_t oracle_jacobian(int n_atoms, const double *pos, const int32_t *species,
+                        const double *cell, int pbc,
+                        int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                        int n_elements, const int32_t *prim_offsets, const double *B,
+                        const double *beta, double tau, int64_t cap, double *jac,
+                        const double *occ, int32_t *status) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  *status = check_probes(&P);
+  if (*status) return 0;
+  for (int i = 0; i < n_atoms; ++i)
+    if (species[i] < 0 || species[i] >= n_elements) { *status = OR_E_INVALID; return 0; }
+  const int ns = n_slots(&P);
+  double *rc2 = (double *)malloc(sizeof(double) * ns);
+  int st = slot_cutoffs(&P, rc2);
+  double rcmax2 = 0.0;
+  for (int s = 0; s < ns; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw = NULL; int32_t *m = NULL;
+  if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (st) { free(rc2); *status = st; return 0; }
+  S.occ = occ;
+  const int nc = total_comps(&P), nf = total_feats(&P);
+  double *mu = (double *)malloc(sizeof(double) * (size_t)nc);
+  double *W = (double *)malloc(sizeof(double) * (size_t)nc);
+  double *Fi = (double *)malloc(sizeof(double) * nf);
+  double *G = (double *)malloc(sizeof(double) * nf);
+  int64_t base = 0;
+  for (int i = 0; i < n_atoms; ++i) {
+    pair_t *pairs;
+    int64_t np = collect(&S, i, ns, rc2, &pairs);
+    centre_features(&P, pairs, np, rc2, mu, Fi);
+    for (int f = 0; f < nf; ++f) {
+      /* dF_f / dmu = W with the upstream gradient the unit vector of f */
+      for (int t = 0; t < nf; ++t) G[t] = t == f ? 1.0 : 0.0;
+      make_W(&P, mu, Fi, G, W);
+      for (int64_t p = 0; p < np; ++p) {
+        if (base + p >= cap) break;
+        double v[3];
+        pair_v(&P, pairs + p, rc2, W, v);
+        for (int k = 0; k < 3; ++k) jac[((size_t)(base + p) * nf + f) * 3 + k] = v[k];
+      }
+    }
+    base += np;
+    free(pairs);
+  }
+  free(mu); free(W); free(Fi); free(G); free(rc2); free(rw); free(m);
+  return base;
+}
+
 /* ------------------------------------------------------------------ */
 /* reference points                                                    */
 /* ------------------------------------------------------------------ */
