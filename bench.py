@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads (512 structures, 1e5 atoms)")
     ap.add_argument("--no-density", action="store_true",
-                    help="skip the order -1 (local density), occupancy (disordered) and reference-point variants")
+                    help="skip the order -1 (local density), occupancy (disordered), reference-point and Jacobian variants")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
@@ -237,6 +237,36 @@ def points_variant(g, gs, torch, batch, probes, steps=10, warmup=3):
     del fb, fo, nb, ws, G, db
     torch.cuda.empty_cache()
     return out
+
+
+def jacobian_variant(g, gs, torch, batch, probes, db, steps=5, warmup=2):
+    """Full per-pair feature Jacobian (no contraction) of the 4096-atom cell,
+    FP32 compensated plan: time of one gmp_feature_jacobian call (adjoint
+    coefficients + pair kernel) and the rate at which it writes the
+    P x n_features x 3 output."""
+    plan = g.GMPPlan.from_probes(probes, "fp32c")
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws, reverse=False)
+    F, mu = g.features(plan, db, nb, ws)
+    out = torch.empty((plan.n_features, 3, nb.n_pairs), dtype=torch.float32, device="cuda")
+
+    def run():
+        g.feature_jacobian(plan, db, nb, ws, mu, out=out)
+    for _ in range(warmup):
+        run()
+    t = _median_ms(run, steps, torch)
+    with g.profile() as pr:
+        run()
+        torch.cuda.synchronize()
+    kern = {k: v[1] / v[0] for k, v in pr.result.items()}
+    nbytes = out.numel() * 4
+    res = {"pairs": int(nb.n_pairs), "features_per_atom": plan.n_features, "output_bytes": nbytes,
+           "call_ms": t, "pair_kernel_ms": kern.get("jacobian"),
+           "output_GB_per_s_pair_kernel": nbytes / (kern["jacobian"] * 1e-3) / 1e9 if "jacobian" in kern else None}
+    print(f"[bench] jacobian: {nbytes / 1e9:.2f} GB in {t:.3f} ms per call", file=sys.stderr, flush=True)
+    del out, nb, ws, F, mu
+    torch.cuda.empty_cache()
+    return res
 
 
 def batched_vs_per_structure(g, gs, torch):
@@ -519,6 +549,7 @@ def main():
         out["density_variant"] = density_variant(g, gs, torch, batch, probes, db)
         out["occupancy_variant"] = occupancy_variant(g, gs, torch, batch, probes)
         out["points_variant"] = points_variant(g, gs, torch, batch, probes)
+        out["jacobian"] = jacobian_variant(g, gs, torch, batch, probes, db)
     if not args.no_batched:
         del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()

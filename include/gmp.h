@@ -256,6 +256,22 @@ gmp_status gmp_features_backward(const gmp_plan *plan, const gmp_batch *batch,
                                  double *grad_pos, double *grad_cell, void *ws, size_t ws_bytes,
                                  void *stream);
 
+/* Full per-pair feature Jacobian ("Examples": feature derivatives with
+ * respect to the atom positions), without contraction: for centre i and pair
+ * p = (j, n) of its list (global index p, as in j / shift),
+ *   jac[(f * 3 + k) * ld + p] = dF_{i,f} / d d_{p,k},  d_p = R_j + n.cell - R_i,
+ * so dF_{i,f}/dR_j = sum of the pairs of i with neighbour j, dF_{i,f}/dR_i (or
+ * the reference point) = minus the sum over i's list, and dF_{i,f}/da_m =
+ * sum_p (n_m - m_j,m + m_i,m) J_p.  Pairs outside a slot's cutoff have zero
+ * entries for its features; entries of pairs past the lists are not written.
+ * jac: [n_features * 3 * ld], float for the FP32 modes, double for GMP_FP64;
+ * ld >= n_pairs (>= capacity when n_pairs is not known, e.g. after a no-sync
+ * build).  Needs the components of the forward; the reverse index is not
+ * used. */
+gmp_status gmp_feature_jacobian(const gmp_plan *plan, const gmp_batch *batch, const gmp_neighbors *nbrs,
+                                const double *components, void *jac, int64_t ld, void *ws, size_t ws_bytes,
+                                void *stream);
+
 /* Syncs `stream` and reports (and clears) the device status word in ws. */
 gmp_status gmp_check_status(void *ws, size_t ws_bytes, void *stream);
 

@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libgmp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "common.hip", "neighbors.hip", "overlap.hip", "adjoint.hip", "transpose.hip"]
+SOURCES = ["api.hip", "common.hip", "neighbors.hip", "overlap.hip", "adjoint.hip", "transpose.hip", "jacobian.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

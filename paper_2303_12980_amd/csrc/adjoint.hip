@@ -36,14 +36,6 @@ __device__ inline float fma_(float a, float b, float c) { return fmaf(a, b, c); 
 __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c); }
 
 
-// coefficient block per (centre, sigma): M [nmono(L)], then Dx, Dy, Dz
-// [nmono(L-1)] each; every part starts on a multiple of 4 entries so the
-// pair kernel's wavefront-uniform LDS reads can be 16-byte vector reads
-__host__ __device__ constexpr int round4(int n) { return (n + 3) & ~3; }
-__host__ __device__ constexpr int coef_m(int lmax) { return round4(nmono(lmax)); }
-__host__ __device__ constexpr int coef_d(int lmax) { return round4(nmono(lmax - 1)); }
-__host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax) + 3 * coef_d(lmax); }
-
 // One wavefront per index: centres get their coefficients, every index
 // (atoms, and reference points) its structure and packed position.
 template <bool F64>
@@ -83,7 +75,8 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
         for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
         F = sqrt(a);
       }
-      const double G = (double)((const T *)grad_features)[(size_t)i * P.nf + t];
+      // unit upstream gradient (grad_features null): the coefficients of dF/dd per feature
+      const double G = grad_features ? (double)((const T *)grad_features)[(size_t)i * P.nf + t] : 1.0;
       scale[t] = F > 0.0 ? G / F : 0.0;
     }
   }
@@ -484,6 +477,22 @@ void transpose_by_neighbour(const NbrDev &nb, int64_t n_centres, int64_t n_atoms
                             uint32_t *key_b, uint32_t *val_a, uint32_t *val_b, int32_t *hist, int64_t *off,
                             int64_t *scan_aux, int64_t *start, uint32_t **vals_out, hipStream_t s);
 
+// Per-centre adjoint coefficients (grad_features null: unit upstream
+// gradient, i.e. the coefficients of dF/dd of every feature), and the packed
+// positions and structures of all indices.
+void launch_bwd_coef(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
+                     const void *grad_features, const WsLayout &L, hipStream_t s) {
+  const int64_t blocks_all = (n_total(bt) + 3) / 4;
+  if (blocks_all == 0) return;
+  size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
+  if (p->prec == GMP_FP64)
+    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
+               components, grad_features, L.bcoef, L.rw4, L.astruct, L.counter);
+  else
+    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
+               components, grad_features, L.bcoef, L.rw4, L.astruct, L.counter);
+}
+
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, double *grad_pos, double *grad_cell, const WsLayout &L, int C,
                      int64_t pairs_bound, hipStream_t s) {
@@ -496,14 +505,8 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   int32_t *astruct = L.astruct;
   const bool f64 = p->prec == GMP_FP64;
   const int64_t blocks = (N + 3) / 4;
-  const int64_t blocks_all = (NT + 3) / 4;
-  size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
-  if (f64)
-    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
-               components, grad_features, bcoef, rw4, astruct, counter);
-  else
-    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
-               components, grad_features, bcoef, rw4, astruct, counter);
+  (void)NT;
+  launch_bwd_coef(p, bt, nb, components, grad_features, L, s);
   const int64_t n_items = N * (int64_t)C;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;

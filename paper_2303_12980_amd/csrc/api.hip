@@ -32,6 +32,8 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
                      const void *grad_features, double *grad_pos, double *grad_cell, const WsLayout &L, int C,
                      int64_t pairs_bound, hipStream_t s);
 void fill_zero3(void *p0, size_t b0, void *p1, size_t b1, void *p2, size_t b2, hipStream_t s);
+void launch_jacobian(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components, void *jac,
+                     int64_t ld, const WsLayout &L, int C, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -334,6 +336,7 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   P.kb = kb;
   P.lmax = 0;
   int coff = 0, foff = 0;
+  for (int l = 0; l <= kMaxL; ++l) P.order_idx[l] = -1;
   for (int o = 0; o < p->n_orders; ++o) {
     const int l = d->orders[o];
     p->orders[o] = l;
@@ -346,6 +349,7 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
       foff += 1;
       continue;
     }
+    P.order_idx[l] = o;
     coff += P.n_sig * ncomp(l);
     foff += P.n_sig;
     if (l > P.lmax) P.lmax = l;
@@ -750,6 +754,36 @@ gmp_status gmp_features_backward(const gmp_plan *p, const gmp_batch *b, const gm
   launch_backward(p, bt, nb, components, grad_features, grad_pos, grad_cell, L, (int)C, pairs, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "adjoint kernels");
+  return GMP_OK;
+}
+
+gmp_status gmp_feature_jacobian(const gmp_plan *p, const gmp_batch *b, const gmp_neighbors *n,
+                                const double *components, void *jac, int64_t ld, void *ws, size_t ws_bytes,
+                                void *stream) {
+  gmp_status st = check_batch(p, b);
+  if (st) return st;
+  st = check_nbrs(p, b, n, true);
+  if (st) return st;
+  const int64_t N = batch_centres(b);
+  if (N == 0) return GMP_OK;
+  if (!components || !jac) return set_error(GMP_E_INVALID, "null jacobian argument");
+  const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
+  if (ld < pairs) return set_error(GMP_E_INVALID, "ld smaller than the pair count (capacity in no-sync use)");
+  if (!ws) return set_error(GMP_E_INVALID, "null workspace");
+  hipStream_t s = (hipStream_t)stream;
+  WsLayout L = carve(p, b->n_structs, b->n_atoms, batch_points(b), n->capacity, ws, ws_bytes);
+  if (L.bytes > ws_bytes) return set_error(GMP_E_NOMEM, "workspace too small");
+  BatchDev bt = to_dev(b);
+  NbrDev nb = to_dev(n);
+  int64_t chunk = p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 256;
+  int64_t by_pairs = (pairs / N) / chunk;
+  if (by_pairs < 1) by_pairs = 1;
+  int64_t want = (8192 + N - 1) / N;
+  int64_t C = want < by_pairs ? want : by_pairs;
+  if (C < 1) C = 1;
+  launch_jacobian(p, bt, nb, components, jac, ld, L, (int)C, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(e, "jacobian kernels");
   return GMP_OK;
 }
 

@@ -70,6 +70,14 @@ __host__ __device__ constexpr MonoTable make_mono_table() {
   return t;
 }
 
+// Adjoint coefficient block per (centre, slot): M [nmono(L)], then Dx, Dy,
+// Dz [nmono(L-1)] each; every part starts on a multiple of 4 entries so the
+// pair kernels' wavefront-uniform LDS reads can be 16-byte vector reads.
+__host__ __device__ constexpr int round4(int n) { return (n + 3) & ~3; }
+__host__ __device__ constexpr int coef_m(int lmax) { return round4(nmono(lmax)); }
+__host__ __device__ constexpr int coef_d(int lmax) { return round4(nmono(lmax - 1)); }
+__host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax) + 3 * coef_d(lmax); }
+
 struct StructInfo {
   double b[9];        // reciprocal rows
   double reach[3];    // fractional reach rc_max/h_k (periodic axes)
@@ -89,6 +97,7 @@ struct PlanDev {
   int orders[kMaxOrders];
   int comp_off[kMaxOrders];       // offset of order o's (sigma, component) block in one centre's components
   int feat_off[kMaxOrders];       // first feature of order o (n_sig features per order, 1 for order -1)
+  int order_idx[kMaxL + 1];       // index o of angular order l in orders (-1: not requested)
   int sig_order[kMaxSigmas];      // slots sorted by rc^2 ascending (stable)
   int rank_lt[kMaxSigmas];        // #{s': rc2[s'] < rc2[s]}
   double rc2[kMaxSigmas];

@@ -22,7 +22,8 @@ from ._lib import GMPError, check
 
 __all__ = ["GMPPlan", "DeviceBatch", "Neighbors", "Workspace", "build_neighbors", "rebuild_neighbors_nosync",
            "build_reverse",
-           "check_status", "features", "features_backward", "GMPFunction", "CapturedStep", "feature_labels",
+           "check_status", "features", "features_backward", "feature_jacobian", "pair_centres", "GMPFunction",
+           "CapturedStep", "feature_labels",
            "profile", "GMPError"]
 
 
@@ -353,6 +354,31 @@ def features_backward(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Work
                                   _ptr(gpos), _ptr(gcell), _ptr(buf), buf.numel(), _stream_ptr(stream)))
     gp = gpos.view(3, N).t()
     return gp, (gcell.view(-1, 3, 3) if want_cell else None)
+
+
+def feature_jacobian(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Workspace, mu, xyz=None, cell=None,
+                     out=None, stream=None):
+    """Per-pair feature Jacobian (no contraction): returns J [P, n_features, 3]
+    with J[p, f] = dF_{i,f}/dd_p for pair p = (i; j, n) of the lists (a view
+    of the [n_features, 3, ld] buffer the library writes; P = nb.n_pairs).
+    Centres of the pairs: pair_centres(nb); neighbours: nb.j."""
+    L = _lib.load()
+    ld = nb.n_pairs if nb.n_pairs > 0 else nb.capacity
+    dev = batch.species.device
+    buf = out if out is not None else torch.empty((plan.n_features, 3, max(ld, 1)), dtype=plan.dtype, device=dev)
+    ld = buf.shape[2]
+    wsb = ws.get(plan.batch_workspace_bytes(batch, nb.capacity))
+    bd, nd = batch.desc(xyz, cell), nb.desc()
+    check(L.gmp_feature_jacobian(plan.handle, ctypes.byref(bd), ctypes.byref(nd), _ptr(mu), _ptr(buf), ld,
+                                 _ptr(wsb), wsb.numel(), _stream_ptr(stream)))
+    return buf[:, :, :nb.n_pairs].permute(2, 0, 1)
+
+
+def pair_centres(nb: Neighbors):
+    """Centre index of every pair of the lists (int64 [n_pairs])."""
+    offs = nb.offsets
+    cnt = offs[1:] - offs[:-1]
+    return torch.repeat_interleave(torch.arange(len(cnt), device=offs.device, dtype=torch.int64), cnt)
 
 
 class GMPFunction(torch.autograd.Function):
