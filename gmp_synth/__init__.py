@@ -40,6 +40,8 @@ class Probes:
                    prim_offsets[e] .. prim_offsets[e+1]-1
     B, beta:       float64 [n_prims]; primitive B*exp(-beta*r^2)
     tau:           overlap threshold (sets the cutoff per sigma)
+    screening:     per-primitive screening (each primitive only inside its
+                   own threshold radius), a variant of the cutoff rule
     """
     orders: np.ndarray
     sigmas: np.ndarray
@@ -47,6 +49,7 @@ class Probes:
     B: np.ndarray
     beta: np.ndarray
     tau: float
+    screening: bool = False
 
     @property
     def n_elements(self) -> int:

@@ -61,7 +61,7 @@ def lib():
             L.oracle_neighbors.argtypes = [c_int, dp, ip, dp, c_int, c_int, dp, c_int, c_i64,
                                            ip, ip, dp, ip, ip]
             L.oracle_neighbors.restype = c_i64
-            probe_args = [c_int, ip, c_int, dp, c_int, ip, dp, dp, c_dbl]
+            probe_args = [c_int, ip, c_int, dp, c_int, ip, dp, dp, c_dbl, c_int]
             L.oracle_slot_cutoffs.argtypes = [*probe_args, dp]
             L.oracle_slot_cutoffs.restype = c_int
             L.oracle_features.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp, dp]
@@ -122,7 +122,8 @@ def _probe_args(probes):
     po, pop = _i(probes.prim_offsets); keep.append(po)
     B, Bp = _d(probes.B); keep.append(B)
     be, bep = _d(probes.beta); keep.append(be)
-    args = [len(o), op, len(s), sp, len(po) - 1, pop, Bp, bep, float(probes.tau)]
+    args = [len(o), op, len(s), sp, len(po) - 1, pop, Bp, bep, float(probes.tau),
+            int(bool(getattr(probes, "screening", False)))]
     return keep, args
 
 

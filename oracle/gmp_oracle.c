@@ -182,6 +182,7 @@ typedef struct {
   int n_elements; const int32_t *prim_offsets;
   const double *B, *beta;
   double tau;
+  int screen;  /* per-primitive screening (see primitive_used) */
 } probes_t;
 
 int oracle_cutoffs(int n_sigmas, const double *sigmas, int n_elements,
@@ -240,22 +241,42 @@ static int slot_cutoffs(const probes_t *P, double *rc2) {
   return st;
 }
 
-/* density of element e's primitives at squared distance q, as a dual number */
-static dual density(const probes_t *P, int e, dual q) {
+/*
+ * Per-primitive screening (a speed variant of the cutoff rule, off by
+ * default): primitive k of element e contributes to a slot only where its own
+ * l = 0 overlap reaches the threshold, |A0| exp(-gamma q) >= tau, i.e. for
+ * q <= r_k^2 = ln(|A0|/tau)/gamma (never when |A0| <= tau); for the density
+ * slot A0 = B and gamma = beta.  The decision compares q and r_k^2 rounded to
+ * FP32, the precision the GPU kernels take it in.  Every skipped term is
+ * below tau (beta/lambda)^l <= tau in its radial factor.
+ */
+static int primitive_used(const probes_t *P, double A0abs, double gam, double qsel) {
+  if (!P->screen) return 1;
+  double thr = A0abs > P->tau ? log(A0abs / P->tau) / gam : -1.0;
+  return (float)qsel <= (float)thr;
+}
+
+/* density of element e's primitives at squared distance q, as a dual number;
+ * qsel decides the screened primitives */
+static dual density(const probes_t *P, int e, dual q, double qsel) {
   dual acc = dconst(0.0);
-  for (int k = P->prim_offsets[e]; k < P->prim_offsets[e + 1]; ++k)
+  for (int k = P->prim_offsets[e]; k < P->prim_offsets[e + 1]; ++k) {
+    if (!primitive_used(P, fabs(P->B[k]), P->beta[k], qsel)) continue;
     acc = dadd(acc, dscale(P->B[k], dexp(dscale(-P->beta[k], q))));
+  }
   return acc;
 }
 
-/* radial factor c_{l,s,e}(q) as a dual number in d */
-static dual radial(const probes_t *P, int l, int s, int e, dual q) {
+/* radial factor c_{l,s,e}(q) as a dual number in d; qsel decides the
+ * screened primitives */
+static dual radial(const probes_t *P, int l, int s, int e, dual q, double qsel) {
   double sg = P->sigmas[s];
   double alpha = 1.0 / (2.0 * sg * sg);
   dual acc = dconst(0.0);
   for (int k = P->prim_offsets[e]; k < P->prim_offsets[e + 1]; ++k) {
     double lam = alpha + P->beta[k];
     double gam = alpha * P->beta[k] / lam;
+    if (!primitive_used(P, fabs(P->B[k]) * pow(alpha / lam, 1.5), gam, qsel)) continue;
     double A = P->B[k] * pow(alpha / lam, 1.5) * pow(P->beta[k] / lam, (double)l);
     acc = dadd(acc, dscale(A, dexp(dscale(-gam, q))));
   }
@@ -463,13 +484,13 @@ static void pair_terms(const probes_t *P, const pair_t *pp, double use, const do
   for (int o = 0; o < P->n_orders; ++o) {
     int l = P->orders[o];
     if (l < 0) {
-      if (use <= rc2[P->n_sigmas]) mu[off] += pp->w * density(P, pp->e, q).v;
+      if (use <= rc2[P->n_sigmas]) mu[off] += pp->w * density(P, pp->e, q, use).v;
       off += 1;
       continue;
     }
     for (int s = 0; s < P->n_sigmas; ++s) {
       if (!(use <= rc2[s])) continue;
-      double c = radial(P, l, s, pp->e, q).v;
+      double c = radial(P, l, s, pp->e, q, use).v;
       for (int k = 0; k < ncomp(l); ++k) {
         int a, b, cc; comp_abc(l, k, &a, &b, &cc);
         mu[(size_t)(off + s * ncomp(l) + k)] += pp->w * (c * solid_harmonic(a, b, cc, x, y, z).v);
@@ -521,10 +542,10 @@ int oracle_features(int n_atoms, const double *pos, const int32_t *species,
                     const double *cell, int pbc,
                     int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                     int n_elements, const int32_t *prim_offsets, const double *B,
-                    const double *beta, double tau,
+                    const double *beta, double tau, int screen,
                     int n_centres, const int32_t *centres, double *F, double *mu,
                     const double *occ) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   int st = check_probes(&P);
   if (st) return st;
   for (int i = 0; i < n_atoms; ++i)
@@ -569,7 +590,7 @@ static void pair_v(const probes_t *P, const pair_t *pp, const double *rc2, const
     int l = P->orders[o];
     if (l < 0) {
       if (pp->q <= rc2[P->n_sigmas] && W[off] != 0.0) {
-        dual t = density(P, pp->e, q);
+        dual t = density(P, pp->e, q, pp->q);
         v[0] += W[off] * t.g[0]; v[1] += W[off] * t.g[1]; v[2] += W[off] * t.g[2];
       }
       off += 1;
@@ -577,7 +598,7 @@ static void pair_v(const probes_t *P, const pair_t *pp, const double *rc2, const
     }
     for (int s = 0; s < P->n_sigmas; ++s) {
       if (!(pp->q <= rc2[s])) continue;
-      dual c = radial(P, l, s, pp->e, q);
+      dual c = radial(P, l, s, pp->e, q, pp->q);
       for (int k = 0; k < ncomp(l); ++k) {
         int a, b, cc; comp_abc(l, k, &a, &b, &cc);
         double w = W[off + s * ncomp(l) + k];
@@ -623,10 +644,10 @@ int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
                 const double *cell, int pbc,
                 int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                 int n_elements, const int32_t *prim_offsets, const double *B,
-                const double *beta, double tau,
+                const double *beta, double tau, int screen,
                 const double *G, double *grad_pos, double *grad_cell, double *F_out,
                 const double *occ) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   int st = check_probes(&P);
   if (st) return st;
   for (int i = 0; i < n_atoms; ++i)
@@ -719,10 +740,10 @@ int oracle_loss_frozen(int n_atoms, const double *pos, const int32_t *species,
                        const double *cell,
                        int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                        int n_elements, const int32_t *prim_offsets, const double *B,
-                       const double *beta, double tau,
+                       const double *beta, double tau, int screen,
                        const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
                        const double *G, double *L_out, const double *occ) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   return loss_frozen_impl(&P, pos, species, cell, n_atoms, pos, po, pj, pn, pq, G, L_out, occ);
 }
 
@@ -741,9 +762,9 @@ int64_t oracle_jacobian(int n_atoms, const double *pos, const int32_t *species,
                         const double *cell, int pbc,
                         int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                         int n_elements, const int32_t *prim_offsets, const double *B,
-                        const double *beta, double tau, int64_t cap, double *jac,
+                        const double *beta, double tau, int screen, int64_t cap, double *jac,
                         const double *occ, int32_t *status) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   *status = check_probes(&P);
   if (*status) return 0;
   for (int i = 0; i < n_atoms; ++i)
@@ -859,9 +880,9 @@ int oracle_point_features(int n_atoms, const double *pos, const int32_t *species
                           const double *cell, int pbc,
                           int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                           int n_elements, const int32_t *prim_offsets, const double *B,
-                          const double *beta, double tau,
+                          const double *beta, double tau, int screen,
                           int n_points, const double *points, double *F, double *mu, const double *occ) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   point_sys_t Q;
   int st = point_sys(&Q, &P, n_atoms, pos, species, cell, pbc, n_points, points);
   if (st) return st;
@@ -886,10 +907,10 @@ int oracle_point_grad(int n_atoms, const double *pos, const int32_t *species,
                       const double *cell, int pbc,
                       int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                       int n_elements, const int32_t *prim_offsets, const double *B,
-                      const double *beta, double tau,
+                      const double *beta, double tau, int screen,
                       int n_points, const double *points, const double *G, double *grad_pos,
                       double *grad_points, double *grad_cell, double *F_out, const double *occ) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   point_sys_t Q;
   int st = point_sys(&Q, &P, n_atoms, pos, species, cell, pbc, n_points, points);
   if (st) return st;
@@ -930,19 +951,19 @@ int oracle_point_loss_frozen(int n_atoms, const double *pos, const int32_t *spec
                              const double *cell,
                              int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                              int n_elements, const int32_t *prim_offsets, const double *B,
-                             const double *beta, double tau, int n_points, const double *points,
+                             const double *beta, double tau, int screen, int n_points, const double *points,
                              const int64_t *po, const int32_t *pj, const int32_t *pn, const double *pq,
                              const double *G, double *L_out, const double *occ) {
   (void)n_atoms;
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   return loss_frozen_impl(&P, pos, species, cell, n_points, points, po, pj, pn, pq, G, L_out, occ);
 }
 
 /* rc^2 of every slot (the sigmas, then the density when order -1 is requested) */
 int oracle_slot_cutoffs(int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
                         int n_elements, const int32_t *prim_offsets, const double *B,
-                        const double *beta, double tau, double *rc2) {
-  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau};
+                        const double *beta, double tau, int screen, double *rc2) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
   int st = check_probes(&P);
   if (st) return st;
   return slot_cutoffs(&P, rc2);
