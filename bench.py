@@ -71,7 +71,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads (512 structures, 1e5 atoms)")
     ap.add_argument("--no-density", action="store_true",
-                    help="skip the order -1 (local density), occupancy (disordered), reference-point and Jacobian variants")
+                    help="skip the order -1 (local density), occupancy (disordered), reference-point, Jacobian and "
+                         "screening variants")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (counter calibration)")
     return ap.parse_args()
@@ -267,6 +268,49 @@ def jacobian_variant(g, gs, torch, batch, probes, db, steps=5, warmup=2):
     del out, nb, ws, F, mu
     torch.cuda.empty_cache()
     return res
+
+
+def screening_variant(g, gs, torch, batch, probes, db, steps=10, warmup=3):
+    """The same 4096-atom cell with per-primitive screening (each primitive
+    only inside its own threshold radius): graph-replayed fwd+bwd and fwd in
+    FP32 compensated mode, its deviation from the screened FP64 oracle and
+    the screened oracle's own distance from the unscreened one on sampled
+    centres."""
+    import oracle
+    ps = gs.Probes(probes.orders, probes.sigmas, probes.prim_offsets, probes.B, probes.beta, probes.tau,
+                   screening=True)
+    N, nf = batch.n_atoms, ps.n_features
+    plan = g.GMPPlan.from_probes(ps, "fp32c")
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    nbf = g.build_neighbors(plan, db, ws, reverse=False)
+    G = torch.as_tensor(np.random.default_rng(7).standard_normal((N, nf)), device="cuda")
+    fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
+    fo = g.CapturedStep(plan, db, ws, nbf, backward=False)
+    for _ in range(warmup):
+        fb.replay()
+        fo.replay()
+    t_fb = _median_ms(fb.replay, steps, torch)
+    t_fo = _median_ms(fo.replay, steps, torch)
+    g.check_status(ws)
+    with g.profile() as pr:
+        g.features(plan, db, nbf, ws)
+        torch.cuda.synchronize()
+    cs = np.sort(np.random.default_rng(29).choice(N, size=24, replace=False))
+    Fs = oracle.features(batch.structure(0), ps, centres=cs)
+    Fe = oracle.features(batch.structure(0), probes, centres=cs)
+    Fg = fb.F.double().cpu().numpy()[cs]
+    big = Fs > probes.tau
+    out = {"fwd_bwd_ms": t_fb, "fwd_ms": t_fo, "atoms_features_per_s_fwd_bwd": N * nf / (t_fb * 1e-3),
+           "overlap_kernel_ms": pr.result["overlap"][1] / pr.result["overlap"][0],
+           "max_rel_err_vs_screened_oracle": float(np.max(np.abs(Fg[big] - Fs[big]) / Fs[big])),
+           "screened_vs_unscreened_oracle_max_rel": float(np.max(np.abs(Fs[big] - Fe[big]) / Fe[big])),
+           "sampled_centres": len(cs)}
+    print(f"[bench] screening: fwd+bwd {t_fb:.3f} ms, fwd {t_fo:.3f} ms, overlap {out['overlap_kernel_ms']:.3f} ms",
+          file=sys.stderr, flush=True)
+    del fb, fo, nb, nbf, ws, G
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_vs_per_structure(g, gs, torch):
@@ -550,6 +594,7 @@ def main():
         out["occupancy_variant"] = occupancy_variant(g, gs, torch, batch, probes)
         out["points_variant"] = points_variant(g, gs, torch, batch, probes)
         out["jacobian"] = jacobian_variant(g, gs, torch, batch, probes, db)
+        out["screening_variant"] = screening_variant(g, gs, torch, batch, probes, db)
     if not args.no_batched:
         del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()

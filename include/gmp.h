@@ -90,6 +90,12 @@ typedef struct {
   const double *B;               /* [prim_offsets[n_elements]] primitive weights (any sign) */
   const double *beta;            /* [prim_offsets[n_elements]] exponents, > 0 (1/Angstrom^2) */
   double overlap_threshold;      /* tau > 0: rc(sigma)^2 = max_{e,k} ln(|A0|/tau)/gamma */
+  int32_t screening;             /* 0: every primitive of a neighbour inside the slot cutoff contributes.
+                                    1: per-primitive screening, a faster variant of the truncation:
+                                    primitive k of element e contributes to slot s only where its own
+                                    l = 0 overlap reaches tau, (float)q <= (float)(ln(|A0|/tau)/gamma)
+                                    (never when |A0| <= tau; density slot: A0 = B, gamma = beta); each
+                                    skipped radial term is below tau */
 } gmp_probe_desc;
 
 /* A packed batch of structures (CSR over atoms); mirrors the featurizer's

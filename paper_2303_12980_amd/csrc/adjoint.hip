@@ -220,7 +220,13 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
           for (int k = 0; k < KB; ++k) {
             if (k < K) {
               const size_t o = roff + k * kCoefStride;
-              const T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+              bool use = true;
+              if (P.screen) {  // per-primitive screening: the primitive's own radius
+                use = (float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]);
+                if (__ballot(use) == 0) continue;
+              }
+              T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+              ek = use ? ek : (T)0;
               cp0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], (LDS ? tabl[o + 6] : tabg[o + 6]) * ek, cp0);
             }
           }
@@ -239,7 +245,13 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
         for (int k = 0; k < KB; ++k) {
           if (k < K) {
             const size_t o = roff + k * kCoefStride;
-            const T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+            bool use = true;
+            if (P.screen) {  // per-primitive screening: the primitive's own radius
+              use = (float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]);
+              if (__ballot(use) == 0) continue;
+            }
+            T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+            ek = use ? ek : (T)0;
             const T gk = (LDS ? tabl[o + 6] : tabg[o + 6]) * ek;
 #pragma unroll
             for (int l = 0; l <= LMAX; ++l) {

@@ -228,6 +228,7 @@ static gmp_status validate_desc(const gmp_probe_desc *d, int *mask_out, int *kma
     return set_error(GMP_E_INVALID, "n_elements must be 1..64");
   if (!(d->overlap_threshold > 0.0) || !isfinite(d->overlap_threshold))
     return set_error(GMP_E_INVALID, "overlap_threshold must be positive and finite");
+  if (d->screening != 0 && d->screening != 1) return set_error(GMP_E_INVALID, "screening must be 0 or 1");
   int mask = 0, dens = 0;
   for (int o = 0; o < d->n_orders; ++o) {
     int l = d->orders[o];
@@ -328,6 +329,7 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   P.n_sig = d->n_sigmas;
   P.dens_slot = dens ? d->n_sigmas : -1;
   P.dens_order = -1;
+  P.screen = d->screening;
   P.E = p->E;
   P.n_orders = p->n_orders;
   P.order_mask = mask;
@@ -372,6 +374,11 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
         c32[idx + 1] = (float)d->B[k];
         c64[idx + 6] = -d->beta[k];
         c32[idx + 6] = (float)(-d->beta[k]);
+        // screening radius^2: |B| exp(-beta q) >= tau (FP32 value, as the kernels compare)
+        const double bb = fabs(d->B[k]);
+        const float r2 = (float)(bb > d->overlap_threshold ? log(bb / d->overlap_threshold) / d->beta[k] : -1.0);
+        c64[idx + 7] = r2;
+        c32[idx + 7] = r2;
       }
     p->rc2[s] = P.rc2[s] = density_cutoff2(d);
     rcmax2 = P.rc2[s];
@@ -399,6 +406,11 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
         }
         c64[idx + 6] = -gam;
         c32[idx + 6] = (float)(-gam);
+        // screening radius^2: the primitive's own l = 0 overlap reaches tau (FP32 value)
+        const double A0 = fabs(d->B[k]) * pow(alpha / lam, 1.5);
+        const float r2 = (float)(A0 > d->overlap_threshold ? log(A0 / d->overlap_threshold) / gam : -1.0);
+        c64[idx + 7] = r2;
+        c32[idx + 7] = r2;
       }
     p->rc2[s] = best;
     P.rc2[s] = best;

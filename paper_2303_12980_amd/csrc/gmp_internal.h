@@ -20,7 +20,7 @@ constexpr int kMaxOrders = 6;    // -1 (local density) and 0..4
 constexpr int kMaxSigmas = 16;   // cutoff slots: the sigmas plus the density slot of order -1
 constexpr int kMaxElements = 64;
 constexpr int kMaxL = 4;
-constexpr int kCoefStride = 8;    // per (sigma, element, primitive): -g', A0..A4, -gamma, pad
+constexpr int kCoefStride = 8;    // per (slot, element, primitive): -g', A0..A4, -gamma, screening radius^2
 constexpr int kMaxPrims = 16;
 constexpr int kSortMax = 8192;    // largest per-centre list sorted in LDS
 constexpr int kWave = 64;
@@ -94,6 +94,7 @@ struct StructInfo {
 struct PlanDev {
   int S, E, n_orders, lmax, order_mask, kmax, kb, nf, ncomp_total;  // kb: primitive stride of the tables (4/8/16)
   int n_sig, dens_slot, dens_order;  // sigmas, density slot, index of order -1 in orders (-1: none)
+  int screen;                        // per-primitive screening (radius^2 in column 7 of the tables, FP32 value)
   int orders[kMaxOrders];
   int comp_off[kMaxOrders];       // offset of order o's (sigma, component) block in one centre's components
   int feat_off[kMaxOrders];       // first feature of order o (n_sig features per order, 1 for order -1)
@@ -102,8 +103,8 @@ struct PlanDev {
   int rank_lt[kMaxSigmas];        // #{s': rc2[s'] < rc2[s]}
   double rc2[kMaxSigmas];
   double rcmax2;
-  const float *coef32;            // [S][E][kb][kCoefStride]: -gamma*log2(e), A_0..A_4, -gamma (zero rows past K_e)
-  const double *coef64;           // [S][E][kb][kCoefStride]: -gamma, A_0..A_4, -gamma
+  const float *coef32;            // [S][E][kb][kCoefStride]: -gamma*log2(e), A_0..A_4, -gamma, r^2 (zero rows past K_e)
+  const double *coef64;           // [S][E][kb][kCoefStride]: -gamma, A_0..A_4, -gamma, r^2
   const int *kcount;              // [E]
   const double *T;                // moment->component maps, per order l: ncomp(l)^2 at toff[l]
   int toff[kMaxL + 1];

@@ -103,6 +103,7 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
             for (int k = 0; k < KB; ++k) {
               if (k < K) {
                 const size_t o = roff + k * kCoefStride;
+                if (P.screen && !((float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]))) continue;
                 const T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
                 cp0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], (LDS ? tabl[o + 6] : tabg[o + 6]) * ek, cp0);
               }
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
           for (int k = 0; k < KB; ++k) {
             if (k < K) {
               const size_t o = roff + k * kCoefStride;
+              if (P.screen && !((float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]))) continue;
               const T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
               const T gk = (LDS ? tabl[o + 6] : tabg[o + 6]) * ek;
 #pragma unroll

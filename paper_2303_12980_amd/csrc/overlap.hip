@@ -155,7 +155,7 @@ template <int MODE, int NM> __device__ inline double acc_value(const Acc<MODE, N
 // The coefficient table [sigma][element][KB][8] (exponent scale, A_0..A_4,
 // -gamma) is copied into LDS once per workgroup when it fits; lanes read
 // the row of their own neighbour's species.
-template <int LMAX, int KB, int MODE, bool LDS, bool DENS>
+template <int LMAX, int KB, int MODE, bool LDS, bool DENS, bool SCREEN>
 __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
                                                  const int32_t *astruct, double *partial, const int64_t *chunk_off,
                                                  int kc, unsigned long long *counter, const void *tab_global) {
@@ -260,7 +260,8 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         const double dx = (rjx - rix) + shx;
         const double dy = (rjy - riy) + shy;
         const double dz = (rjz - riz) + shz;
-        const TR qv = (TR)((dx * dx + dy * dy) + dz * dz);
+        const double q = (dx * dx + dy * dy) + dz * dz;
+        const TR qv = (TR)q;
         const int e = shift_species(w);
         const int K = lds_k[e];
         const size_t roff = ((size_t)(sgm * E + e) * KB) * kCoefStride;
@@ -269,7 +270,13 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         for (int k = 0; k < KB; ++k) {
           if (k < K) {
             const size_t o = roff + k * kCoefStride;
-            c0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], exp_scaled(LDS ? tabl[o] : tabg[o], qv), c0);
+            bool use = true;
+            if constexpr (SCREEN) {  // the primitive's own radius; skipped by the wavefront when no lane needs it
+              use = (float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]);
+              if (__ballot(use) == 0) continue;
+            }
+            const TR ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+            c0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], use ? ek : (TR)0, c0);
           }
         }
         c0 = c0 * (TR)occj;
@@ -293,7 +300,13 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         for (int k = 0; k < KB; ++k) {
           if (k < K) {
             const size_t o = roff + k * kCoefStride;
-            const TR ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+            bool use = true;
+            if constexpr (SCREEN) {  // the primitive's own radius; skipped by the wavefront when no lane needs it
+              use = (float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]);
+              if (__ballot(use) == 0) continue;
+            }
+            TR ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
+            if constexpr (SCREEN) ek = use ? ek : (TR)0;
 #pragma unroll
             for (int l = 0; l <= LMAX; ++l) cl[l] = fma_(LDS ? tabl[o + 1 + l] : tabg[o + 1 + l], ek, cl[l]);
           }
@@ -401,32 +414,34 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
 using OverlapFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const int32_t *, double *, const int64_t *,
                            int, unsigned long long *, const void *);
 
-// DENS: the plan has the density slot of order -1 (a separate instantiation
-// keeps that branch out of the loop of plans without it)
-template <int L, int MODE, bool LDS, bool DENS> OverlapFn pick_k(int kb) {
-  if (kb <= 4) return k_overlap<L, 4, MODE, LDS, DENS>;
-  if (kb <= 8) return k_overlap<L, 8, MODE, LDS, DENS>;
-  return k_overlap<L, 16, MODE, LDS, DENS>;
+// DENS: the plan has the density slot of order -1; SCREEN: per-primitive
+// screening (separate instantiations keep both branches out of the loop of
+// plans without them)
+template <int L, int MODE, bool LDS, bool DENS, bool SCREEN> OverlapFn pick_k(int kb) {
+  if (kb <= 4) return k_overlap<L, 4, MODE, LDS, DENS, SCREEN>;
+  if (kb <= 8) return k_overlap<L, 8, MODE, LDS, DENS, SCREEN>;
+  return k_overlap<L, 16, MODE, LDS, DENS, SCREEN>;
 }
 
-template <int MODE, bool LDS, bool DENS> OverlapFn pick_l(int lmax, int kb) {
+template <int MODE, bool LDS, bool DENS, bool SCREEN> OverlapFn pick_l(int lmax, int kb) {
   switch (lmax) {
-    case 0: return pick_k<0, MODE, LDS, DENS>(kb);
-    case 1: return pick_k<1, MODE, LDS, DENS>(kb);
-    case 2: return pick_k<2, MODE, LDS, DENS>(kb);
-    case 3: return pick_k<3, MODE, LDS, DENS>(kb);
-    default: return pick_k<4, MODE, LDS, DENS>(kb);
+    case 0: return pick_k<0, MODE, LDS, DENS, SCREEN>(kb);
+    case 1: return pick_k<1, MODE, LDS, DENS, SCREEN>(kb);
+    case 2: return pick_k<2, MODE, LDS, DENS, SCREEN>(kb);
+    case 3: return pick_k<3, MODE, LDS, DENS, SCREEN>(kb);
+    default: return pick_k<4, MODE, LDS, DENS, SCREEN>(kb);
   }
 }
 
-template <bool LDS, bool DENS> OverlapFn pick_d(gmp_precision prec, int lmax, int kb) {
-  if (prec == GMP_FP64) return pick_l<ACC_F64, LDS, DENS>(lmax, kb);
-  if (prec == GMP_FP32_WIDE) return pick_l<ACC_WIDE, LDS, DENS>(lmax, kb);
-  return pick_l<ACC_TWOSUM, LDS, DENS>(lmax, kb);
+template <bool LDS, bool DENS, bool SCREEN> OverlapFn pick_d(gmp_precision prec, int lmax, int kb) {
+  if (prec == GMP_FP64) return pick_l<ACC_F64, LDS, DENS, SCREEN>(lmax, kb);
+  if (prec == GMP_FP32_WIDE) return pick_l<ACC_WIDE, LDS, DENS, SCREEN>(lmax, kb);
+  return pick_l<ACC_TWOSUM, LDS, DENS, SCREEN>(lmax, kb);
 }
 
-template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb, bool dens) {
-  return dens ? pick_d<LDS, true>(prec, lmax, kb) : pick_d<LDS, false>(prec, lmax, kb);
+template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb, bool dens, bool screen) {
+  if (screen) return dens ? pick_d<LDS, true, true>(prec, lmax, kb) : pick_d<LDS, false, true>(prec, lmax, kb);
+  return dens ? pick_d<LDS, true, false>(prec, lmax, kb) : pick_d<LDS, false, false>(prec, lmax, kb);
 }
 
 }  // namespace
@@ -482,8 +497,9 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
   const size_t smem = use_lds ? tab_bytes : 0;
   const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
   const bool dens = p->dev.dens_slot >= 0;
-  OverlapFn fn = use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb, dens)
-                         : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb, dens);
+  const bool screen = p->dev.screen != 0;
+  OverlapFn fn = use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb, dens, screen)
+                         : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb, dens, screen);
   const int64_t items_bound = max_chunks(p, N, pairs_bound);
   int64_t blocks = persistent_blocks((const void *)fn, smem, p->tuning.blocks_per_cu);
   const int64_t need = (items_bound + 3) / 4;

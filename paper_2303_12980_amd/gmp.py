@@ -53,7 +53,8 @@ def feature_labels(orders: Sequence[int], sigmas: Sequence[float]):
 class GMPPlan:
     """Probe set + density primitives + precision (wraps gmp_plan)."""
 
-    def __init__(self, orders, sigmas, prim_offsets, B, beta, overlap_threshold, precision="fp32c"):
+    def __init__(self, orders, sigmas, prim_offsets, B, beta, overlap_threshold, precision="fp32c",
+                 screening=False):
         L = _lib.load()
         self._orders = np.ascontiguousarray(orders, dtype=np.int32)
         self._sigmas = np.ascontiguousarray(sigmas, dtype=np.float64)
@@ -67,7 +68,8 @@ class GMPPlan:
                            len(self._sigmas), self._sigmas.ctypes.data_as(_lib.P_dbl),
                            len(self._poff) - 1, self._poff.ctypes.data_as(_lib.P_i32),
                            self._B.ctypes.data_as(_lib.P_dbl), self._beta.ctypes.data_as(_lib.P_dbl),
-                           self.tau)
+                           self.tau, 1 if screening else 0)
+        self.screening = bool(screening)
         h = ctypes.c_void_p(0)
         check(L.gmp_plan_create(ctypes.byref(d), prec, ctypes.byref(h)))
         self._h = h
@@ -83,7 +85,7 @@ class GMPPlan:
     @classmethod
     def from_probes(cls, probes, precision="fp32c"):
         return cls(probes.orders, probes.sigmas, probes.prim_offsets, probes.B, probes.beta, probes.tau,
-                   precision)
+                   precision, getattr(probes, "screening", False))
 
     @property
     def orders(self):
