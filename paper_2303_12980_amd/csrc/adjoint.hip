@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
 // and read wavefront-uniformly.  The loads of pair data (j, shift) run two
 // steps ahead and the gathers of the neighbours' wrapped positions one step
 // ahead.  Dynamic LDS: [coefficient table if staged][4 wavefronts][S * NB].
-template <int LMAX, int KB, bool F64, bool LDS>
+template <int LMAX, int KB, bool F64, bool LDS, bool SCREEN>
 __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
                                                    const int32_t *astruct, const void *bcoef_, void *vbuf_, int C,
                                                    int64_t n_items,
@@ -221,12 +221,12 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
             if (k < K) {
               const size_t o = roff + k * kCoefStride;
               bool use = true;
-              if (P.screen) {  // per-primitive screening: the primitive's own radius
+              if constexpr (SCREEN) {  // per-primitive screening: the primitive's own radius
                 use = (float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]);
                 if (__ballot(use) == 0) continue;
               }
               T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
-              ek = use ? ek : (T)0;
+              if constexpr (SCREEN) ek = use ? ek : (T)0;
               cp0 = fma_(LDS ? tabl[o + 1] : tabg[o + 1], (LDS ? tabl[o + 6] : tabg[o + 6]) * ek, cp0);
             }
           }
@@ -246,12 +246,12 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
           if (k < K) {
             const size_t o = roff + k * kCoefStride;
             bool use = true;
-            if (P.screen) {  // per-primitive screening: the primitive's own radius
+            if constexpr (SCREEN) {  // per-primitive screening: the primitive's own radius
               use = (float)q <= (float)(LDS ? tabl[o + 7] : tabg[o + 7]);
               if (__ballot(use) == 0) continue;
             }
             T ek = exp_scaled(LDS ? tabl[o] : tabg[o], qv);
-            ek = use ? ek : (T)0;
+            if constexpr (SCREEN) ek = use ? ek : (T)0;
             const T gk = (LDS ? tabl[o + 6] : tabg[o + 6]) * ek;
 #pragma unroll
             for (int l = 0; l <= LMAX; ++l) {
@@ -462,19 +462,24 @@ __global__ __launch_bounds__(256) void k_cell_reduce(BatchDev bt, const int64_t 
 
 using PairsFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const int32_t *, const void *, void *, int,
                          int64_t, unsigned long long *, const void *);
-template <int L, bool F64, bool LDS> PairsFn pick_kb(int kb) {
-  if (kb <= 4) return k_bwd_pairs<L, 4, F64, LDS>;
-  if (kb <= 8) return k_bwd_pairs<L, 8, F64, LDS>;
-  return k_bwd_pairs<L, 16, F64, LDS>;
+// SCREEN: per-primitive screening (its own instantiation keeps the branch
+// out of the loop of plans without it)
+template <int L, bool F64, bool LDS, bool SCREEN> PairsFn pick_kb(int kb) {
+  if (kb <= 4) return k_bwd_pairs<L, 4, F64, LDS, SCREEN>;
+  if (kb <= 8) return k_bwd_pairs<L, 8, F64, LDS, SCREEN>;
+  return k_bwd_pairs<L, 16, F64, LDS, SCREEN>;
 }
-template <bool F64, bool LDS> PairsFn pick_pairs(int lmax, int kb) {
+template <bool F64, bool LDS, bool SCREEN> PairsFn pick_l(int lmax, int kb) {
   switch (lmax) {
-    case 0: return pick_kb<0, F64, LDS>(kb);
-    case 1: return pick_kb<1, F64, LDS>(kb);
-    case 2: return pick_kb<2, F64, LDS>(kb);
-    case 3: return pick_kb<3, F64, LDS>(kb);
-    default: return pick_kb<4, F64, LDS>(kb);
+    case 0: return pick_kb<0, F64, LDS, SCREEN>(kb);
+    case 1: return pick_kb<1, F64, LDS, SCREEN>(kb);
+    case 2: return pick_kb<2, F64, LDS, SCREEN>(kb);
+    case 3: return pick_kb<3, F64, LDS, SCREEN>(kb);
+    default: return pick_kb<4, F64, LDS, SCREEN>(kb);
   }
+}
+template <bool F64, bool LDS> PairsFn pick_pairs(int lmax, int kb, bool screen) {
+  return screen ? pick_l<F64, LDS, true>(lmax, kb) : pick_l<F64, LDS, false>(lmax, kb);
 }
 
 }  // namespace
@@ -524,10 +529,11 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   const bool use_lds = tab_bytes <= 48 * 1024;
   const size_t tsm = (use_lds ? tab_bytes : 0) + 4 * (size_t)p->dev.S * coef_block(p->dev.lmax) * (f64 ? 8 : 4);
   const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
-  PairsFn fn = f64 ? (use_lds ? pick_pairs<true, true>(p->dev.lmax, p->dev.kb)
-                              : pick_pairs<true, false>(p->dev.lmax, p->dev.kb))
-                   : (use_lds ? pick_pairs<false, true>(p->dev.lmax, p->dev.kb)
-                              : pick_pairs<false, false>(p->dev.lmax, p->dev.kb));
+  const bool scr = p->dev.screen != 0;
+  PairsFn fn = f64 ? (use_lds ? pick_pairs<true, true>(p->dev.lmax, p->dev.kb, scr)
+                              : pick_pairs<true, false>(p->dev.lmax, p->dev.kb, scr))
+                   : (use_lds ? pick_pairs<false, true>(p->dev.lmax, p->dev.kb, scr)
+                              : pick_pairs<false, false>(p->dev.lmax, p->dev.kb, scr));
   int64_t pb = persistent_blocks((const void *)fn, tsm, p->tuning.blocks_per_cu);
   if (pb > (n_items + 3) / 4) pb = (n_items + 3) / 4;
   if (pb < 1) pb = 1;
