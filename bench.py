@@ -35,6 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed issue)
+# non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz (this build issues no packed FP32)
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0
 # v_exp_f32 is a quarter-rate transcendental: 256 CU x 4 SIMD x 16 lanes / 4 x 2.4 GHz
@@ -529,6 +531,8 @@ def main():
     rec = counter_record("overlap")
     roofline = {"kernel": "overlap", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "peak_nonpacked_fp32": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
+                "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                 "traffic": rec["hbm_bytes_per_launch"] if rec else None,
                 "executed": ({"fp32_tflops": 64 * rec["valu_flops_fp32_per_wave"] / (ov["avg_ms"] * 1e-3) / 1e12,
                               "valu_issue_frac": rec["valu_insts"] / (ov["avg_ms"] * 1e-3) / VALU_WAVE_INSTS_PER_S,
