@@ -118,3 +118,66 @@ def test_autotune_choice_and_cache(g, tmp_path):
     F, _ = g.features(plan2, db, nb, ws)
     Fref = oracle.features_batch(b, probes)
     assert_features(F.cpu().numpy(), Fref, probes.tau, 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_graph_replay_points_occupancy_density(g, precision):
+    """Reference points as centres, occupancies and order -1 in one captured
+    step (no-sync build, forward, adjoint with the by-neighbour sort):
+    every replay bitwise equal to eager launches; moving the points in
+    place is followed."""
+    say(f"[graph replay with points {precision}]")
+    rng = np.random.default_rng(13)
+    b, probes = _batch(11)
+    dis = [gs.disorder(rng, b.structure(s), n_elements=3) for s in range(b.n_structs)]
+    b = gs.make_batch([d[0] for d in dis], occupancy=[d[1] for d in dis])
+    probes = gs.Probes(np.array([-1, 0, 2, 3], np.int32), probes.sigmas, probes.prim_offsets, probes.B,
+                       probes.beta, probes.tau)
+    pts, po = [], [0]
+    for s in range(b.n_structs):
+        pos, _, cell, pbc = b.structure(s)
+        q = rng.uniform(0, 1, (6, 3)) @ cell if pbc else rng.normal(size=(6, 3)) * 2.0
+        pts.append(q)
+        po.append(po[-1] + 6)
+    plan = g.GMPPlan.from_probes(probes, precision)
+    db = g.DeviceBatch.from_batch(b).with_points(np.concatenate(pts), po)
+    ws = g.Workspace()
+    G = torch.as_tensor(rng.standard_normal((db.n_centres, probes.n_features)), device="cuda").to(plan.dtype)
+    nb, F0, mu0, gp0, gc0 = _eager(g, plan, db, ws, G)
+    nbc = g.build_neighbors(plan, db, ws, capacity=2 * nb.n_pairs + 1024)
+    step = g.CapturedStep(plan, db, ws, nbc, backward=True, G=G)
+    for r in range(3):
+        step.replay()
+        torch.cuda.synchronize()
+        assert _same(step.F, F0) and _same(step.mu, mu0), f"replay {r}"
+        assert _same(step.gpos, gp0) and _same(step.gcell, gc0), f"replay {r}"
+    db.pxyz.add_(torch.as_tensor(0.1 * rng.standard_normal(tuple(db.pxyz.shape)), device="cuda"))
+    step.replay()
+    torch.cuda.synchronize()
+    g.check_status(ws)
+    nb1, F1, mu1, gp1, gc1 = _eager(g, plan, db, g.Workspace(), G)
+    assert _same(step.F, F1) and _same(step.gpos, gp1) and _same(step.gcell, gc1)
+    assert not _same(F1, F0)
+
+
+def test_jacobian_after_nosync_rebuild(g):
+    """The Jacobian of lists rebuilt without synchronization (ld = capacity)
+    equals the one of the synchronous build on the written pairs."""
+    b, probes = _batch(17)
+    plan = g.GMPPlan.from_probes(probes, "fp64")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    F, mu = g.features(plan, db, nb, ws)
+    J0 = g.feature_jacobian(plan, db, nb, ws, mu).clone()
+    nbc = g.build_neighbors(plan, db, ws, capacity=nb.n_pairs + 4096)
+    P = nb.n_pairs
+    nbc.n_pairs = 0  # as after a no-sync rebuild: the pair count is not known on the host
+    g.rebuild_neighbors_nosync(plan, db, ws, nbc)
+    g.check_status(ws)
+    F1, mu1 = g.features(plan, db, nbc, ws)
+    out = torch.full((plan.n_features, 3, nbc.capacity), float("nan"), dtype=torch.float64, device="cuda")
+    g.feature_jacobian(plan, db, nbc, ws, mu1, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out[:, :, :P].permute(2, 0, 1), J0)
+    assert bool(torch.isnan(out[:, :, P:]).all())  # entries past the lists are not written
