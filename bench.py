@@ -427,8 +427,9 @@ def algorithmic_counts(nb, probes, rc2):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is described "
-                                   "in DESIGN.md and not executed", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: sharding (structures of a batch across "
+                                   "GPUs with no exchange; a large system by centres with one reduction of the "
+                                   "position gradients) is not executed", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     import gmp_synth as gs
