@@ -109,3 +109,22 @@ def test_paper_feature_enumeration():
     got = feature_labels(fx["orders"], fx["sigmas"])
     want = [tuple(x) for x in fx["features"]]
     assert [(a, (0 if a == -1 else b)) for a, b in got] == [(a, (0 if a == -1 else b)) for a, b in want]
+
+
+def test_screening_flag_validation(lib):
+    d, keep = _desc(_probes())
+    rc2 = np.zeros(4)
+    for flag, code in ((0, 0), (1, 0), (2, 1), (-1, 1)):
+        d.screening = flag
+        assert lib.gmp_probe_cutoffs(ctypes.byref(d), rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == code
+
+
+def test_density_cutoff_slot_bit_exact(lib):
+    """With order -1 the library's last cutoff slot is the density radius,
+    bit-equal to the oracle's."""
+    p = _probes(orders=np.array([2, -1, 0], np.int32))
+    d, keep = _desc(p)
+    rc2 = np.zeros(3)
+    assert lib.gmp_probe_cutoffs(ctypes.byref(d), rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+    assert rc2.tobytes() == oracle.cutoffs(p).tobytes()
+    assert rc2[2] == oracle.density_cutoff(p)
