@@ -101,6 +101,38 @@ def test_nosync_overflow_is_reported(g):
     assert torch.isfinite(gp).all() and torch.isfinite(gc).all()
 
 
+def test_nosync_overflow_with_points(g):
+    """Reference points whose lists overflow a no-sync rebuild: reported by
+    the status word; points whose list fits are exact, the others zero, and
+    the backward (by-neighbour sort included) stays finite."""
+    say("[no-sync capacity overflow, reference points]")
+    b, p = gs.config("C1")
+    cell = b.cell[0]
+    pts = np.random.default_rng(5).uniform(0, 1, (40, 3)) @ cell
+    plan = g.GMPPlan.from_probes(p, "fp32c")
+    db = g.DeviceBatch.from_batch(b).with_points(pts, [0, len(pts)])
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    small = g.Neighbors(plan, db, nb.n_pairs // 2)
+    small.max_list = nb.max_list
+    g.rebuild_neighbors_nosync(plan, db, ws, small)
+    small.n_pairs = small.capacity
+    F, mu = g.features(plan, db, small, ws)
+    gp, gc = g.features_backward(plan, db, small, ws, mu, F, torch.ones_like(F))
+    J = g.feature_jacobian(plan, db, small, ws, mu)
+    torch.cuda.synchronize()
+    with pytest.raises(g.GMPError, match="CAPACITY"):
+        g.check_status(ws)
+    Fref, _ = g.features(plan, db, nb, ws)
+    offs = small.offsets.cpu().numpy()
+    fits = offs[1:] <= small.capacity
+    assert fits.any() and not fits.all()
+    Fh, Fr = F.cpu().numpy(), Fref.cpu().numpy()
+    assert np.array_equal(Fh[fits], Fr[fits])
+    assert np.all(Fh[~fits] == 0.0)
+    assert torch.isfinite(gp).all() and torch.isfinite(gc).all() and J.shape[0] == small.capacity
+
+
 def test_two_call_capacity_pattern(g):
     say("[two-call capacity]")
     b, p = gs.config("C1")
