@@ -121,7 +121,34 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
         T cl[LMAX + 1], cp[LMAX + 1];
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) { cl[l] = (T)0; cp[l] = (T)0; }
-        if (inside) {
+        bool radial_done = false;
+        if constexpr (!F64) {
+          if (inside && !P.screen) {
+            // as in the adjoint kernel: zero rows past an element's own count,
+            // the plan's largest count for every lane, row k+1 read ahead
+            const float *row = (LDS ? tabl : tabg) + roff;
+            const int kmx = P.kmax;
+            float4 ra = *(const float4 *)row, rb4 = *(const float4 *)(row + 4);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+              if (k >= kmx) break;
+              float4 na, nb4;
+              if (k + 1 < KB) { na = *(const float4 *)(row + (k + 1) * kCoefStride); nb4 = *(const float4 *)(row + (k + 1) * kCoefStride + 4); }
+              asm volatile("" ::: "memory");
+              const T ek = exp_scaled(ra.x, qv);
+              const T gk = rb4.z * ek;
+              const T av[5] = {ra.y, ra.z, ra.w, rb4.x, rb4.y};
+#pragma unroll
+              for (int l = 0; l <= LMAX; ++l) {
+                cl[l] = fma_(av[l], ek, cl[l]);
+                cp[l] = fma_(av[l], gk, cp[l]);
+              }
+              if (k + 1 < KB) { ra = na; rb4 = nb4; }
+            }
+            radial_done = true;
+          }
+        }
+        if (inside && !radial_done) {
 #pragma unroll
           for (int k = 0; k < KB; ++k) {
             if (k < K) {

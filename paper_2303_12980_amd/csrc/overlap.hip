@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
   using TR = typename std::conditional<F64, double, float>::type;                 // radial arithmetic
   using TM = typename std::conditional<MODE == ACC_TWOSUM, float, double>::type;  // monomials
   constexpr int NM = nmono(LMAX);
-  extern __shared__ double lds_dyn[];
+  extern __shared__ __align__(16) double lds_dyn[];
   __shared__ double lds_red[4][64 * 9];
   __shared__ int lds_k[kMaxElements];
   const int S = P.S, E = P.E;
@@ -296,6 +296,29 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         TR cl[LMAX + 1];
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) cl[l] = (TR)0;
+        if constexpr (!SCREEN && !F64) {
+          // FP32 table rows past an element's own primitive count are zero
+          // (they add exact zeros), so every lane runs the plan's largest
+          // count with wavefront-uniform control flow, and the LDS read of
+          // row k+1 is issued before row k is used (the empty asm statement
+          // keeps the compiler from sinking it)
+          const TR *row = (LDS ? tabl : tabg) + roff;
+          const int kmx = P.kmax;
+          float4 ra = *(const float4 *)row;
+          float2 rb2 = *(const float2 *)(row + 4);
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            if (k >= kmx) break;
+            float4 na; float2 nb2;
+            if (k + 1 < KB) { na = *(const float4 *)(row + (k + 1) * kCoefStride); nb2 = *(const float2 *)(row + (k + 1) * kCoefStride + 4); }
+            asm volatile("" ::: "memory");
+            const TR ek = exp_scaled(ra.x, qv);
+            const TR av[5] = {ra.y, ra.z, ra.w, rb2.x, rb2.y};
+#pragma unroll
+            for (int l = 0; l <= LMAX; ++l) cl[l] = fma_(av[l], ek, cl[l]);
+            if (k + 1 < KB) { ra = na; rb2 = nb2; }
+          }
+        } else {
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
           if (k < K) {
@@ -310,6 +333,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
 #pragma unroll
             for (int l = 0; l <= LMAX; ++l) cl[l] = fma_(LDS ? tabl[o + 1 + l] : tabg[o + 1 + l], ek, cl[l]);
           }
+        }
         }
         TM mono[NM];
         {
