@@ -128,6 +128,8 @@ WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t M, int64_t c
   L.vbuf = c.take<char>((size_t)capacity * 4 * tsz);
   L.pair_key = c.take<uint64_t>(M > 0 ? 0 : (size_t)capacity);
   L.pair_centre = c.take<int32_t>(M > 0 ? 0 : (size_t)capacity);
+  L.pair_sum = c.take<uint64_t>(M > 0 ? 0 : (size_t)(capacity / 16 + 1));
+  L.abs_bstart = c.take<int64_t>(M > 0 ? 0 : (size_t)N * (p->dev.E * p->dev.S + 1));
   L.cellpart = c.take<double>((size_t)NC * 9);
   const size_t trn = M > 0 ? (size_t)capacity : 0;
   L.tr_key_in = c.take<uint32_t>(trn);

@@ -428,7 +428,8 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
                                               const double *sx, const double *sy, const double *sz,
                                               const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
                                               const int32_t *cnt, int lds_keys, uint64_t *pair_key,
-                                              int32_t *pair_centre, uint32_t *status) {
+                                              int32_t *pair_centre, uint64_t *pair_sum, int64_t *abs_bstart,
+                                              uint32_t *status) {
   extern __shared__ uint64_t lds_u64[];
   __shared__ CandLds lds_cand[4];
   const int nbk = P.E * P.S;
@@ -467,7 +468,10 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
     }
   }
   __syncthreads();
-  for (int b = tid; b <= nbk; b += blockDim.x) nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
+  for (int b = tid; b <= nbk; b += blockDim.x) {
+    nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
+    if (pair_key) abs_bstart[i * (nbk + 1) + b] = base + bstart[b];
+  }
   for (int s = tid; s < P.S; s += blockDim.x) nb.sigma_end[i * P.S + s] = bstart[(P.rank_lt[s] + 1) * P.E];
   if (overflow) return;  // consumers skip centres whose list ends past the capacity
   if (too_big) {
@@ -481,7 +485,9 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       nb.j[base + t] = (int32_t)jp;
       nb.shift[base + t] = (int32_t)((uint32_t)ei << 24);
       if (pair_key) {
-        pair_key[base + t] = make_key(i, 0, 0, 0);
+        const uint64_t k = make_key(i, 0, 0, 0);
+        pair_key[base + t] = k;
+        if (((base + t) & 15) == 0) pair_sum[(base + t) >> 4] = k;
         pair_centre[base + t] = (int32_t)i;
         nb.reverse[base + t] = -1;
       }
@@ -523,9 +529,11 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       nb.j[base + b0 + t] = jj;
       nb.shift[base + b0 + t] = (int32_t)(n1 | (n2 << 8) | (n3 << 16) | ((uint32_t)e << 24));
       if (pair_key) {  // inputs of the reverse-index kernel; the index starts unresolved
-        pair_key[base + b0 + t] = k;
-        pair_centre[base + b0 + t] = (int32_t)i;
-        nb.reverse[base + b0 + t] = -1;
+        const int64_t gp = base + b0 + t;
+        pair_key[gp] = k;
+        if ((gp & 15) == 0) pair_sum[gp >> 4] = k;
+        pair_centre[gp] = (int32_t)i;
+        nb.reverse[gp] = -1;
       }
     }
   }
@@ -533,11 +541,15 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
 
 // Reverse index: pair (i, j, n) and its mirror (j, i, -n).  One thread per
 // pair; only the owner of each mirror couple -- i < j, or i == j with n >= 0
-// lexicographically -- searches its mirror (binary search over the packed
-// keys of j's bucket (shell, species of i); the mirror has the same q, so
-// the shell stored in the pair's key) and writes both entries.
+// lexicographically -- searches its mirror among the packed keys of j's
+// bucket (shell, species of i; the mirror has the same q, so the shell
+// stored in the pair's key) and writes both entries.  The search is bound by
+// the cache lines it fetches from lists that do not fit in L2, so it runs on
+// two levels: the fill also stores every 16th key (a 16-key window is one
+// 128-byte line) and the bucket starts as global indices.
 __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev nb, const uint64_t *pair_key,
-                                                 const int32_t *pair_centre, int64_t n_pairs, uint32_t *status) {
+                                                 const int32_t *pair_centre, const uint64_t *pair_sum,
+                                                 const int64_t *abs_bstart, int64_t n_pairs, uint32_t *status) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = bt.n_atoms;
   const int64_t total = nb.offsets[N];
@@ -557,14 +569,27 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
   int ei = bt.species[i];
   ei = ei < 0 ? 0 : (ei >= P.E ? P.E - 1 : ei);
   const int b = h * P.E + ei;  // the mirror has the same q, hence the same shell
-  const int32_t *bs = nb.bucket_start + (int64_t)j * (nbk + 1);
-  int lo = bs[b], hi = bs[b + 1];
+  const int64_t *ab = abs_bstart + (int64_t)j * (nbk + 1);
+  const int64_t A = ab[b], Z = ab[b + 1];  // the bucket as global pair indices
   const uint64_t key = make_key(i, -n1, -n2, -n3, h);
   const int64_t jb = nb.offsets[j];
-  int found = -1;
+  // two levels: the every-16th keys that fall inside the bucket (one or two
+  // cache lines) select a 16-key window (one line), searched in turn
+  int64_t lo = A, hi = Z;
+  if (Z - A > 16) {
+    const int64_t sA = (A + 15) >> 4, sB = (Z - 1) >> 4;
+    int64_t a = sA, c = sB + 1;  // first sampled key above the key sought
+    while (a < c) {
+      const int64_t m = (a + c) >> 1;
+      if (pair_sum[m] <= key) a = m + 1; else c = m;
+    }
+    lo = a == sA ? A : (a - 1) * 16;
+    hi = a * 16 < Z ? a * 16 : Z;
+  }
+  int64_t found = -1;
   while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    const uint64_t km = pair_key[jb + mid];
+    const int64_t mid = (lo + hi) >> 1;
+    const uint64_t km = pair_key[mid];
     if (km == key) { found = mid; break; }
     if (km < key) lo = mid + 1; else hi = mid;
   }
@@ -572,8 +597,8 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
     atomicOr(status, ST_INTERNAL);
     return;
   }
-  nb.reverse[p] = found;
-  nb.reverse[jb + found] = (int32_t)(p - nb.offsets[i]);
+  nb.reverse[p] = (int32_t)(found - jb);
+  nb.reverse[found] = (int32_t)(p - nb.offsets[i]);
 }
 
 }  // namespace
@@ -615,7 +640,8 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
   if (n_centres(bt) == 0) return;
   GMP_LAUNCH("nbr_fill_sort", k_fill, dim3((unsigned)n_centres(bt)), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
              L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, lds_keys,
-             (nb.reverse && !point_mode(bt)) ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.status);
+             (nb.reverse && !point_mode(bt)) ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.pair_sum,
+             L.abs_bstart, L.status);
 }
 
 void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,
@@ -624,7 +650,7 @@ void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, con
   const int64_t blocks = (n_pairs + 255) / 256;
   if (blocks > 0)
     GMP_LAUNCH("nbr_reverse", k_reverse, dim3((unsigned)blocks), dim3(256), 0, s, p->dev, bt, nb, L.pair_key,
-               L.pair_centre, n_pairs, L.status);
+               L.pair_centre, L.pair_sum, L.abs_bstart, n_pairs, L.status);
 }
 
 }  // namespace gmp
