@@ -330,7 +330,9 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BatchDev bt, NbrDev nb, cons
   using T = typename Real<F64>::T;
   const T *vbuf = (const T *)vbuf_;
   const int lane = lane_id();
-  const int64_t a = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  // each XCD takes one contiguous range of atoms: their mirror reads fall in
+  // the same stretch of every partner bucket (sorted by atom), so in shared lines
+  const int64_t a = xcd_contiguous(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int64_t N = bt.n_atoms;
   if (a >= N) return;
   const int64_t base = nb.offsets[a];
@@ -386,7 +388,8 @@ __global__ __launch_bounds__(256) void k_bwd_gather_atoms(BatchDev bt, const voi
   using T = typename Real<F64>::T;
   const T *vbuf = (const T *)vbuf_;
   const int lane = lane_id();
-  const int64_t a = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  // one contiguous range of atoms per XCD, as in the atoms-only gather
+  const int64_t a = xcd_contiguous(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int64_t N = bt.n_atoms, NT = n_total(bt);
   if (a >= N) return;
   double g[3] = {0.0, 0.0, 0.0};

@@ -148,6 +148,13 @@ struct NbrDev {
 };
 
 // ---------------------------------------------------------------- device helpers
+// Workgroup index -> position in a sequence, such that the workgroups the
+// dispatcher places on one XCD (every eighth) take one contiguous range.
+__device__ inline int64_t xcd_contiguous(int64_t b, int64_t nblk) {
+  const int64_t x = b & 7, per = nblk >> 3, rem = nblk & 7;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
 // LDS writes of one wavefront become visible to its other lanes.

@@ -312,13 +312,6 @@ __device__ inline int shell_of(const PlanDev &P, double q) {
   return sh;
 }
 
-// Workgroup index -> position in a sequence, such that the workgroups the
-// dispatcher places on one XCD (every eighth) take one contiguous range.
-__device__ inline int64_t xcd_contiguous(int64_t b, int64_t nblk) {
-  const int64_t x = b & 7, per = nblk >> 3, rem = nblk & 7;
-  return x * per + (x < rem ? x : rem) + (b >> 3);
-}
-
 // One workgroup per centre (centres in cell-list order): count neighbours
 // per (shell, species) bucket; the wavefronts share the centre's candidates.
 __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
