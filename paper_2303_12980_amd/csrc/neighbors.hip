@@ -383,21 +383,23 @@ __device__ void wave_sort(uint64_t *a, int n) {
     wave_lds_sync();
     return;
   }
-  int p2 = 1;
-  while (p2 < n) p2 <<= 1;
-  const int half = p2 >> 1;
-  for (int k = 2; k <= p2; k <<= 1) {
-    const int hk = k >> 1;
+  int lp2 = 1;
+  while ((1 << lp2) < n) ++lp2;
+  const int half = 1 << (lp2 - 1);
+  // block sizes are powers of two: block and offset by shift and mask
+  for (int lk = 1; lk <= lp2; ++lk) {
+    const int k = 1 << lk, lh = lk - 1;
     for (int t = lane; t < half; t += kWave) {
-      int blk = t / hk, off = t - blk * hk;
-      int i = blk * k + off, l = blk * k + k - 1 - off;
+      const int blk = t >> lh, off = t & ((1 << lh) - 1);
+      const int i = (blk << lk) + off, l = (blk << lk) + k - 1 - off;
       if (l < n) cmpswap(a, i, l);
     }
     wave_lds_sync();
-    for (int j = k >> 2; j >= 1; j >>= 1) {
+    for (int lj = lk - 2; lj >= 0; --lj) {
+      const int j = 1 << lj;
       for (int t = lane; t < half; t += kWave) {
-        int blk = t / j, off = t - blk * j;
-        int i = blk * 2 * j + off, l = i + j;
+        const int blk = t >> lj, off = t & (j - 1);
+        const int i = (blk << (lj + 1)) + off, l = i + j;
         if (l < n) cmpswap(a, i, l);
       }
       wave_lds_sync();
