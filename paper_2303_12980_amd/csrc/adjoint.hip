@@ -38,7 +38,7 @@ __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c
 
 // One wavefront per index: centres get their coefficients, every index
 // (atoms, and reference points) its structure and packed position.
-template <bool F64>
+template <int LMAX, bool F64>
 __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev nb, const double *components,
                                                   const void *grad_features, void *bcoef, double4 *rw4,
                                                   int32_t *astruct, unsigned long long *counter) {
@@ -47,8 +47,11 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   extern __shared__ double lds_b[];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
-  const int S = P.S, NM = nmono(P.lmax), NM1 = nmono(P.lmax - 1), NB = coef_block(P.lmax);
-  const int NMP = coef_m(P.lmax), NDP = coef_d(P.lmax);
+  // block sizes are compile-time constants (the index splits below are then
+  // multiplications, not integer divisions)
+  constexpr int NM = nmono(LMAX), NM1 = nmono(LMAX - 1), NB = coef_block(LMAX);
+  constexpr int NMP = coef_m(LMAX), NDP = coef_d(LMAX);
+  const int S = P.S;
   double *scale = lds_b + (size_t)w * (P.nf + S * NM);  // [nf]
   double *M = scale + P.nf;                               // [S][NM]
   const bool live = i < N;
@@ -247,9 +250,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
           const T *row = (LDS ? tabl : tabg) + roff;
           const int kmx = P.kmax;
           float4 ra = *(const float4 *)row, rb4 = *(const float4 *)(row + 4);
-#pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            if (k >= kmx) break;
+          auto row_step = [&](int k) {
             float4 na, nb4;
             if (k + 1 < KB) { na = *(const float4 *)(row + (k + 1) * kCoefStride); nb4 = *(const float4 *)(row + (k + 1) * kCoefStride + 4); }
             asm volatile("" ::: "memory");
@@ -262,6 +263,17 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
               cp[l] = fma_(av[l], gk, cp[l]);
             }
             if (k + 1 < KB) { ra = na; rb4 = nb4; }
+          };
+          if constexpr (KB <= 8) {  // full unroll with an early exit (trip count bound <= 8)
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+              if (k >= kmx) break;
+              row_step(k);
+            }
+          } else {  // 16-row tables: a wavefront-uniform guard keeps the trip count constant
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+              if (k < kmx) row_step(k);
           }
         } else
 #pragma unroll
@@ -528,12 +540,14 @@ void launch_bwd_coef(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   const int64_t blocks_all = (n_total(bt) + 3) / 4;
   if (blocks_all == 0) return;
   size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
-  if (p->prec == GMP_FP64)
-    GMP_LAUNCH("adj_coef", k_bwd_coef<true>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
-               components, grad_features, L.bcoef, L.rw4, L.astruct, L.counter);
-  else
-    GMP_LAUNCH("adj_coef", k_bwd_coef<false>, dim3((unsigned)blocks_all), dim3(256), smem, s, p->dev, bt, nb,
-               components, grad_features, L.bcoef, L.rw4, L.astruct, L.counter);
+  using CoefFn = void (*)(PlanDev, BatchDev, NbrDev, const double *, const void *, void *, double4 *, int32_t *,
+                          unsigned long long *);
+  static const CoefFn fns[2][kMaxL + 1] = {
+      {k_bwd_coef<0, false>, k_bwd_coef<1, false>, k_bwd_coef<2, false>, k_bwd_coef<3, false>, k_bwd_coef<4, false>},
+      {k_bwd_coef<0, true>, k_bwd_coef<1, true>, k_bwd_coef<2, true>, k_bwd_coef<3, true>, k_bwd_coef<4, true>}};
+  const int lm = p->dev.lmax < 0 ? 0 : (p->dev.lmax > kMaxL ? kMaxL : p->dev.lmax);
+  GMP_LAUNCH("adj_coef", fns[p->prec == GMP_FP64 ? 1 : 0][lm], dim3((unsigned)blocks_all), dim3(256), smem, s,
+             p->dev, bt, nb, components, grad_features, L.bcoef, L.rw4, L.astruct, L.counter);
 }
 
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,

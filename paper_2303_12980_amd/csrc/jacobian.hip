@@ -129,9 +129,7 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
             const float *row = (LDS ? tabl : tabg) + roff;
             const int kmx = P.kmax;
             float4 ra = *(const float4 *)row, rb4 = *(const float4 *)(row + 4);
-#pragma unroll
-            for (int k = 0; k < KB; ++k) {
-              if (k >= kmx) break;
+            auto row_step = [&](int k) {
               float4 na, nb4;
               if (k + 1 < KB) { na = *(const float4 *)(row + (k + 1) * kCoefStride); nb4 = *(const float4 *)(row + (k + 1) * kCoefStride + 4); }
               asm volatile("" ::: "memory");
@@ -144,6 +142,17 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
                 cp[l] = fma_(av[l], gk, cp[l]);
               }
               if (k + 1 < KB) { ra = na; rb4 = nb4; }
+            };
+            if constexpr (KB <= 8) {  // full unroll with an early exit (trip count bound <= 8)
+#pragma unroll
+              for (int k = 0; k < KB; ++k) {
+                if (k >= kmx) break;
+                row_step(k);
+              }
+            } else {  // 16-row tables: a wavefront-uniform guard keeps the trip count constant
+#pragma unroll
+              for (int k = 0; k < KB; ++k)
+                if (k < kmx) row_step(k);
             }
             radial_done = true;
           }

@@ -306,9 +306,7 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
           const int kmx = P.kmax;
           float4 ra = *(const float4 *)row;
           float2 rb2 = *(const float2 *)(row + 4);
-#pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            if (k >= kmx) break;
+          auto row_step = [&](int k) {
             float4 na; float2 nb2;
             if (k + 1 < KB) { na = *(const float4 *)(row + (k + 1) * kCoefStride); nb2 = *(const float2 *)(row + (k + 1) * kCoefStride + 4); }
             asm volatile("" ::: "memory");
@@ -317,6 +315,17 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
 #pragma unroll
             for (int l = 0; l <= LMAX; ++l) cl[l] = fma_(av[l], ek, cl[l]);
             if (k + 1 < KB) { ra = na; rb2 = nb2; }
+          };
+          if constexpr (KB <= 8) {  // full unroll with an early exit (trip count bound <= 8)
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+              if (k >= kmx) break;
+              row_step(k);
+            }
+          } else {  // 16-row tables: a wavefront-uniform guard keeps the trip count constant
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+              if (k < kmx) row_step(k);
           }
         } else {
 #pragma unroll
