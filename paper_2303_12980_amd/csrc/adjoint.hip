@@ -4,8 +4,8 @@
 //
 //   W_{i,l,s,abc} = G_{i,l,s} w_abc mu_abc / F_{i,l,s}   (0 when F = 0)
 //   For centre i and sigma s the polynomial Q_{i,s,l}(d) = sum_abc W P_abc(d)
-//   is stored in monomial form (coefficients M) together with the monomial
-//   coefficients of its gradient (Dx, Dy, Dz), so per pair
+//   is stored in monomial form (coefficients M); the pair kernel evaluates
+//   it and its gradient (the exponents are constants) from M, so per pair
 //   v_{ijn} = grad_d sum_{s,l} c_{l,s}(q) Q_{i,s,l}(d)
 //          = sum_{s,l} [ 2 c'_{l,s}(q) Q_{i,s,l}(d) d + c_{l,s}(q) grad Q_{i,s,l}(d) ].
 //   dL/dR_j += v, dL/dR_i -= v, dL/da_m += (n_m - m_{j,m} + m_{i,m}) v,
@@ -49,8 +49,7 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
   // block sizes are compile-time constants (the index splits below are then
   // multiplications, not integer divisions)
-  constexpr int NM = nmono(LMAX), NM1 = nmono(LMAX - 1), NB = coef_block(LMAX);
-  constexpr int NMP = coef_m(LMAX), NDP = coef_d(LMAX);
+  constexpr int NM = nmono(LMAX), NB = coef_block(LMAX);
   const int S = P.S;
   double *scale = lds_b + (size_t)w * (P.nf + S * NM);  // [nf]
   double *M = scale + P.nf;                               // [S][NM]
@@ -111,17 +110,7 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
     T *out = (T *)bcoef + (size_t)i * S * NB;
     for (int t = lane; t < S * NB; t += kWave) {
       const int s = t / NB, r = t - s * NB;
-      double v = 0.0;
-      if (r < NMP) {
-        if (r < NM) v = M[s * NM + r];
-      } else if (NDP > 0 && (r - NMP) % NDP < NM1) {
-        const int ax = (r - NMP) / NDP, m1 = (r - NMP) - ax * NDP;  // derivative axis and lower monomial
-        const int d1 = kMT.deg[m1];
-        int a = kMT.ea[m1], b = kMT.eb[m1], c = kMT.ec[m1];
-        double f;
-        if (ax == 0) { f = a + 1; ++a; } else if (ax == 1) { f = b + 1; ++b; } else { f = c + 1; ++c; }
-        v = f * M[s * NM + doff(d1 + 1) + midx(d1 + 1, a, b)];
-      }
+      const double v = r < NM ? M[s * NM + r] : 0.0;
       out[t] = (T)v;
     }
   }
@@ -131,8 +120,8 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
 // items.  Lanes take consecutive pairs of the centre's list; a pair is used
 // by every sigma whose prefix contains it.  Radial coefficients come from
 // the LDS copy of the plan table (row of the lane's neighbour species); the
-// centre's polynomial coefficients M, Dx, Dy, Dz are staged in LDS per item
-// and read wavefront-uniformly.  The loads of pair data (j, shift) run two
+// centre's polynomial coefficients M are staged in LDS per item and read
+// wavefront-uniformly (the gradient reuses them: one LDS value per monomial).  The loads of pair data (j, shift) run two
 // steps ahead and the gathers of the neighbours' wrapped positions one step
 // ahead.  Dynamic LDS: [coefficient table if staged][4 wavefronts][S * NB].
 template <int LMAX, int KB, bool F64, bool LDS, bool SCREEN>
@@ -142,7 +131,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
                                                    unsigned long long *counter, const void *tab_global) {
   using T = typename Real<F64>::T;
   constexpr int NM = nmono(LMAX);
-  constexpr int NMP = coef_m(LMAX), NDP = coef_d(LMAX), NB = coef_block(LMAX);
+  constexpr int NB = coef_block(LMAX);
   extern __shared__ __align__(16) double lds_dyn[];
   __shared__ int lds_k[kMaxElements];
   const int S = P.S, E = P.E;
@@ -300,19 +289,21 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) {
           if (!((mask >> l) & 1)) continue;
-          T Q = (T)0;
+          // P(d) = sum_m M_m d^m and its gradient from the same coefficients:
+          // d/dx of x^a y^b z^c is a x^(a-1) y^b z^c (exponents are constants)
+          T Q = (T)0, gx = (T)0, gy = (T)0, gz = (T)0;
 #pragma unroll
-          for (int mm = 0; mm < ncomp(l); ++mm) Q = fma_(bc[doff(l) + mm], mono[doff(l) + mm], Q);
+          for (int mm = 0; mm < ncomp(l); ++mm) {
+            const int m = doff(l) + mm;
+            const T Mv = bc[m];
+            Q = fma_(Mv, mono[m], Q);
+            const int a = kMT.ea[m], b = kMT.eb[m], c = kMT.ec[m];
+            if (a >= 1) gx = fma_(a == 1 ? Mv : (T)a * Mv, mono[doff(l - 1) + midx(l - 1, a - 1, b)], gx);
+            if (b >= 1) gy = fma_(b == 1 ? Mv : (T)b * Mv, mono[doff(l - 1) + midx(l - 1, a, b - 1)], gy);
+            if (c >= 1) gz = fma_(c == 1 ? Mv : (T)c * Mv, mono[doff(l - 1) + midx(l - 1, a, b)], gz);
+          }
           A = fma_(cp[l], Q, A);
           if (l >= 1) {
-            T gx = (T)0, gy = (T)0, gz = (T)0;
-#pragma unroll
-            for (int mm = 0; mm < ncomp(l - 1); ++mm) {
-              const T mv = mono[doff(l - 1) + mm];
-              gx = fma_(bc[NMP + doff(l - 1) + mm], mv, gx);
-              gy = fma_(bc[NMP + NDP + doff(l - 1) + mm], mv, gy);
-              gz = fma_(bc[NMP + 2 * NDP + doff(l - 1) + mm], mv, gz);
-            }
             Bx = fma_(cl[l], gx, Bx);
             By = fma_(cl[l], gy, By);
             Bz = fma_(cl[l], gz, Bz);

@@ -70,13 +70,14 @@ __host__ __device__ constexpr MonoTable make_mono_table() {
   return t;
 }
 
-// Adjoint coefficient block per (centre, slot): M [nmono(L)], then Dx, Dy,
-// Dz [nmono(L-1)] each; every part starts on a multiple of 4 entries so the
-// pair kernels' wavefront-uniform LDS reads can be 16-byte vector reads.
+// Adjoint coefficient block per (centre, slot): the monomial coefficients M
+// [nmono(L)] of the upstream-weighted polynomial, padded to a multiple of 4
+// entries so the pair kernels' wavefront-uniform LDS reads can be 16-byte
+// vector reads.  The pair kernels take the gradient of the polynomial from
+// the same coefficients (exponents are compile-time constants).
 __host__ __device__ constexpr int round4(int n) { return (n + 3) & ~3; }
 __host__ __device__ constexpr int coef_m(int lmax) { return round4(nmono(lmax)); }
-__host__ __device__ constexpr int coef_d(int lmax) { return round4(nmono(lmax - 1)); }
-__host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax) + 3 * coef_d(lmax); }
+__host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax); }
 
 struct StructInfo {
   double b[9];        // reciprocal rows

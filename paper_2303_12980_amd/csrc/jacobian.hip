@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
                                                    const void *tab_global) {
   using T = typename std::conditional<F64, double, float>::type;
   constexpr int NM = nmono(LMAX);
-  constexpr int NMP = coef_m(LMAX), NDP = coef_d(LMAX), NB = coef_block(LMAX);
+  constexpr int NB = coef_block(LMAX);
   extern __shared__ __align__(16) double lds_dyn[];
   __shared__ int lds_k[kMaxElements];
   const int S = P.S, E = P.E;
@@ -177,18 +177,18 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) {
           if (!((mask >> l) & 1)) continue;
-          T Q = (T)0;
+          // the polynomial and its gradient from the same coefficients, as in
+          // the adjoint pair kernel
+          T Q = (T)0, gx = (T)0, gy = (T)0, gz = (T)0;
 #pragma unroll
-          for (int mm = 0; mm < ncomp(l); ++mm) Q = fma_(bc[doff(l) + mm], mono[doff(l) + mm], Q);
-          T gx = (T)0, gy = (T)0, gz = (T)0;
-          if (l >= 1) {
-#pragma unroll
-            for (int mm = 0; mm < ncomp(l - 1); ++mm) {
-              const T mv = mono[doff(l - 1) + mm];
-              gx = fma_(bc[NMP + doff(l - 1) + mm], mv, gx);
-              gy = fma_(bc[NMP + NDP + doff(l - 1) + mm], mv, gy);
-              gz = fma_(bc[NMP + 2 * NDP + doff(l - 1) + mm], mv, gz);
-            }
+          for (int mm = 0; mm < ncomp(l); ++mm) {
+            const int m = doff(l) + mm;
+            const T Mv = bc[m];
+            Q = fma_(Mv, mono[m], Q);
+            const int a = kMT.ea[m], b = kMT.eb[m], c = kMT.ec[m];
+            if (a >= 1) gx = fma_(a == 1 ? Mv : (T)a * Mv, mono[doff(l - 1) + midx(l - 1, a - 1, b)], gx);
+            if (b >= 1) gy = fma_(b == 1 ? Mv : (T)b * Mv, mono[doff(l - 1) + midx(l - 1, a, b - 1)], gy);
+            if (c >= 1) gz = fma_(c == 1 ? Mv : (T)c * Mv, mono[doff(l - 1) + midx(l - 1, a, b)], gz);
           }
           const T A2 = (T)2 * cp[l] * Q;
           const int64_t f = P.feat_off[P.order_idx[l]] + s;
