@@ -467,26 +467,27 @@ __global__ __launch_bounds__(256) void k_bwd_point_centres(BatchDev bt, NbrDev n
   }
 }
 
-// One wavefront per structure: fixed-order sum of the per-centre cell
-// partials (centres of structure s: [offs[s], offs[s+1])).
+// One workgroup (four wavefronts) per structure: fixed-order sum of the
+// per-centre cell partials (centres of structure s: [offs[s], offs[s+1])),
+// strided over the 256 threads, then over the four wavefronts.
 __global__ __launch_bounds__(256) void k_cell_reduce(BatchDev bt, const int64_t *offs, const double *cellpart,
                                                      double *grad_cell) {
-  const int lane = lane_id();
-  const int64_t s = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (s >= bt.n_structs) return;
+  __shared__ double part[4][9];
+  const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+  const int64_t s = blockIdx.x;
+  if (s >= bt.n_structs) return;  // uniform over the workgroup
   const int64_t a0 = offs[s], a1 = offs[s + 1];
   double cp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t a = a0 + lane; a < a1; a += kWave)
+  for (int64_t a = a0 + tid; a < a1; a += blockDim.x)
 #pragma unroll
     for (int k = 0; k < 9; ++k) cp[k] += cellpart[(size_t)a * 9 + k];
 #pragma unroll
   for (int k = 0; k < 9; ++k) cp[k] = wave_sum(cp[k]);
-  if (lane < 9) {
-    double v = cp[0];
+  if (lane == 0)
 #pragma unroll
-    for (int k = 1; k < 9; ++k) v = lane == k ? cp[k] : v;
-    grad_cell[s * 9 + lane] = v;
-  }
+    for (int k = 0; k < 9; ++k) part[w][k] = cp[k];
+  __syncthreads();
+  if (tid < 9) grad_cell[s * 9 + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
 }
 
 using PairsFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const int32_t *, const void *, void *, int,
@@ -598,9 +599,8 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
       GMP_LAUNCH("adj_points", k_bwd_point_centres<false>, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, vbuf,
                  grad_pos, cellpart);
   }
-  if (grad_cell) {
-    const int64_t sb = (bt.n_structs + 3) / 4;
-    GMP_LAUNCH("adj_cell", k_cell_reduce, dim3((unsigned)sb), dim3(256), 0, s, bt,
+  if (grad_cell && bt.n_structs > 0) {
+    GMP_LAUNCH("adj_cell", k_cell_reduce, dim3((unsigned)bt.n_structs), dim3(256), 0, s, bt,
                point_mode(bt) ? bt.point_offsets : bt.atom_offsets, cellpart, grad_cell);
   }
 }

@@ -380,13 +380,14 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
 // components with the exact integer matrices, then the weighted norm
 // F_{l,s} = sqrt(sum_abc l!/(a!b!c!) mu_abc^2).  Order -1 takes the degree-0
 // moment of the density slot as its component rho and |rho| as its feature.
-template <bool F64OUT>
+template <int LMAX, bool F64OUT>
 __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const double *partial,
                                                 const int64_t *chunk_off, void *features, double *components) {
   extern __shared__ double lds_f[];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
-  const int S = P.S, NM = nmono(P.lmax);
+  constexpr int NM = nmono(LMAX);  // compile-time: the index splits below are not divisions
+  const int S = P.S;
   double *mom = lds_f + (size_t)w * (S * NM + P.ncomp_total);
   double *mu = mom + S * NM;
   const bool live = i < N;
@@ -548,12 +549,13 @@ void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const in
   const int NM = nmono(p->dev.lmax);
   size_t smem = sizeof(double) * 4 * (size_t)(p->dev.S * NM + p->dev.ncomp_total);
   int64_t blocks = (N + 3) / 4;
-  if (p->prec == GMP_FP64)
-    GMP_LAUNCH("norm", k_finish<true>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N, partial, chunk_off,
-               features, components);
-  else
-    GMP_LAUNCH("norm", k_finish<false>, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N, partial, chunk_off,
-               features, components);
+  using FinishFn = void (*)(PlanDev, int64_t, const double *, const int64_t *, void *, double *);
+  static const FinishFn fns[2][kMaxL + 1] = {
+      {k_finish<0, false>, k_finish<1, false>, k_finish<2, false>, k_finish<3, false>, k_finish<4, false>},
+      {k_finish<0, true>, k_finish<1, true>, k_finish<2, true>, k_finish<3, true>, k_finish<4, true>}};
+  const int lm = p->dev.lmax < 0 ? 0 : (p->dev.lmax > kMaxL ? kMaxL : p->dev.lmax);
+  GMP_LAUNCH("norm", fns[p->prec == GMP_FP64 ? 1 : 0][lm], dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N,
+             partial, chunk_off, features, components);
 }
 
 }  // namespace gmp
