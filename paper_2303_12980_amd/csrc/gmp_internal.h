@@ -86,6 +86,7 @@ struct StructInfo {
   int pbc;
   int64_t bin_base;   // first bin slot of this structure
   double lam_lo;      // lower bound of the smallest eigenvalue of the lattice metric (0: no bin culling)
+  double inv_nb[3];   // 1 / nb[k] (bin-image culling bounds)
 };
 
 // Device view of a plan (passed by value to kernels).  S counts cutoff

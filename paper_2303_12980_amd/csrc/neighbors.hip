@@ -103,6 +103,7 @@ __global__ void k_struct_setup(BatchDev bt, StructInfo *info, double rcmax, int 
       }
     }
   }
+  for (int k = 0; k < 3; ++k) I.inv_nb[k] = 1.0 / (double)I.nb[k];
   info[s] = I;
 }
 
@@ -196,6 +197,7 @@ struct Cand {
   const double *cell;
   double f[3];
   int lo[3], hi[3], nv[3];
+  double inv_nv[3];
   int total;
 };
 
@@ -209,6 +211,7 @@ __device__ inline void cand_setup(Cand &C, const StructInfo *info, const BatchDe
   for (int k = 0; k < 3; ++k) {
     vrange(*C.I, k, C.f[k], C.lo[k], C.hi[k]);
     C.nv[k] = C.hi[k] - C.lo[k] + 1;
+    C.inv_nv[k] = 1.0 / (double)C.nv[k];
     C.total *= C.nv[k];
   }
 }
@@ -217,20 +220,28 @@ __device__ inline void cand_setup(Cand &C, const StructInfo *info, const BatchDe
 // when the whole bin image lies outside the cutoff sphere (fractional gaps
 // g_k to the centre satisfy lam_lo * |g|^2 > rc_max^2).
 __device__ inline int64_t cand_bin(const Cand &C, int v, int n[3], double rcmax2) {
+  // small non-negative / signed integer quotients through FP64 reciprocals:
+  // (x + 1/2) / d keeps its fractional part at least 1/(2d) from an integer,
+  // far above the rounding of the product
   int r[3];
   int t = v;
-  r[2] = t % C.nv[2]; t /= C.nv[2];
-  r[1] = t % C.nv[1]; t /= C.nv[1];
+  int q = (int)floor(((double)t + 0.5) * C.inv_nv[2]);
+  r[2] = t - q * C.nv[2]; t = q;
+  q = (int)floor(((double)t + 0.5) * C.inv_nv[1]);
+  r[1] = t - q * C.nv[1]; t = q;
   r[0] = t;
   int b[3];
   double g2 = 0.0;
   for (int k = 0; k < 3; ++k) {
     const int V = C.lo[k] + r[k];
     const int nbk = C.I->nb[k];
-    b[k] = pmod(V, nbk);
-    n[k] = floordiv(V, nbk);
+    n[k] = (int)floor(((double)V + 0.5) * C.I->inv_nb[k]);
+    b[k] = V - n[k] * nbk;
     if (C.I->pbc & (1 << k)) {
-      const double x0 = (double)V / (double)nbk, x1 = (double)(V + 1) / (double)nbk;
+      // bin-image bounds in fractional coordinates; a product with the
+      // reciprocal is within 2 ulp of the quotient, far inside the 1e-9
+      // slack that keeps the culling conservative
+      const double x0 = (double)V * C.I->inv_nb[k], x1 = (double)(V + 1) * C.I->inv_nb[k];
       double g = x0 - C.f[k];
       const double g1 = C.f[k] - x1;
       g = g > g1 ? g : g1;
