@@ -377,6 +377,29 @@ __device__ inline void cmpswap(uint64_t *a, int i, int l) {
   if (x > y) { a[i] = y; a[l] = x; }
 }
 
+// Four elements e0 < e1 < e2 < e3 through two comparator stages in
+// registers: mirror = true compares (e0, e3), (e1, e2) and then (e0, e1),
+// (e2, e3); otherwise (e0, e2), (e1, e3) and then (e0, e1), (e2, e3).
+// Positions >= n read as +infinity and are not written.
+__device__ inline void group4(uint64_t *a, int n, int e0, int e1, int e2, int e3, bool mirror) {
+  uint64_t x0 = e0 < n ? a[e0] : ~0ull, x1 = e1 < n ? a[e1] : ~0ull;
+  uint64_t x2 = e2 < n ? a[e2] : ~0ull, x3 = e3 < n ? a[e3] : ~0ull;
+  uint64_t u;
+  if (mirror) {
+    if (x0 > x3) { u = x0; x0 = x3; x3 = u; }
+    if (x1 > x2) { u = x1; x1 = x2; x2 = u; }
+  } else {
+    if (x0 > x2) { u = x0; x0 = x2; x2 = u; }
+    if (x1 > x3) { u = x1; x1 = x3; x3 = u; }
+  }
+  if (x0 > x1) { u = x0; x0 = x1; x1 = u; }
+  if (x2 > x3) { u = x2; x2 = x3; x3 = u; }
+  if (e0 < n) a[e0] = x0;
+  if (e1 < n) a[e1] = x1;
+  if (e2 < n) a[e2] = x2;
+  if (e3 < n) a[e3] = x3;
+}
+
 // Sort a[0..n) of distinct keys ascending by one wavefront.  Up to 64 keys:
 // each lane counts the keys below its own (broadcast LDS reads) and stores
 // its key at that rank.  Longer: bitonic network whose first merge stage
@@ -397,21 +420,42 @@ __device__ void wave_sort(uint64_t *a, int n) {
   int lp2 = 1;
   while ((1 << lp2) < n) ++lp2;
   const int half = 1 << (lp2 - 1);
-  // block sizes are powers of two: block and offset by shift and mask
+  // Comparators in groups of four that are closed under two consecutive
+  // stages: each pass reads a lane's group once, compares in registers and
+  // writes it once (indices >= n stay +infinity, never written); block
+  // sizes are powers of two, so block and offset are shifts and masks.
+  const int quarter = half >> 1;
   for (int lk = 1; lk <= lp2; ++lk) {
-    const int k = 1 << lk, lh = lk - 1;
-    for (int t = lane; t < half; t += kWave) {
-      const int blk = t >> lh, off = t & ((1 << lh) - 1);
-      const int i = (blk << lk) + off, l = (blk << lk) + k - 1 - off;
-      if (l < n) cmpswap(a, i, l);
-    }
-    wave_lds_sync();
-    for (int lj = lk - 2; lj >= 0; --lj) {
-      const int j = 1 << lj;
+    const int k = 1 << lk;
+    int lj;
+    if (lk == 1) {  // blocks of two: the mirror stage alone
       for (int t = lane; t < half; t += kWave) {
-        const int blk = t >> lj, off = t & (j - 1);
-        const int i = (blk << (lj + 1)) + off, l = i + j;
-        if (l < n) cmpswap(a, i, l);
+        const int i = t << 1;
+        if (i + 1 < n) cmpswap(a, i, i + 1);
+      }
+      wave_lds_sync();
+      lj = -1;
+    } else {  // mirror stage and the stage of distance k/4
+      const int lq = lk - 2, Q = 1 << lq;
+      for (int t = lane; t < quarter; t += kWave) {
+        const int base = (t >> lq) << lk, off = t & (Q - 1);
+        group4(a, n, base + off, base + off + Q, base + k - 1 - off - Q, base + k - 1 - off, true);
+      }
+      wave_lds_sync();
+      lj = lk - 3;
+    }
+    for (; lj >= 1; lj -= 2) {  // the stages of distance j and j/2
+      const int J = 1 << lj, H = J >> 1;
+      for (int t = lane; t < quarter; t += kWave) {
+        const int b = ((t >> (lj - 1)) << (lj + 1)) + (t & (H - 1));
+        group4(a, n, b, b + H, b + J, b + J + H, false);
+      }
+      wave_lds_sync();
+    }
+    if (lj == 0) {  // a last stage of distance 1
+      for (int t = lane; t < half; t += kWave) {
+        const int i = t << 1;
+        if (i + 1 < n) cmpswap(a, i, i + 1);
       }
       wave_lds_sync();
     }
