@@ -42,3 +42,32 @@ def test_reverse_index_across_bucket_sizes(g, ws, tau):
     sizes = np.diff(nb.offsets.cpu().numpy())
     say(f"  list lengths {sizes.min()}..{sizes.max()}, {int(nb.n_pairs)} pairs")
     check_neighbors(nb, b, p)
+
+
+@pytest.mark.parametrize("tau", [1e-9, 1e-14])
+def test_long_single_bucket_lists(g, ws, tau):
+    """Lists of 2,900-5,700 neighbours in one bucket: the in-LDS bitonic sort
+    runs many grouped comparator passes per lane, the reverse search many
+    sampled keys per bucket, and the overlap several chunks per centre; lists
+    bit-exact, features and gradients against the oracle on the FP64 path
+    (this near-isotropic environment cancels the l = 1 moment to ~1.5e-5 of
+    the l = 0 feature, beyond what FP32 pair terms resolve at 1e-5)."""
+    from gpu_helpers import assert_features
+    rng = np.random.default_rng(93)
+    st = gs.small_periodic(rng, n_atoms=12, n_elements=1, density=0.08, dmin=1.1)
+    b = gs.make_batch([st])
+    p = gs.Probes(np.array([0, 1, 2], np.int32), np.array([0.5]), np.array([0, 1], np.int32),
+                  np.array([1.0]), np.array([0.05]), tau)
+    say(f"[long lists, tau={tau:g}]")
+    plan, db, nb, F, mu = run_path(g, b, p, "fp64", ws)
+    sizes = np.diff(nb.offsets.cpu().numpy())
+    say(f"  list lengths {sizes.min()}..{sizes.max()}")
+    assert sizes.min() > 2048  # several overlap chunks per centre
+    check_neighbors(nb, b, p)
+    assert_features(F.cpu().numpy(), oracle.features_batch(b, p), p.tau, 1e-11)
+    G = np.random.default_rng(94).standard_normal((b.n_atoms, p.n_features))
+    gp, gc = g.features_backward(plan, db, nb, ws, mu, F, torch.as_tensor(G, device="cuda"))
+    rp, rc, _ = oracle.grad(st, p, G)
+    scale = max(np.abs(rp).max(), np.abs(rc).max())
+    assert np.abs(gp.cpu().numpy() - rp).max() <= 1e-9 * scale
+    assert np.abs(gc.cpu().numpy()[0] - rc).max() <= 1e-9 * scale
