@@ -290,23 +290,37 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
         for (int l = 0; l <= LMAX; ++l) {
           if (!((mask >> l) & 1)) continue;
           // P(d) = sum_m M_m d^m and its gradient from the same coefficients:
-          // d/dx of x^a y^b z^c is a x^(a-1) y^b z^c (exponents are constants)
-          T Q = (T)0, gx = (T)0, gy = (T)0, gz = (T)0;
+          // d/dx of x^a y^b z^c is a x^(a-1) y^b z^c (exponents are constants).
+          // FP32: gradient terms summed per exponent value e, then combined as
+          // sum e g_e (fewer instructions); FP64: each term scaled by its e.
+          T Q = (T)0, gx[LMAX + 1], gy[LMAX + 1], gz[LMAX + 1];
+#pragma unroll
+          for (int e = 0; e <= LMAX; ++e) { gx[e] = (T)0; gy[e] = (T)0; gz[e] = (T)0; }
 #pragma unroll
           for (int mm = 0; mm < ncomp(l); ++mm) {
             const int m = doff(l) + mm;
             const T Mv = bc[m];
             Q = fma_(Mv, mono[m], Q);
             const int a = kMT.ea[m], b = kMT.eb[m], c = kMT.ec[m];
-            if (a >= 1) gx = fma_(a == 1 ? Mv : (T)a * Mv, mono[doff(l - 1) + midx(l - 1, a - 1, b)], gx);
-            if (b >= 1) gy = fma_(b == 1 ? Mv : (T)b * Mv, mono[doff(l - 1) + midx(l - 1, a, b - 1)], gy);
-            if (c >= 1) gz = fma_(c == 1 ? Mv : (T)c * Mv, mono[doff(l - 1) + midx(l - 1, a, b)], gz);
+            const int ia = F64 ? 1 : a, ib = F64 ? 1 : b, ic = F64 ? 1 : c;  // accumulator index
+            if (a >= 1) gx[ia] = fma_(F64 && a > 1 ? (T)a * Mv : Mv, mono[doff(l - 1) + midx(l - 1, a - 1, b)], gx[ia]);
+            if (b >= 1) gy[ib] = fma_(F64 && b > 1 ? (T)b * Mv : Mv, mono[doff(l - 1) + midx(l - 1, a, b - 1)], gy[ib]);
+            if (c >= 1) gz[ic] = fma_(F64 && c > 1 ? (T)c * Mv : Mv, mono[doff(l - 1) + midx(l - 1, a, b)], gz[ic]);
           }
           A = fma_(cp[l], Q, A);
           if (l >= 1) {
-            Bx = fma_(cl[l], gx, Bx);
-            By = fma_(cl[l], gy, By);
-            Bz = fma_(cl[l], gz, Bz);
+            T sx = gx[1], sy = gy[1], sz = gz[1];
+            if constexpr (!F64) {
+#pragma unroll
+              for (int e = 2; e <= l; ++e) {
+                sx = fma_((T)e, gx[e], sx);
+                sy = fma_((T)e, gy[e], sy);
+                sz = fma_((T)e, gz[e], sz);
+              }
+            }
+            Bx = fma_(cl[l], sx, Bx);
+            By = fma_(cl[l], sy, By);
+            Bz = fma_(cl[l], sz, Bz);
           }
         }
         const T A2 = A + A;
