@@ -45,6 +45,13 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   const int64_t N = n_centres(bt);
   using T = typename Real<F64>::T;
   extern __shared__ double lds_b[];
+  // moment -> component maps of all orders and the multinomial weights,
+  // staged in LDS once per workgroup (read with lane-varying indices)
+  __shared__ double lds_T[kTmat];
+  __shared__ double lds_w[nmono(kMaxL)];
+  for (int t = threadIdx.x; t < kTmat; t += blockDim.x) lds_T[t] = P.T[t];
+  for (int t = threadIdx.x; t < nmono(kMaxL); t += blockDim.x) lds_w[t] = P.weight[t];
+  __syncthreads();
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
   // block sizes are compile-time constants (the index splits below are then
@@ -74,7 +81,7 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
         const int s = t - P.feat_off[o], nc = ncomp(l);
         const double *mv = mu + P.comp_off[o] + s * nc;
         double a = 0.0;
-        for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
+        for (int cc = 0; cc < nc; ++cc) a += lds_w[doff(l) + cc] * mv[cc] * mv[cc];
         F = sqrt(a);
       }
       // unit upstream gradient (grad_features null): the coefficients of dF/dd per feature
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
         if (o >= 0) {
           const int nc = ncomp(l), mm = m - doff(l);
           const double *mv = mu + P.comp_off[o] + s * nc;
-          for (int cc = 0; cc < nc; ++cc) v += P.weight[doff(l) + cc] * mv[cc] * P.T[P.toff[l] + cc * nc + mm];
+          for (int cc = 0; cc < nc; ++cc) v += lds_w[doff(l) + cc] * mv[cc] * lds_T[P.toff[l] + cc * nc + mm];
           v *= scale[P.feat_off[o] + s];
         }
       }

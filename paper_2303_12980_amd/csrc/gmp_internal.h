@@ -75,6 +75,13 @@ __host__ __device__ constexpr MonoTable make_mono_table() {
 // entries so the pair kernels' wavefront-uniform LDS reads can be 16-byte
 // vector reads.  The pair kernels take the gradient of the polynomial from
 // the same coefficients (exponents are compile-time constants).
+// entries of the moment -> component maps of orders 0..kMaxL (ncomp(l)^2 each)
+__host__ __device__ constexpr int tmat_size() {
+  int n = 0;
+  for (int l = 0; l <= kMaxL; ++l) n += ncomp(l) * ncomp(l);
+  return n;
+}
+constexpr int kTmat = tmat_size();
 __host__ __device__ constexpr int round4(int n) { return (n + 3) & ~3; }
 __host__ __device__ constexpr int coef_m(int lmax) { return round4(nmono(lmax)); }
 __host__ __device__ constexpr int coef_block(int lmax) { return coef_m(lmax); }

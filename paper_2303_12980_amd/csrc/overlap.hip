@@ -384,6 +384,13 @@ template <int LMAX, bool F64OUT>
 __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const double *partial,
                                                 const int64_t *chunk_off, void *features, double *components) {
   extern __shared__ double lds_f[];
+  // moment -> component maps of all orders and the multinomial weights,
+  // staged in LDS once per workgroup (read with lane-varying indices)
+  __shared__ double lds_T[kTmat];
+  __shared__ double lds_w[nmono(kMaxL)];
+  for (int t = threadIdx.x; t < kTmat; t += blockDim.x) lds_T[t] = P.T[t];
+  for (int t = threadIdx.x; t < nmono(kMaxL); t += blockDim.x) lds_w[t] = P.weight[t];
+  __syncthreads();
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
   constexpr int NM = nmono(LMAX);  // compile-time: the index splits below are not divisions
@@ -415,7 +422,7 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
         const int nc = ncomp(l);
         const int r = t - P.comp_off[o];
         const int s = r / nc, cc = r - s * nc;
-        const double *Tl = P.T + P.toff[l] + cc * nc;
+        const double *Tl = lds_T + P.toff[l] + cc * nc;
         const double *ms = mom + s * NM + doff(l);
         for (int mm = 0; mm < nc; ++mm) v += Tl[mm] * ms[mm];
       }
@@ -436,7 +443,7 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
         const int s = t - P.feat_off[o], nc = ncomp(l);
         const double *mv = mu + P.comp_off[o] + s * nc;
         double a = 0.0;
-        for (int cc = 0; cc < nc; ++cc) a += P.weight[doff(l) + cc] * mv[cc] * mv[cc];
+        for (int cc = 0; cc < nc; ++cc) a += lds_w[doff(l) + cc] * mv[cc] * mv[cc];
         F = sqrt(a);
       }
       if (F64OUT) ((double *)features)[(size_t)i * P.nf + t] = F;
