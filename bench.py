@@ -574,8 +574,10 @@ def main():
         "value": value, "unit": "atoms*features/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt_fb * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: periodic 40x40x40 A cell, {N} atoms, 5 elements, "
-                               f"5 primitives/element, l=0..4 x 8 sigma (0.1-1.6 A), tau 1e-11",
+        "config": {"workload": (f"{args.workload}: periodic 40x40x40 A cell, {N} atoms, 5 elements, "
+                                f"5 primitives/element, l=0..4 x 8 sigma (0.1-1.6 A), tau 1e-11"
+                                if args.workload.upper() == "C2" else
+                                f"{args.workload}: {gs.CONFIG_TEXT[args.workload.upper()]}"),
                    "atoms": N, "features_per_atom": nf, "pairs": counts["pairs"], "precision": "fp32c"},
         "roofline": roofline,
         "cpu_baseline": cpu,
