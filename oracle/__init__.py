@@ -68,6 +68,13 @@ def lib():
             L.oracle_features.restype = c_int
             L.oracle_grad.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, dp, dp, dp, dp, dp]
             L.oracle_grad.restype = c_int
+            L.oracle_features_abs.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp]
+            L.oracle_features_abs.restype = c_int
+            L.oracle_grad_centres.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp, dp, dp]
+            L.oracle_grad_centres.restype = c_int
+            L.oracle_neighbors_many.argtypes = [c_int, dp, ip, dp, c_int, c_int, dp, c_int, ip, lp, c_i64,
+                                                ip, ip, dp, ip, ip]
+            L.oracle_neighbors_many.restype = c_i64
             L.oracle_loss_frozen.argtypes = [c_int, dp, ip, dp, *probe_args, lp, ip, ip, dp, dp, dp, dp]
             L.oracle_loss_frozen.restype = c_int
             L.oracle_point_neighbors.argtypes = [c_int, dp, ip, dp, c_int, c_int, dp, dp, c_i64,
@@ -204,6 +211,35 @@ def neighbors(struct, rc2, centre: int):
         cap = int(cnt)
 
 
+def neighbors_many(struct, rc2, centres):
+    """Canonical lists of many centres (the same lists as neighbors(), in
+    parallel over centres): dict with offs [k+1], j, n [P,3], q, shell, e."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    rc2, rp = _d(rc2)
+    cl, clp = _i(np.asarray(centres))
+    offs = np.zeros(len(cl) + 1, np.int64)
+    st = ctypes.c_int32(0)
+    L = lib()
+    ip = ctypes.POINTER(ctypes.c_int32)
+    total = L.oracle_neighbors_many(len(pos), pp, sp, cp, int(pbc), len(rc2), rp, len(cl), clp,
+                                    offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0, None, None, None,
+                                    None, ctypes.byref(st))
+    _check(st.value)
+    j = np.zeros(max(total, 1), np.int32); n = np.zeros((max(total, 1), 3), np.int32)
+    q = np.zeros(max(total, 1)); sh = np.zeros(max(total, 1), np.int32)
+    t2 = L.oracle_neighbors_many(len(pos), pp, sp, cp, int(pbc), len(rc2), rp, len(cl), clp,
+                                 offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), total,
+                                 j.ctypes.data_as(ip), n.ctypes.data_as(ip), _dp(q), sh.ctypes.data_as(ip),
+                                 ctypes.byref(st))
+    _check(st.value)
+    assert t2 == total
+    j, n, q, sh = j[:total], n[:total], q[:total], sh[:total]
+    return dict(offs=offs, j=j, n=n, q=q, shell=sh, e=np.asarray(spec)[j])
+
+
 def _occ(occupancy, n):
     """(keep-alive array, pointer) of the per-atom occupancies, or (None, None)."""
     if occupancy is None:
@@ -240,6 +276,26 @@ def features(struct, probes, centres: Optional[Sequence[int]] = None, with_mu: b
     return (F, mu) if with_mu else F
 
 
+def features_abs(struct, probes, centres: Optional[Sequence[int]] = None, occupancy=None):
+    """F_abs [n_centres, nf]: the features of the absolute values of the pair
+    terms (the conditioning reference kappa = F_abs / F of a feature)."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    keep, a = _probe_args(probes)
+    if centres is None:
+        nc, cptr, carr, ncent = -1, None, None, len(pos)
+    else:
+        carr, cptr = _i(np.asarray(centres))
+        nc = ncent = len(carr)
+    F = np.zeros((ncent, n_features(probes.orders, len(probes.sigmas))))
+    occ, op = _occ(occupancy, len(pos))
+    _check(lib().oracle_features_abs(len(pos), pp, sp, cp, int(pbc), *a, nc, cptr,
+                                     F.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), op))
+    return F
+
+
 def features_batch(batch, probes, with_mu=False):
     Fs, mus = [], []
     occ = getattr(batch, "occupancy", None)
@@ -272,6 +328,26 @@ def grad(struct, probes, G, occupancy=None):
                              gcell.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              F.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), op))
     return gpos, gcell, F
+
+
+def grad_centres(struct, probes, centres, G, occupancy=None):
+    """Analytic dL/dR [n,3] and dL/dcell [3,3] of L = sum_t G[t] . F[centres[t]]:
+    the gradient of oracle grad() with the upstream gradient zero on every
+    centre not listed (centres distinct; G [len(centres), nf])."""
+    pos, spec, cell, pbc = struct
+    pos, pp = _d(pos)
+    spec, sp = _i(spec)
+    cell, cp = _d(np.asarray(cell).reshape(9))
+    keep, a = _probe_args(probes)
+    cl, clp = _i(np.asarray(centres))
+    G, gp = _d(np.asarray(G).reshape(len(cl), -1))
+    n = len(pos)
+    gpos = np.zeros((n, 3)); gcell = np.zeros((3, 3))
+    occ, op = _occ(occupancy, n)
+    _check(lib().oracle_grad_centres(n, pp, sp, cp, int(pbc), *a, len(cl), clp, gp,
+                                     gpos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     gcell.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), op))
+    return gpos, gcell
 
 
 def frozen_pairs(struct, probes):

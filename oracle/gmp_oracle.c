@@ -448,6 +448,51 @@ int64_t oracle_neighbors(int n_atoms, const double *pos, const int32_t *species,
   return n;
 }
 
+/*
+ * Canonical lists of many centres at once (the same lists as
+ * oracle_neighbors, computed in parallel over centres): centre list[t]'s
+ * entries go to [offs[t], offs[t+1]) of the outputs.  Pass 1 (out_j NULL)
+ * fills offs [n_list+1] only; pass 2 writes j, n [3 each], q and shell for
+ * at most cap entries.  Returns the total count.
+ */
+int64_t oracle_neighbors_many(int n_atoms, const double *pos, const int32_t *species,
+                              const double *cell, int pbc, int n_sigmas, const double *rc2,
+                              int n_list, const int32_t *list, int64_t *offs, int64_t cap,
+                              int32_t *out_j, int32_t *out_n, double *out_q, int32_t *out_shell,
+                              int32_t *status) {
+  double rcmax2 = 0.0;
+  for (int s = 0; s < n_sigmas; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw; int32_t *m;
+  *status = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (*status) return 0;
+  for (int t = 0; t < n_list; ++t)
+    if (list[t] < 0 || list[t] >= n_atoms) { *status = OR_E_INVALID; free(rw); free(m); return 0; }
+  int64_t *cnt = (int64_t *)calloc((size_t)(n_list > 0 ? n_list : 1), sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < n_list; ++t) {
+    pair_t *P;
+    int64_t n = collect(&S, list[t], n_sigmas, rc2, &P);
+    cnt[t] = n;
+    if (out_j && offs[t] + n <= cap) {
+      for (int64_t k = 0; k < n; ++k) {
+        const int64_t o = offs[t] + k;
+        out_j[o] = P[k].j;
+        out_n[3 * o] = P[k].n[0]; out_n[3 * o + 1] = P[k].n[1]; out_n[3 * o + 2] = P[k].n[2];
+        out_q[o] = P[k].q; out_shell[o] = P[k].shell;
+      }
+    }
+    free(P);
+  }
+  int64_t total = 0;
+  if (!out_j) {
+    offs[0] = 0;
+    for (int t = 0; t < n_list; ++t) offs[t + 1] = offs[t] + cnt[t];
+  }
+  for (int t = 0; t < n_list; ++t) total += cnt[t];
+  free(cnt); free(rw); free(m);
+  return total;
+}
+
 /* ------------------------------------------------------------------ */
 /* features                                                            */
 /* ------------------------------------------------------------------ */
@@ -477,14 +522,26 @@ static int check_probes(const probes_t *P) {
 /* add one pair's terms to mu, laid out [order][sigma][comp] (order -1: one
  * entry); `use` is the squared distance that decides which slots see the
  * pair, (x, y, z) and q the displacement and squared distance evaluated */
+static void pair_terms_mode(const probes_t *P, const pair_t *pp, double use, const double *rc2, double *mu,
+                            int absval);
 static void pair_terms(const probes_t *P, const pair_t *pp, double use, const double *rc2, double *mu) {
+  pair_terms_mode(P, pp, use, rc2, mu, 0);
+}
+
+/* absval = 1 adds |term| instead of term (the conditioning reference
+ * F_abs: the feature of the absolute values of the pair terms) */
+static void pair_terms_mode(const probes_t *P, const pair_t *pp, double use, const double *rc2, double *mu,
+                            int absval) {
   dual x = dconst(pp->d[0]), y = dconst(pp->d[1]), z = dconst(pp->d[2]);
   dual q = dconst(pp->q);
   int off = 0;
   for (int o = 0; o < P->n_orders; ++o) {
     int l = P->orders[o];
     if (l < 0) {
-      if (use <= rc2[P->n_sigmas]) mu[off] += pp->w * density(P, pp->e, q, use).v;
+      if (use <= rc2[P->n_sigmas]) {
+        const double t = pp->w * density(P, pp->e, q, use).v;
+        mu[off] += absval ? fabs(t) : t;
+      }
       off += 1;
       continue;
     }
@@ -493,7 +550,8 @@ static void pair_terms(const probes_t *P, const pair_t *pp, double use, const do
       double c = radial(P, l, s, pp->e, q, use).v;
       for (int k = 0; k < ncomp(l); ++k) {
         int a, b, cc; comp_abc(l, k, &a, &b, &cc);
-        mu[(size_t)(off + s * ncomp(l) + k)] += pp->w * (c * solid_harmonic(a, b, cc, x, y, z).v);
+        const double t = pp->w * (c * solid_harmonic(a, b, cc, x, y, z).v);
+        mu[(size_t)(off + s * ncomp(l) + k)] += absval ? fabs(t) : t;
       }
     }
     off += order_comps(P, l);
@@ -571,6 +629,49 @@ int oracle_features(int n_atoms, const double *pos, const int32_t *species,
     centre_features(&P, pairs, np, rc2, mu_i, F + (size_t)t * nf);
     if (mu) memcpy(mu + (size_t)t * nc, mu_i, sizeof(double) * (size_t)nc);
     free(mu_i); free(pairs);
+  }
+  free(rc2); free(rw); free(m);
+  return OR_OK;
+}
+
+/*
+ * Conditioning reference of the listed centres: F_abs, the features computed
+ * from the absolute values of every pair term (same layout as
+ * oracle_features).  F_abs / F bounds how far a feature is the remainder of
+ * cancelling terms: a result whose every pair term carries a relative error
+ * e is within e F_abs of the exact feature.
+ */
+int oracle_features_abs(int n_atoms, const double *pos, const int32_t *species,
+                        const double *cell, int pbc,
+                        int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                        int n_elements, const int32_t *prim_offsets, const double *B,
+                        const double *beta, double tau, int screen,
+                        int n_centres, const int32_t *centres, double *F, const double *occ) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
+  int st = check_probes(&P);
+  if (st) return st;
+  for (int i = 0; i < n_atoms; ++i)
+    if (species[i] < 0 || species[i] >= n_elements) return OR_E_INVALID;
+  const int ns = n_slots(&P);
+  double *rc2 = (double *)malloc(sizeof(double) * ns);
+  st = slot_cutoffs(&P, rc2);
+  double rcmax2 = 0.0;
+  for (int s = 0; s < ns; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw = NULL; int32_t *m = NULL;
+  if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (st) { free(rc2); return st; }
+  S.occ = occ;
+  const int nc = total_comps(&P), nf = total_feats(&P);
+  const int ncent = n_centres < 0 ? n_atoms : n_centres;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < ncent; ++t) {
+    int i = n_centres < 0 ? t : centres[t];
+    pair_t *pairs;
+    int64_t np = collect(&S, i, ns, rc2, &pairs);
+    double *mu = (double *)calloc((size_t)nc, sizeof(double));
+    for (int64_t p = 0; p < np; ++p) pair_terms_mode(&P, pairs + p, pairs[p].q, rc2, mu, 1);
+    norms(&P, mu, F + (size_t)t * nf);
+    free(mu); free(pairs);
   }
   free(rc2); free(rw); free(m);
   return OR_OK;
@@ -687,6 +788,73 @@ int oracle_grad(int n_atoms, const double *pos, const int32_t *species,
     free(pairs);
   }
   free(mu); free(W); free(Fi); free(rc2); free(rw); free(m);
+  return OR_OK;
+}
+
+/*
+ * Gradient of L restricted to listed centres: L = sum over the n_list centres
+ * list[t] of sum_f G[t][f] F[list[t]][f] (the upstream gradient is zero on
+ * every other centre), with the same definitions as oracle_grad.  Centres
+ * are independent, so their pair vectors are computed in parallel into
+ * per-centre buffers; the scatter into grad_pos / grad_cell then runs in list
+ * order, one centre after another, as oracle_grad's loop does.  grad_pos
+ * [n_atoms*3], grad_cell [9]; occ as in oracle_features.
+ */
+int oracle_grad_centres(int n_atoms, const double *pos, const int32_t *species,
+                        const double *cell, int pbc,
+                        int n_orders, const int32_t *orders, int n_sigmas, const double *sigmas,
+                        int n_elements, const int32_t *prim_offsets, const double *B,
+                        const double *beta, double tau, int screen,
+                        int n_list, const int32_t *list, const double *G,
+                        double *grad_pos, double *grad_cell, const double *occ) {
+  probes_t P = {n_orders, orders, n_sigmas, sigmas, n_elements, prim_offsets, B, beta, tau, screen};
+  int st = check_probes(&P);
+  if (st) return st;
+  for (int i = 0; i < n_atoms; ++i)
+    if (species[i] < 0 || species[i] >= n_elements) return OR_E_INVALID;
+  for (int t = 0; t < n_list; ++t)
+    if (list[t] < 0 || list[t] >= n_atoms) return OR_E_INVALID;
+  const int ns = n_slots(&P);
+  double *rc2 = (double *)malloc(sizeof(double) * ns);
+  st = slot_cutoffs(&P, rc2);
+  double rcmax2 = 0.0;
+  for (int s = 0; s < ns; ++s) if (rc2[s] > rcmax2) rcmax2 = rc2[s];
+  sys_t S; double *rw = NULL; int32_t *m = NULL;
+  if (!st) st = make_sys(&S, n_atoms, pos, species, cell, pbc, rcmax2, &rw, &m);
+  if (st) { free(rc2); return st; }
+  S.occ = occ;
+  const int nc = total_comps(&P), nf = total_feats(&P);
+  pair_t **pairs = (pair_t **)calloc((size_t)(n_list > 0 ? n_list : 1), sizeof(pair_t *));
+  int64_t *np = (int64_t *)calloc((size_t)(n_list > 0 ? n_list : 1), sizeof(int64_t));
+  double **vv = (double **)calloc((size_t)(n_list > 0 ? n_list : 1), sizeof(double *));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < n_list; ++t) {
+    double *mu = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *W = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *Fi = (double *)malloc(sizeof(double) * nf);
+    np[t] = collect(&S, list[t], ns, rc2, &pairs[t]);
+    centre_features(&P, pairs[t], np[t], rc2, mu, Fi);
+    make_W(&P, mu, Fi, G + (size_t)t * nf, W);
+    vv[t] = (double *)malloc(sizeof(double) * 3 * (size_t)(np[t] > 0 ? np[t] : 1));
+    for (int64_t p = 0; p < np[t]; ++p) pair_v(&P, pairs[t] + p, rc2, W, vv[t] + 3 * p);
+    free(mu); free(W); free(Fi);
+  }
+  memset(grad_pos, 0, sizeof(double) * 3 * (size_t)n_atoms);
+  memset(grad_cell, 0, sizeof(double) * 9);
+  for (int t = 0; t < n_list; ++t) {
+    const int i = list[t];
+    for (int64_t p = 0; p < np[t]; ++p) {
+      const double *v = vv[t] + 3 * p;
+      const int j = pairs[t][p].j;
+      for (int k = 0; k < 3; ++k) { grad_pos[3 * j + k] += v[k]; grad_pos[3 * i + k] -= v[k]; }
+      for (int a = 0; a < 3; ++a) {
+        double nt = (double)(pairs[t][p].n[a] - m[3 * j + a] + m[3 * i + a]);
+        for (int k = 0; k < 3; ++k) grad_cell[3 * a + k] += nt * v[k];
+      }
+    }
+    free(vv[t]); free(pairs[t]);
+  }
+  free(vv); free(pairs); free(np); free(rc2); free(rw); free(m);
   return OR_OK;
 }
 

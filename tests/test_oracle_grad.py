@@ -86,3 +86,43 @@ def test_grad_isolated_atom_is_zero():
     G = np.ones((1, probes.n_features))
     gpos, gcell, _ = oracle.grad((np.zeros((1, 3)), np.zeros(1, np.int32), np.zeros((3, 3)), 0), probes, G)
     assert np.all(gpos == 0.0)
+
+
+def test_grad_restricted_to_listed_centres():
+    """The gradient restricted to listed centres (used where the full oracle
+    gradient of a large system is too slow): with every centre listed it is
+    oracle grad() bit for bit; with a subset it equals grad() with G zero on
+    the other centres, and central differences of the frozen-pair loss with
+    that G (an independent check of the restriction)."""
+    rng = np.random.default_rng(11)
+    struct = gs.small_periodic(rng, n_atoms=7, density=0.05, dmin=1.4)
+    probes = _probes(12)
+    G = rng.standard_normal((7, probes.n_features))
+    gp_all, gc_all, _ = oracle.grad(struct, probes, G)
+    gp, gc = oracle.grad_centres(struct, probes, np.arange(7), G)
+    assert np.array_equal(gp, gp_all) and np.array_equal(gc, gc_all)
+    sub = np.array([5, 1, 3])
+    Gz = np.zeros_like(G)
+    Gz[sub] = G[sub]
+    gp_z, gc_z, _ = oracle.grad(struct, probes, Gz)
+    gp_s, gc_s = oracle.grad_centres(struct, probes, sub, G[sub])
+    scale = max(np.abs(gp_z).max(), np.abs(gc_z).max())
+    assert np.abs(gp_s - gp_z).max() <= 1e-14 * scale and np.abs(gc_s - gc_z).max() <= 1e-14 * scale
+    gp_fd, gc_fd = _fd_check(struct, probes, Gz, [(i, k) for i in range(7) for k in range(3)],
+                             [(a, k) for a in range(3) for k in range(3)])
+    assert np.abs(gp_s - gp_fd).max() <= 1e-14 * scale
+
+
+def test_neighbors_many_equal_single_lists():
+    """Lists of many centres computed together are the single-centre lists."""
+    rng = np.random.default_rng(13)
+    struct = gs.small_periodic(rng, n_atoms=9, density=0.06, dmin=1.3)
+    probes = _probes(14)
+    rc2 = oracle.cutoffs(probes)
+    cs = [4, 0, 8, 2]
+    r = oracle.neighbors_many(struct, rc2, cs)
+    for t, c in enumerate(cs):
+        one = oracle.neighbors(struct, rc2, c)
+        lo, hi = r["offs"][t], r["offs"][t + 1]
+        for key in ("j", "n", "q", "shell", "e"):
+            assert np.array_equal(r[key][lo:hi], one[key]), key
