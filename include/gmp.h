@@ -56,6 +56,9 @@ typedef enum {
   GMP_E_NONFINITE = 5,    /* non-finite coordinate or lattice entry */
   GMP_E_HIP = 6,          /* a HIP runtime call failed */
   GMP_E_NOMEM = 7,        /* host allocation or workspace too small */
+  GMP_E_STALE = 8,        /* a no-sync rebuild met a list longer than the sort sized from max_list of the
+                             last synchronous build: that centre holds placeholder entries; call the
+                             synchronous build (which re-sizes) */
 } gmp_status;
 
 /* Arithmetic of the overlap kernels.
@@ -134,7 +137,11 @@ typedef struct {
  * b = shell * n_elements + species holds the entries of one (shell, species). */
 typedef struct {
   int64_t capacity;              /* [host] entries allocated in j, shift, reverse */
-  int64_t n_pairs;               /* [host] set by gmp_build_neighbors (sync mode) */
+  int64_t n_pairs;               /* [host] total pairs, set by a synchronous build; a no-sync build sets
+                                    it to 0 (unknown on the host): every call then bounds its pair
+                                    range by the capacity and the list ends on the device.  Callers
+                                    that copy this struct must not pass a count from an earlier
+                                    build after a no-sync rebuild */
   int64_t *offsets;              /* [n_centres+1] */
   int32_t *j;                    /* [capacity] neighbour atom (global index) */
   int32_t *shift;                /* [capacity] bytes (n1, n2, n3, species_j), n_k signed, little endian;

@@ -13,9 +13,9 @@ P_i32 = ctypes.POINTER(c_i32)
 P_dbl = ctypes.POINTER(c_dbl)
 
 GMP_OK, GMP_E_INVALID, GMP_E_UNSUPPORTED, GMP_E_CELL = 0, 1, 2, 3
-GMP_E_CAPACITY, GMP_E_NONFINITE, GMP_E_HIP, GMP_E_NOMEM = 4, 5, 6, 7
+GMP_E_CAPACITY, GMP_E_NONFINITE, GMP_E_HIP, GMP_E_NOMEM, GMP_E_STALE = 4, 5, 6, 7, 8
 STATUS_NAMES = {0: "GMP_OK", 1: "GMP_E_INVALID", 2: "GMP_E_UNSUPPORTED", 3: "GMP_E_CELL",
-                4: "GMP_E_CAPACITY", 5: "GMP_E_NONFINITE", 6: "GMP_E_HIP", 7: "GMP_E_NOMEM"}
+                4: "GMP_E_CAPACITY", 5: "GMP_E_NONFINITE", 6: "GMP_E_HIP", 7: "GMP_E_NOMEM", 8: "GMP_E_STALE"}
 GMP_FP64, GMP_FP32_COMPENSATED, GMP_FP32_WIDE = 0, 1, 2
 
 # every symbol include/gmp.h declares

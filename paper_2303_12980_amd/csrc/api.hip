@@ -588,9 +588,19 @@ gmp_status status_to_error(uint32_t st) {
   if (st & ST_SHIFT_RANGE) return set_error(GMP_E_UNSUPPORTED, "cutoff spans more than 126 cells along an axis");
   if (st & ST_OVERFLOW) return set_error(GMP_E_CAPACITY, "neighbour capacity exceeded (no-sync mode)");
   if (st & ST_SORT_SIZE)
-    return set_error(GMP_E_UNSUPPORTED, "a centre has more neighbours than the in-LDS sort holds");
+    return set_error(GMP_E_STALE,
+                     "a list outgrew the in-LDS sort sized by the last synchronous build (max_list); "
+                     "rebuild synchronously");
   if (st & ST_INTERNAL) return set_error(GMP_E_INVALID, "inconsistent neighbour lists (internal check)");
   return set_error(GMP_E_INVALID, "device status " + std::to_string(st));
+}
+
+// In-LDS sort size of a no-sync rebuild: the longest list of the last
+// synchronous build with headroom (1/8, at least 64 entries), so lists that
+// grow a little between rebuilds of a changing geometry still sort.
+int64_t nosync_sort_size(int64_t max_list) {
+  const int64_t extra = max_list / 8 > 64 ? max_list / 8 : 64;
+  return max_list + extra;
 }
 
 int lds_keys_for(const gmp_plan *p, int64_t maxcnt) {
@@ -655,7 +665,10 @@ gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, i
     if ((int64_t)stw[4] > lds_keys)
       return set_error(GMP_E_UNSUPPORTED, "a centre's neighbour list exceeds the in-LDS sort for this probe set");
   } else {
-    lds_keys = lds_keys_for(p, n->max_list > 0 ? n->max_list : kSortMax);
+    // the pair count is known on the device only: every later call bounds
+    // its pair range by the capacity and the device-side list ends
+    n->n_pairs = 0;
+    lds_keys = lds_keys_for(p, n->max_list > 0 ? nosync_sort_size(n->max_list) : kSortMax);
   }
   launch_fill(p, bt, nb, L, lds_keys, s);
   // the reverse index pairs mirror entries of atom-centred lists; with

@@ -235,7 +235,8 @@ class Neighbors:
         N, NT = batch.n_centres, batch.n_total  # lists per centre; wrap / rw per atom and point
         E, S = plan.n_elements, plan.n_slots
         self.capacity = int(capacity)
-        self.n_pairs = 0
+        self.n_pairs = 0   # pairs of the last synchronous build (host views of the lists)
+        self.synced = False  # False after a no-sync rebuild: the pair count is known on the device only
         self.max_list = 0  # longest list of the last synchronous build (sizes no-sync rebuilds)
         self.offsets = torch.zeros(N + 1, dtype=torch.int64, device=dev)
         self.j = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
@@ -249,7 +250,10 @@ class Neighbors:
         self.reverse = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev) if reverse else None
 
     def desc(self):
-        return _lib.NbrDesc(self.capacity, self.n_pairs, self.offsets.data_ptr(), self.j.data_ptr(),
+        # after a no-sync rebuild the count of the earlier synchronous build is
+        # stale: pass 0 (unknown), so the library bounds pair ranges by the
+        # capacity and the list ends it reads on the device
+        return _lib.NbrDesc(self.capacity, self.n_pairs if self.synced else 0, self.offsets.data_ptr(), self.j.data_ptr(),
                             self.shift.data_ptr(), self.bucket_start.data_ptr(), self.sigma_end.data_ptr(),
                             self.wrap.data_ptr(), self.rw.data_ptr(),
                             self.reverse.data_ptr() if self.reverse is not None else 0, self.max_list)
@@ -289,6 +293,7 @@ def build_neighbors(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, capacity: 
             continue
         check(st)
         nb.n_pairs = int(npairs.value)
+        nb.synced = True
         nb.max_list = int(nd.max_list)
         return nb
     raise GMPError(_lib.GMP_E_CAPACITY, "capacity retry failed")
@@ -305,6 +310,7 @@ def rebuild_neighbors_nosync(plan: GMPPlan, batch: DeviceBatch, ws: Workspace, n
     buf = ws.get(nbytes)
     bd, nd = batch.desc(), nb.desc()
     check(call(plan.handle, ctypes.byref(bd), ctypes.byref(nd), None, _ptr(buf), buf.numel(), _stream_ptr(stream)))
+    nb.synced = False
     return nb
 
 
@@ -365,7 +371,7 @@ def feature_jacobian(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Works
     of the [n_features, 3, ld] buffer the library writes; P = nb.n_pairs).
     Centres of the pairs: pair_centres(nb); neighbours: nb.j."""
     L = _lib.load()
-    ld = nb.n_pairs if nb.n_pairs > 0 else nb.capacity
+    ld = nb.n_pairs if nb.synced and nb.n_pairs > 0 else nb.capacity
     dev = batch.species.device
     buf = out if out is not None else torch.empty((plan.n_features, 3, max(ld, 1)), dtype=plan.dtype, device=dev)
     ld = buf.shape[2]
@@ -446,7 +452,10 @@ class CapturedStep:
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self._run()
-        # the graph holds raw addresses: keep every buffer it touches alive
+        # the graph holds raw addresses: keep every buffer it touches alive;
+        # the workspace buffer is the one captured (ws.buf may be replaced
+        # later by a larger eager call on the same Workspace)
+        self.ws_buf = ws.buf
         self._held = (ws.buf, nb.offsets, nb.j, nb.shift, nb.bucket_start, nb.sigma_end, nb.wrap, nb.rw,
                       nb.reverse, batch.xyz, batch.cell, batch.species, batch.atom_offsets, batch.pbc,
                       batch.occupancy, batch.point_offsets, batch.pxyz)
@@ -473,6 +482,12 @@ class CapturedStep:
 
     def replay(self):
         self.graph.replay()
+
+    def check_status(self, stream=None):
+        """Synchronize and raise on a device-side condition (list overflow,
+        a list that outgrew the sort, non-finite input) that replays recorded
+        in the captured workspace."""
+        check(_lib.load().gmp_check_status(_ptr(self.ws_buf), self.ws_buf.numel(), _stream_ptr(stream)))
 
 
 class profile:

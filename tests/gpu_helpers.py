@@ -105,3 +105,56 @@ def assert_features(F, Fref, tau, rel_tol):
     assert r <= rel_tol, f"max relative error {r:.3e} > {rel_tol:.1e}"
     assert a <= tau, f"max absolute error below threshold {a:.3e} > {tau:.1e}"
     return r, a
+
+
+def check_lists_many(nb, batch_np, probes, s, local=None):
+    """Bit-exact comparison, vectorized over many centres, of structure s's
+    lists (j, shifts, species byte, bucket starts, sigma-prefix ends, wrap
+    indices and wrapped positions) with the oracle's lists of the same
+    centres (local indices; None = every atom of the structure).  Returns
+    the number of centres checked."""
+    rc2 = oracle.cutoffs(probes)
+    E, S = probes.n_elements, oracle.n_slots(probes)
+    a0, a1 = int(batch_np.atom_offsets[s]), int(batch_np.atom_offsets[s + 1])
+    struct = batch_np.structure(s)
+    loc = np.arange(a1 - a0, dtype=np.int32) if local is None else np.asarray(local, np.int32)
+    orw, om = oracle.wrap(struct[0], struct[2], struct[3])
+    assert np.array_equal(nb.wrap.view(-1, 3)[a0:a1].cpu().numpy(), om)
+    assert nb.rw.view(3, -1)[:, a0:a1].t().contiguous().cpu().numpy().tobytes() == orw.tobytes()
+    ref = oracle.neighbors_many(struct, rc2, loc)
+    offs = nb.offsets.cpu().numpy()
+    gi = a0 + loc.astype(np.int64)
+    lo, hi = offs[gi], offs[gi + 1]
+    cnt = hi - lo
+    assert np.array_equal(cnt, np.diff(ref["offs"])), "list lengths differ"
+    idx = np.repeat(lo - ref["offs"][:-1], cnt) + np.arange(int(cnt.sum()))
+    import torch
+    it = torch.as_tensor(idx, device=nb.j.device)
+    J = nb.j[it].cpu().numpy()
+    w = nb.shift[it].cpu().numpy().view(np.uint8).reshape(-1, 4)
+    assert np.array_equal(J, ref["j"] + a0), "neighbour indices differ"
+    assert np.array_equal(w[:, :3].view(np.int8).astype(np.int32), ref["n"]), "image shifts differ"
+    assert np.array_equal(w[:, 3].astype(np.int32), ref["e"]), "species bytes differ"
+    k = len(loc)
+    owner = np.repeat(np.arange(k), cnt)
+    bucket = ref["shell"] * E + ref["e"]
+    per = np.bincount(owner * (S * E) + bucket, minlength=k * S * E).reshape(k, S * E)
+    bs_ref = np.concatenate([np.zeros((k, 1), np.int64), np.cumsum(per, axis=1)], axis=1)
+    bs = nb.bucket_start.view(-1, S * E + 1)[torch.as_tensor(gi, device=nb.j.device)].cpu().numpy()
+    assert np.array_equal(bs, bs_ref), "bucket starts differ"
+    se_ref = np.stack([np.bincount(owner, weights=(ref["q"] <= rc2[t]), minlength=k) for t in range(S)], 1)
+    se = nb.sigma_end.view(-1, S)[torch.as_tensor(gi, device=nb.j.device)].cpu().numpy()
+    assert np.array_equal(se, se_ref.astype(np.int64)), "sigma-prefix ends differ"
+    return k
+
+
+def conditioning(Fabs, Fref, tau):
+    """kappa = F_abs / F_ref per feature above the threshold (inf elsewhere):
+    F_abs is the feature of the absolute values of the pair terms, so a large
+    kappa says a feature is the small remainder of cancelling terms, whose
+    FP32 error is bounded by about 2^-24 F_abs rather than 2^-24 F_ref."""
+    Fabs = np.asarray(Fabs, np.float64)
+    out = np.full(Fref.shape, np.inf)
+    big = Fref > tau
+    out[big] = Fabs[big] / Fref[big]
+    return out

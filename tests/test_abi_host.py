@@ -6,6 +6,7 @@ import ctypes
 import json
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -128,3 +129,18 @@ def test_density_cutoff_slot_bit_exact(lib):
     assert lib.gmp_probe_cutoffs(ctypes.byref(d), rc2.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
     assert rc2.tobytes() == oracle.cutoffs(p).tobytes()
     assert rc2[2] == oracle.density_cutoff(p)
+
+
+def test_oracle_output_layout_is_the_golden_enumeration():
+    """The oracle's feature vector of an isolated dimer, position by
+    position, equals the closed forms listed in the golden enumeration's
+    order (every (order, sigma) has its own value)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import layout_dimer as ld
+    fx = ld.golden()
+    p = gs.Probes(np.array(fx["orders"], np.int32), np.array(fx["sigmas"]), np.array([0, 2], np.int32),
+                  ld.B, ld.BETA, 1e-12)
+    want = ld.expected_vector()
+    assert len(np.unique(np.round(want, 12))) == len(want)
+    F = oracle.features(ld.dimer_structure(), p)[0]
+    assert np.allclose(F, want, rtol=1e-13, atol=0)

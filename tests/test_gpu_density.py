@@ -4,7 +4,7 @@ on the HIP path vs the FP64 oracle, through the C ABI.
 Same bars as the other parity tests: neighbour lists (now with the density
 cutoff slot) bit-exact; features within 1e-11 (FP64) or 1e-5 (FP32 modes)
 relative above the threshold, tau absolute below; gradients norm-wise per
-structure within 1e-9 (FP64) or 1e-5 (FP32 modes).
+structure within 1e-11 (FP64) or 1e-5 (FP32 modes).
 """
 import numpy as np
 import pytest
@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 TOL = {"fp64": 1e-11, "fp32c": 1e-5, "fp32w": 1e-5}
-GTOL = {"fp64": 1e-9, "fp32c": 1e-5, "fp32w": 1e-5}
+GTOL = {"fp64": 1e-11, "fp32c": 1e-5, "fp32w": 1e-5}
 
 
 @pytest.fixture(scope="module")

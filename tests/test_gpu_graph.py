@@ -181,3 +181,88 @@ def test_jacobian_after_nosync_rebuild(g):
     torch.cuda.synchronize()
     assert torch.equal(out[:, :, :P].permute(2, 0, 1), J0)
     assert bool(torch.isnan(out[:, :, P:]).all())  # entries past the lists are not written
+
+
+def _scale_geometry(db, f):
+    """Shrink (f < 1) or stretch the whole batch in place: positions, cells
+    and reference points scale together, so distances scale by f."""
+    db.xyz.mul_(f)
+    db.cell.mul_(f)
+    if db.pxyz is not None:
+        db.pxyz.mul_(f)
+
+
+@pytest.mark.parametrize("points,split", [(False, False), (False, True), (True, False)])
+def test_graph_replay_growing_pair_count(g, points, split):
+    """Replays after the geometry shrinks by 2% find strictly more pairs than
+    the synchronous build before capture (within the capacity): every
+    kernel must bound its pair range by the device-side list ends, not by
+    the count of the earlier build.  Compared bitwise with eager launches on
+    the new geometry (atoms as centres with the reverse search on one or two
+    streams; reference points with the by-neighbour sort)."""
+    say(f"[graph replay, growing pair count, points={points} split={split}]")
+    rng = np.random.default_rng(21)
+    b, probes = _batch(23)
+    db = g.DeviceBatch.from_batch(b)
+    if points:
+        pts, po = [], [0]
+        for s in range(b.n_structs):
+            pos, _, cell, pbc = b.structure(s)
+            q = rng.uniform(0, 1, (5, 3)) @ cell if pbc else rng.normal(size=(5, 3)) * 2.0
+            pts.append(q)
+            po.append(po[-1] + 5)
+        db = db.with_points(np.concatenate(pts), po)
+    plan = g.GMPPlan.from_probes(probes, "fp64")
+    ws = g.Workspace()
+    G = torch.as_tensor(rng.standard_normal((db.n_centres, probes.n_features)), device="cuda")
+    nb0 = g.build_neighbors(plan, db, ws)
+    nbc = g.build_neighbors(plan, db, ws, capacity=3 * nb0.n_pairs + 1024)
+    step = g.CapturedStep(plan, db, ws, nbc, backward=True, G=G, concurrent_reverse=split)
+    step.replay()
+    torch.cuda.synchronize()
+    _scale_geometry(db, 0.98)
+    step.replay()
+    torch.cuda.synchronize()
+    step.check_status()
+    nb1, F1, mu1, gp1, gc1 = _eager(g, plan, db, g.Workspace(), G)
+    say(f"  pairs {nb0.n_pairs} -> {nb1.n_pairs}, capacity {nbc.capacity}")
+    assert nb0.n_pairs < nb1.n_pairs <= nbc.capacity
+    assert _same(step.F, F1) and _same(step.mu, mu1)
+    assert _same(step.gpos, gp1) and _same(step.gcell, gc1)
+
+
+def test_nosync_list_outgrowing_the_sort_is_reported(g):
+    """A no-sync rebuild sizes its in-LDS sort from the longest list of the
+    last synchronous build plus headroom (1/8, at least 64 entries).  A list
+    that grows beyond that is reported as GMP_E_STALE by the captured step's
+    own status word, and a synchronous rebuild then gives the exact lists."""
+    b, probes = _batch(29)
+    plan = g.GMPPlan.from_probes(probes, "fp64")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb0 = g.build_neighbors(plan, db, ws)
+    nbc = g.build_neighbors(plan, db, ws, capacity=6 * nb0.n_pairs + 4096)
+    step = g.CapturedStep(plan, db, ws, nbc, backward=False)
+    step.replay()
+    step.check_status()
+    # a small growth stays within the headroom
+    _scale_geometry(db, 0.99)
+    step.replay()
+    step.check_status()
+    nb1 = g.build_neighbors(plan, db, g.Workspace())
+    assert nb1.max_list > nb0.max_list
+    # a large one does not: reported, not silently wrong
+    _scale_geometry(db, 0.8)
+    nb2 = g.build_neighbors(plan, db, g.Workspace())
+    assert nb2.max_list > nb0.max_list + max(64, nb0.max_list // 8)
+    assert nb2.n_pairs <= nbc.capacity
+    step.replay()
+    with pytest.raises(g.GMPError) as ei:
+        step.check_status()
+    assert ei.value.status == 8  # GMP_E_STALE
+    # the synchronous build re-sizes the sort: features equal a fresh build's
+    nbs = g.build_neighbors(plan, db, ws, out=nbc)
+    F, _ = g.features(plan, db, nbs, ws)
+    F2, _ = g.features(plan, db, nb2, g.Workspace())
+    torch.cuda.synchronize()
+    assert _same(F, F2)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 TOL = {"fp64": 1e-11, "fp32c": 1e-5, "fp32w": 1e-5}
-GTOL = {"fp64": 1e-9, "fp32c": 1e-5, "fp32w": 1e-5}
+GTOL = {"fp64": 1e-11, "fp32c": 1e-5, "fp32w": 1e-5}
 
 
 @pytest.fixture(scope="module")

@@ -5,7 +5,7 @@ boundaries, wrap indices, wrapped coordinates).
 Features: the overlap-threshold rule -- relative error <= 1e-11 (FP64 path)
 or <= 1e-5 (FP32 compensated path) where the oracle feature exceeds the
 threshold tau, absolute error <= tau elsewhere.
-Gradients: max |g - g_ref| <= tol * max |g_ref| per structure, tol 1e-9
+Gradients: max |g - g_ref| <= tol * max |g_ref| per structure, tol 1e-11
 (FP64) / 1e-5 (FP32 compensated).
 """
 import numpy as np
@@ -115,7 +115,7 @@ def test_tunings_do_not_change_lists_or_features(g, ws, c1, bin_divisor, blocks,
     assert_features(F.cpu().numpy(), Fref, p.tau, 1e-11 if precision == "fp64" else 1e-5)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32c", 1e-5), ("fp32w", 1e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32c", 1e-5), ("fp32w", 1e-5)])
 def test_backward_vs_oracle(g, ws, precision, tol):
     rng = np.random.default_rng(17)
     structs = [gs.small_periodic(rng, n_atoms=12, n_elements=2, density=0.06, dmin=1.3),
