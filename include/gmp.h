@@ -257,6 +257,24 @@ gmp_status gmp_features(const gmp_plan *plan, const gmp_batch *batch, const gmp_
                         void *features, double *components, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* gmp_features without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the forward's scratch (partial moments
+ * per work item, chunk offsets, packed positions, the work-item counter) is
+ * a fixed array of GMP_NOALLOC_SCRATCH_BYTES in device memory that the
+ * library holds on every GPU it runs on until the process ends.  Same
+ * arguments, results (bitwise) and status codes as gmp_features, plus
+ * GMP_E_NOMEM when the batch needs more scratch than the array holds
+ * (about 8 S (l_max+1)(l_max+2)(l_max+3)/6 bytes per work item, i.e. per
+ * centre and per chunk_pairs pairs, plus ~100 bytes per atom; the message
+ * names both sizes).  Nothing is allocated.  Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (concurrent
+ * streams, several host threads) race and must be serialized by the
+ * caller. */
+#define GMP_NOALLOC_SCRATCH_BYTES (64u << 20)
+gmp_status gmp_features_noalloc(const gmp_plan *plan, const gmp_batch *batch, const gmp_neighbors *nbrs,
+                                void *features, double *components, void *stream);
+
 /* Adjoint: given G = dL/dF [n_centres * n_features] (same type as features),
  * writes grad_pos [3 * n_total] (FP64, SoA: x block, y block, z block; each
  * block the atoms, then the reference points) and, when grad_cell is not

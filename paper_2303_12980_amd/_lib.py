@@ -22,7 +22,7 @@ GMP_FP64, GMP_FP32_COMPENSATED, GMP_FP32_WIDE = 0, 1, 2
 EXPORTS = (
     "gmp_probe_cutoffs", "gmp_plan_create", "gmp_plan_destroy", "gmp_plan_info", "gmp_plan_get_tuning", "gmp_plan_set_tuning",
     "gmp_workspace_size", "gmp_build_neighbors", "gmp_build_lists", "gmp_build_reverse", "gmp_features",
-    "gmp_features_backward", "gmp_feature_jacobian",
+    "gmp_features_noalloc", "gmp_features_backward", "gmp_feature_jacobian",
     "gmp_check_status", "gmp_profile_begin", "gmp_profile_end", "gmp_last_error",
 )
 
@@ -92,6 +92,8 @@ def load():
     L.gmp_features.argtypes = [c_vp, ctypes.POINTER(BatchDesc), ctypes.POINTER(NbrDesc), c_vp, c_vp, c_vp,
                                ctypes.c_size_t, c_vp]
     L.gmp_features.restype = c_i32
+    L.gmp_features_noalloc.argtypes = [c_vp, ctypes.POINTER(BatchDesc), ctypes.POINTER(NbrDesc), c_vp, c_vp, c_vp]
+    L.gmp_features_noalloc.restype = c_i32
     L.gmp_features_backward.argtypes = [c_vp, ctypes.POINTER(BatchDesc), ctypes.POINTER(NbrDesc), c_vp, c_vp,
                                         c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
     L.gmp_features_backward.restype = c_i32

@@ -27,6 +27,7 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
                     int32_t *astruct, int64_t pairs_bound, hipStream_t s);
 void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off, void *features,
                    double *components, hipStream_t s);
+void *noalloc_scratch(size_t *bytes, hipError_t *err);
 size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms);
 void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const double *components,
                      const void *grad_features, double *grad_pos, double *grad_cell, const WsLayout &L, int C,
@@ -742,6 +743,43 @@ gmp_status gmp_features(const gmp_plan *p, const gmp_batch *b, const gmp_neighbo
   launch_overlap(p, bt, nb, L.partial, L.nch, L.chunk_off, L.scan_aux, L.counter, L.rw4, L.astruct, pairs, s);
   launch_finish(p, N, L.partial, L.chunk_off, features, components, s);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(e, "feature kernels");
+  return GMP_OK;
+}
+
+gmp_status gmp_features_noalloc(const gmp_plan *p, const gmp_batch *b, const gmp_neighbors *n, void *features,
+                                double *components, void *stream) {
+  gmp_status st = check_batch(p, b);
+  if (st) return st;
+  st = check_nbrs(p, b, n, true);
+  if (st) return st;
+  const int64_t N = batch_centres(b);
+  if (N == 0) return GMP_OK;
+  if (!features) return set_error(GMP_E_INVALID, "null features");
+  hipError_t e = hipSuccess;
+  size_t cap = 0;
+  void *base = noalloc_scratch(&cap, &e);
+  if (!base) return hip_error(e, "scratch array address");
+  // the forward's scratch: partial moments per work item, chunk counts and
+  // offsets, scan carries, the work-item counter, packed positions and
+  // structure indices
+  const int64_t NC = N, NT = b->n_atoms + batch_points(b);
+  const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
+  Carver c(base, cap);
+  double *partial = c.take<double>((size_t)max_chunks(p, NC, pairs) * p->dev.S * nmono(p->dev.lmax));
+  int64_t *nch = c.take<int64_t>(NC);
+  int64_t *chunk_off = c.take<int64_t>(NC + 1);
+  int64_t *scan_aux = c.take<int64_t>(scan_aux_size(NC));
+  unsigned long long *counter = c.take<unsigned long long>(32);
+  double4 *rw4 = c.take<double4>(NT);
+  int32_t *astruct = c.take<int32_t>(NT);
+  if (c.off > cap)
+    return set_error(GMP_E_NOMEM, "gmp_features_noalloc needs " + std::to_string(c.off) +
+                                      " bytes of scratch; its fixed array holds " + std::to_string(cap));
+  hipStream_t s = (hipStream_t)stream;
+  launch_overlap(p, to_dev(b), to_dev(n), partial, nch, chunk_off, scan_aux, counter, rw4, astruct, pairs, s);
+  launch_finish(p, N, partial, chunk_off, features, components, s);
+  e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "feature kernels");
   return GMP_OK;
 }

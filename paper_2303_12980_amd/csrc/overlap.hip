@@ -487,6 +487,34 @@ template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb, bool 
 
 }  // namespace
 
+// Scratch memory of gmp_features_noalloc: a fixed array in device memory
+// (each GPU the library runs on holds its own copy until the process ends).
+// Host code never passes the array's name to a kernel: it takes the device
+// address from hipGetSymbolAddress once per device and passes that.
+constexpr size_t kNoallocScratchBytes = (size_t)GMP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+// Device address of this GPU's scratch array (looked up on the first call on
+// each device, with that device current), or null with *err set.
+void *noalloc_scratch(size_t *bytes, hipError_t *err) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDev] = {};
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= kMaxDev) { *err = hipErrorInvalidDevice; return nullptr; }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    addr[dev] = ptr;
+  }
+  *bytes = kNoallocScratchBytes;
+  return addr[dev];
+}
+
 int chunk_size(const gmp_plan *p) { return p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 0; }
 
 // upper bound on the number of chunks of a batch with at most `pairs` pairs
