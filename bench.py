@@ -400,12 +400,21 @@ def batched_vs_per_structure(g, gs, torch):
     }
 
 
+# monomial terms of the solid harmonics of each order with r^2 expanded
+# (1, 3, 12, 28, 63 for l = 0..4): the per-pair polynomial work of the cost model
+POLY_TERMS = {0: 1, 1: 3, 2: 12, 3: 28, 4: 63}
+
+
 def algorithmic_counts(nb, probes, rc2):
-    """Per-launch algorithmic work of the overlap kernel, from the lists:
-    per pair, the monomials of degree >= 2 up to l_max (one multiply each)
-    and q (5 flops); per (pair, active sigma), per primitive one multiply,
-    one exp and one multiply-add per order for the radial sums, and one
-    multiply-add per requested component for the accumulation."""
+    """Per-launch algorithmic work of the overlap kernel, from the lists, as
+    the cost model counts it: per pair, q (5 flops) and the polynomials
+    (2 flops per monomial term of every requested order, r^2 expanded); per
+    (pair, active sigma) and primitive, one multiply for the exponent and a
+    multiply-add per order for the radial factors (the exponential itself is
+    counted separately against the transcendental rate); per (pair, active
+    sigma), a multiply-add per requested component for the accumulation.
+    `executed_alg` is the smaller count of the operations the recursion
+    actually needs (q, one multiply per monomial of degree >= 2)."""
     E, S = probes.n_elements, len(probes.sigmas)
     offs = nb.offsets.cpu().numpy()
     bs = nb.bucket_start.cpu().numpy().reshape(-1, S * E + 1).astype(np.int64)
@@ -413,15 +422,68 @@ def algorithmic_counts(nb, probes, rc2):
     rank = np.array([int(np.sum(rc2 < rc2[s])) for s in range(S)])
     active = np.cumsum(sizes, axis=1)[:, rank, :]          # [N, sigma, species] pairs each sigma uses
     K = np.diff(probes.prim_offsets).astype(np.int64)      # primitives per element
-    L = np.asarray(probes.orders)
-    lmax = int(L.max())
+    L = [int(l) for l in probes.orders]
+    lmax = max(L)
     ncomp = int(sum((l + 1) * (l + 2) // 2 for l in L))
+    terms = int(sum(POLY_TERMS[l] for l in L))
     nmono_hi = (lmax + 1) * (lmax + 2) * (lmax + 3) // 6 - 4 if lmax >= 2 else 0
     pairs = int(offs[-1])
     pair_sigma = int(active.sum())
     exps = int((active.sum(axis=(0, 1)) * K).sum())
-    flops = pairs * (5 + nmono_hi) + exps * (2 + 2 * len(L)) + pair_sigma * 2 * ncomp
-    return dict(pairs=pairs, pair_sigma=pair_sigma, exps=exps, flops=flops)
+    flops = pairs * (5 + 2 * terms) + exps * (1 + 2 * len(L)) + pair_sigma * 2 * ncomp
+    executed_alg = pairs * (5 + nmono_hi) + exps * (2 + 2 * len(L)) + pair_sigma * 2 * ncomp
+    return dict(pairs=pairs, pair_sigma=pair_sigma, exps=exps, flops=flops, executed_alg=executed_alg,
+                per_pair=5 + 2 * terms, per_exp=1 + 2 * len(L), per_pair_sigma=2 * ncomp)
+
+
+def list_bytes(nb, n_centres, n_slots, n_elements):
+    """Algorithmic bytes the neighbour build writes: per pair the neighbour
+    index, the packed shift and the reverse index (12 B); per centre the list
+    offset (8 B), the bucket starts (4 (S E + 1) B) and the prefix ends (4 S B)."""
+    return int(nb.n_pairs) * 12 + n_centres * (8 + 4 * (n_slots * n_elements + 1) + 4 * n_slots)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(oracle, batch, probes, n_features):
+    """The oracle's forward (brute-force neighbours + closed-form overlaps,
+    OpenMP over centres), median of 3 runs: on every available core over all
+    centres of the workload, and on one core over a 256-centre sample."""
+    avail = len(os.sched_getaffinity(0))
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", "0")) or avail, avail)
+    N = batch.n_atoms
+    struct = batch.structure(0)
+    prev = oracle.set_threads(threads)
+
+    def med(fn):
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+    t_all = med(lambda: oracle.features(struct, probes))
+    oracle.set_threads(1)
+    sample = np.sort(np.random.default_rng(31).choice(N, size=min(256, N), replace=False))
+    t_one = med(lambda: oracle.features(struct, probes, centres=sample))
+    oracle.set_threads(prev)
+    return {"value": N * n_features / t_all, "unit": "atoms*features/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle forward (brute-force neighbours + closed-form overlaps) over all {N} centres "
+                      f"of the workload on {threads} OpenMP threads, median of 3 runs ({t_all:.2f} s); forward "
+                      f"only",
+            "single_core": {"value": len(sample) * n_features / t_one, "unit": "atoms*features/s", "cores": 1,
+                            "sample": f"{len(sample)} sampled centres of the same workload, median of 3 runs "
+                                      f"({t_one:.2f} s)"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": avail}
 
 
 def main():
@@ -530,8 +592,15 @@ def main():
     ov = kern["overlap"]
     achieved = counts["flops"] / (ov["avg_ms"] * 1e-3) / 1e12
     rec = counter_record("overlap")
+    h3_ms = sum(kern[k]["avg_ms"] for k in ("nbr_count", "nbr_fill_sort", "nbr_reverse") if k in kern)
+    h3_bytes = list_bytes(nb32, N, plan32.n_slots, probes.n_elements)
     roofline = {"kernel": "overlap", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "flop_count": {"per_pair": counts["per_pair"], "per_primitive_exp": counts["per_exp"],
+                               "per_pair_sigma": counts["per_pair_sigma"], "pairs": counts["pairs"],
+                               "primitive_exps": counts["exps"], "pair_sigmas": counts["pair_sigma"]},
+                "executed_alg": {"flops_per_launch": counts["executed_alg"],
+                                 "tflops": round(counts["executed_alg"] / (ov["avg_ms"] * 1e-3) / 1e12, 3)},
                 "peak_nonpacked_fp32": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
                 "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                 "traffic": rec["hbm_bytes_per_launch"] if rec else None,
@@ -541,7 +610,10 @@ def main():
                 "exp_rate_per_s": counts["exps"] / (ov["avg_ms"] * 1e-3),
                 "exp_frac": counts["exps"] / (ov["avg_ms"] * 1e-3) / PEAK_EXP_PER_S,
                 "algorithmic_flops_per_launch": counts["flops"], "avg_launch_ms": ov["avg_ms"],
-                "dominant_kernel_of_step": dom}
+                "dominant_kernel_of_step": dom,
+                "h3": {"kernels": "nbr_count + nbr_fill_sort + nbr_reverse", "ms": round(h3_ms, 5),
+                       "algorithmic_bytes": h3_bytes, "GBps": round(h3_bytes / (h3_ms * 1e-3) / 1e9, 1),
+                       "frac_hbm": round(h3_bytes / (h3_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}}
 
     # accuracy on sampled centres vs the FP64 oracle (outputs of the last graph replays)
     import oracle
@@ -549,23 +621,18 @@ def main():
     cs = np.sort(rng.choice(N, size=min(args.sample_centres, N), replace=False))
     Fref = oracle.features(batch.structure(0), probes, centres=cs)
     big = Fref > probes.tau
-    acc = {"sampled_centres": int(len(cs)), "rule": "max |F-F_ref|/F_ref over F_ref > tau"}
+    Fabs = oracle.features_abs(batch.structure(0), probes, centres=cs)
+    kappa = Fabs[big] / Fref[big]
+    acc = {"sampled_centres": int(len(cs)), "rule": "max |F-F_ref|/F_ref over F_ref > tau",
+           "kappa": {"definition": "F_abs / F_ref, F_abs the feature of the absolute pair terms",
+                     "max": float(kappa.max()), "median": float(np.median(kappa))}}
     for prec, (_, _, _, st, _) in graphs.items():
         Fg = st.F.double().cpu().numpy()[cs]
         acc[f"{prec}_max_rel_err"] = float(np.max(np.abs(Fg[big] - Fref[big]) / Fref[big]))
+        acc[f"{prec}_max_err_over_2^-24_Fabs"] = float(np.max(np.abs(Fg - Fref) / (2.0 ** -24 * Fabs)))
 
-    # CPU baseline: the oracle, forward, over every centre of the workload
-    cpu = None
-    if not args.no_cpu_baseline:
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        threads = min(threads, len(os.sched_getaffinity(0)))
-        t = time.perf_counter()
-        oracle.features(batch.structure(0), probes)
-        dt = time.perf_counter() - t
-        cpu = {"value": N * nf / dt, "unit": "atoms*features/s", "cores": threads, "kind": "oracle",
-               "sample": f"FP64 oracle forward (brute-force neighbours + closed-form overlaps) over all {N} "
-                         f"centres of the workload, {dt:.1f} s wall on {threads} OpenMP threads; forward only "
-                         f"(the oracle's analytic gradient is not timed)"}
+    # CPU baseline: the oracle, forward (all cores over every centre; one core on a sample)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, batch, probes, nf)
 
     atoms_feat = N * nf
     value = atoms_feat / dt_fb

@@ -68,6 +68,8 @@ def lib():
             L.oracle_features.restype = c_int
             L.oracle_grad.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, dp, dp, dp, dp, dp]
             L.oracle_grad.restype = c_int
+            L.oracle_set_threads.argtypes = [c_int]
+            L.oracle_set_threads.restype = c_int
             L.oracle_features_abs.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp]
             L.oracle_features_abs.restype = c_int
             L.oracle_grad_centres.argtypes = [c_int, dp, ip, dp, c_int, *probe_args, c_int, ip, dp, dp, dp, dp]
@@ -209,6 +211,11 @@ def neighbors(struct, rc2, centre: int):
             return dict(j=j[:cnt], n=n[:cnt], q=q[:cnt], shell=sh[:cnt],
                         e=np.asarray(spec)[j[:cnt]])
         cap = int(cnt)
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's loops over centres; returns the previous count."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def neighbors_many(struct, rc2, centres):

@@ -63,6 +63,7 @@
  * The derivative of c(q) P(d) is taken with forward-mode dual numbers.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1161,4 +1162,12 @@ void oracle_radial(int l, double sigma, int n_prims, const double *B, const doub
     }
     out[p] = acc;
   }
+}
+
+/* Threads of the parallel loops over centres (timing of the CPU baseline on
+ * one core and on all cores); returns the previous setting. */
+int oracle_set_threads(int n) {
+  int prev = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return prev;
 }
