@@ -315,6 +315,65 @@ def screening_variant(g, gs, torch, batch, probes, db, steps=10, warmup=3):
     return out
 
 
+def tabulated_variant(g, gs, torch, batch, probes, db, steps=10, warmup=3, intervals=2048):
+    """Tabulated radial factors (cubic Hermite tables in r = sqrt(q),
+    `intervals` per slot and element) on the 4096-atom cell: graph-replayed
+    fwd+bwd and fwd steps in FP32 compensated mode, the overlap kernel beside
+    the exact one, the FP64 oracle on sampled centres; and the overlap of both
+    on the same cell with 16 primitives per element (where the table's fixed
+    cost per pair meets the exponentials' cost per primitive)."""
+    import oracle
+    pt = gs.Probes(probes.orders, probes.sigmas, probes.prim_offsets, probes.B, probes.beta, probes.tau,
+                   radial_intervals=intervals)
+    N, nf = batch.n_atoms, pt.n_features
+    plan = g.GMPPlan.from_probes(pt, "fp32c")
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    nbf = g.build_neighbors(plan, db, ws, reverse=False)
+    G = torch.as_tensor(np.random.default_rng(7).standard_normal((N, nf)), device="cuda")
+    fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
+    fo = g.CapturedStep(plan, db, ws, nbf, backward=False)
+    for _ in range(warmup):
+        fb.replay()
+        fo.replay()
+    t_fb = _median_ms(fb.replay, steps, torch)
+    t_fo = _median_ms(fo.replay, steps, torch)
+    fb.check_status()
+    cs = np.sort(np.random.default_rng(37).choice(N, size=24, replace=False))
+    Fref = oracle.features(batch.structure(0), probes, centres=cs)
+    Fg = fb.F.double().cpu().numpy()[cs]
+    big = Fref > probes.tau
+
+    def overlap_ms(p, prec):
+        pl = g.GMPPlan.from_probes(p, prec)
+        w = g.Workspace()
+        n2 = g.build_neighbors(pl, db, w, reverse=False)
+        g.features(pl, db, n2, w)
+        torch.cuda.synchronize()
+        with g.profile() as pr:
+            for _ in range(5):
+                g.features(pl, db, n2, w)
+            torch.cuda.synchronize()
+        return pr.result["overlap"][1] / pr.result["overlap"][0]
+    rng = np.random.default_rng(5)
+    o16, B16, b16 = gs.density_tables(rng, probes.n_elements, 16, (0.01, 10.0), (0.1, 30.0))
+    kern = {}
+    for label, (po, B, be) in (("5_primitives", (probes.prim_offsets, probes.B, probes.beta)),
+                               ("16_primitives", (o16, B16, b16))):
+        for nint in (0, intervals):
+            pp = gs.Probes(probes.orders, probes.sigmas, po, B, be, probes.tau, radial_intervals=nint)
+            kern[f"{label}_{'tabulated' if nint else 'exact'}_ms"] = {
+                prec: round(overlap_ms(pp, prec), 4) for prec in ("fp32c", "fp32w")}
+    out = {"intervals_per_slot_and_element": intervals, "fwd_bwd_ms": t_fb, "fwd_ms": t_fo,
+           "atoms_features_per_s_fwd_bwd": N * nf / (t_fb * 1e-3),
+           "max_rel_err_vs_exact_oracle": float(np.max(np.abs(Fg[big] - Fref[big]) / Fref[big])),
+           "sampled_centres": len(cs), "overlap_kernel": kern}
+    print(f"[bench] tabulated radial: fwd+bwd {t_fb:.3f} ms, overlap {kern}", file=sys.stderr, flush=True)
+    del fb, fo, nb, nbf, ws, G
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_vs_per_structure(g, gs, torch):
     """2048 structures of 8-256 atoms (half periodic triclinic, half
     clusters), FP32 compensated forward (neighbour build + overlap + norm):
@@ -669,6 +728,7 @@ def main():
         out["points_variant"] = points_variant(g, gs, torch, batch, probes)
         out["jacobian"] = jacobian_variant(g, gs, torch, batch, probes, db)
         out["screening_variant"] = screening_variant(g, gs, torch, batch, probes, db)
+        out["tabulated_variant"] = tabulated_variant(g, gs, torch, batch, probes, db)
     if not args.no_batched:
         del graphs, plan32, nb32, step32
         torch.cuda.empty_cache()

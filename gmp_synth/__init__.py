@@ -42,6 +42,8 @@ class Probes:
     tau:           overlap threshold (sets the cutoff per sigma)
     screening:     per-primitive screening (each primitive only inside its
                    own threshold radius), a variant of the cutoff rule
+    radial_intervals: 0, or the interval count of tabulated radial factors
+                   (a speed variant of the HIP path's forward)
     """
     orders: np.ndarray
     sigmas: np.ndarray
@@ -50,6 +52,7 @@ class Probes:
     beta: np.ndarray
     tau: float
     screening: bool = False
+    radial_intervals: int = 0
 
     @property
     def n_elements(self) -> int:

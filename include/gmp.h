@@ -99,6 +99,16 @@ typedef struct {
                                     l = 0 overlap reaches tau, (float)q <= (float)(ln(|A0|/tau)/gamma)
                                     (never when |A0| <= tau; density slot: A0 = B, gamma = beta); each
                                     skipped radial term is below tau */
+  int32_t radial_intervals;      /* 0: the radial factors c_{l,s,e}(q) = sum_k A exp(-gamma q) are
+                                    evaluated exactly.  16..65536 (FP32 precisions, no screening):
+                                    a faster variant for elements with many primitives, the
+                                    forward reads c from a table instead: per (slot, element,
+                                    order) a cubic Hermite interpolant of c in r = sqrt(q) on
+                                    radial_intervals equal intervals of [0, rc(slot)], whose
+                                    error is at most h^4/32 sum_k gamma_k^2 |A_k| (h the interval
+                                    width; the fourth r-derivative of exp(-gamma r^2) is at most
+                                    12 gamma^2); the adjoint and the Jacobian keep the exact
+                                    factors */
 } gmp_probe_desc;
 
 /* A packed batch of structures (CSR over atoms); mirrors the featurizer's

@@ -30,7 +30,7 @@ EXPORTS = (
 class ProbeDesc(ctypes.Structure):
     _fields_ = [("n_orders", c_i32), ("orders", P_i32), ("n_sigmas", c_i32), ("sigmas", P_dbl),
                 ("n_elements", c_i32), ("prim_offsets", P_i32), ("B", P_dbl), ("beta", P_dbl),
-                ("overlap_threshold", c_dbl), ("screening", c_i32)]
+                ("overlap_threshold", c_dbl), ("screening", c_i32), ("radial_intervals", c_i32)]
 
 
 class BatchDesc(ctypes.Structure):

@@ -232,6 +232,10 @@ static gmp_status validate_desc(const gmp_probe_desc *d, int *mask_out, int *kma
   if (!(d->overlap_threshold > 0.0) || !isfinite(d->overlap_threshold))
     return set_error(GMP_E_INVALID, "overlap_threshold must be positive and finite");
   if (d->screening != 0 && d->screening != 1) return set_error(GMP_E_INVALID, "screening must be 0 or 1");
+  if (d->radial_intervals != 0 && (d->radial_intervals < 16 || d->radial_intervals > 65536))
+    return set_error(GMP_E_INVALID, "radial_intervals must be 0 or 16..65536");
+  if (d->radial_intervals != 0 && d->screening != 0)
+    return set_error(GMP_E_UNSUPPORTED, "tabulated radial factors with per-primitive screening");
   int mask = 0, dens = 0;
   for (int o = 0; o < d->n_orders; ++o) {
     int l = d->orders[o];
@@ -320,6 +324,10 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   int mask = 0, kmax = 1, dens = 0;
   gmp_status vst = validate_desc(d, &mask, &kmax, &dens);
   if (vst) return vst;
+  if (d->radial_intervals != 0 && precision == GMP_FP64)
+    return set_error(GMP_E_UNSUPPORTED, "tabulated radial factors are an FP32 variant");
+  if ((size_t)(d->n_sigmas + dens) * d->n_elements * d->radial_intervals * 80 > (size_t(512) << 20))
+    return set_error(GMP_E_UNSUPPORTED, "radial table larger than 512 MB");
 
   gmp_plan *p = new gmp_plan();
   memset(&p->dev, 0, sizeof(p->dev));
@@ -445,13 +453,66 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   }
   std::vector<int> kc(p->E);
   for (int e = 0; e < p->E; ++e) kc[e] = d->prim_offsets[e + 1] - d->prim_offsets[e];
+  // tabulated radial factors: per (slot, element) and interval [r_k, r_k+1]
+  // of r = sqrt(q), the cubic Hermite interpolant of every c_l from its values
+  // and r-derivatives at both ends, as coefficients of t = (r - r_k) / h
+  const int NTb = d->radial_intervals;
+  P.tab_n = NTb;
+  std::vector<float> rt((size_t)p->S * p->E * NTb * 5 * 4, 0.0f);
+  for (int s = 0; s < p->S && NTb > 0; ++s) {
+    const double rc = sqrt(p->rc2[s] > 0.0 ? p->rc2[s] : 0.0);
+    const double h = rc > 0.0 ? rc / NTb : 1.0;
+    P.tab_inv_h[s] = (float)(1.0 / h);
+    const bool dslot = s == P.dens_slot;
+    const double alpha = dslot ? 0.0 : 1.0 / (2.0 * p->sigmas[s] * p->sigmas[s]);
+    for (int e = 0; e < p->E; ++e) {
+      // value and r-derivative of c_l at r
+      auto eval = [&](double r, double *f, double *df) {
+        for (int l = 0; l <= kMaxL; ++l) { f[l] = 0.0; df[l] = 0.0; }
+        for (int k = d->prim_offsets[e]; k < d->prim_offsets[e + 1]; ++k) {
+          const double beta = d->beta[k];
+          double gam, A0, ratio;
+          if (dslot) { gam = beta; A0 = d->B[k]; ratio = 0.0; }
+          else {
+            const double lam = alpha + beta;
+            gam = alpha * beta / lam;
+            A0 = d->B[k] * pow(alpha / lam, 1.5);
+            ratio = beta / lam;
+          }
+          const double ex = exp(-gam * r * r);
+          double A = A0;
+          for (int l = 0; l <= (dslot ? 0 : kMaxL); ++l) {
+            f[l] += A * ex;
+            df[l] += -2.0 * gam * r * A * ex;
+            A *= ratio;
+          }
+        }
+      };
+      double f0[kMaxL + 1], d0[kMaxL + 1], f1[kMaxL + 1], d1[kMaxL + 1];
+      eval(0.0, f0, d0);
+      for (int k = 0; k < NTb; ++k) {
+        eval((k + 1) * h, f1, d1);
+        for (int l = 0; l <= kMaxL; ++l) {
+          const size_t o = ((((size_t)s * p->E + e) * NTb + k) * 5 + l) * 4;
+          rt[o] = (float)f0[l];
+          rt[o + 1] = (float)(h * d0[l]);
+          rt[o + 2] = (float)(3.0 * (f1[l] - f0[l]) - h * (2.0 * d0[l] + d1[l]));
+          rt[o + 3] = (float)(2.0 * (f0[l] - f1[l]) + h * (d0[l] + d1[l]));
+          f0[l] = f1[l];
+          d0[l] = d1[l];
+        }
+      }
+    }
+  }
 
   const size_t b32 = c32.size() * sizeof(float), b64 = c64.size() * sizeof(double);
   const size_t bT = T.size() * sizeof(double), bk = kc.size() * sizeof(int);
+  const size_t brt = rt.size() * sizeof(float);
   const size_t o64 = (b32 + 255) & ~size_t(255);
   const size_t oT = (o64 + b64 + 255) & ~size_t(255);
   const size_t ok = (oT + bT + 255) & ~size_t(255);
-  const size_t total = ok + bk;
+  const size_t ort = (ok + bk + 255) & ~size_t(255);
+  const size_t total = ort + brt;
   hipError_t e = hipMalloc(&p->dmem, total);
   if (e != hipSuccess) { delete p; return hip_error(e, "hipMalloc(plan tables)"); }
   char *base = (char *)p->dmem;
@@ -459,11 +520,13 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   if (e == hipSuccess) e = hipMemcpy(base + o64, c64.data(), b64, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(base + oT, T.data(), bT, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(base + ok, kc.data(), bk, hipMemcpyHostToDevice);
+  if (e == hipSuccess && brt > 0) e = hipMemcpy(base + ort, rt.data(), brt, hipMemcpyHostToDevice);
   if (e != hipSuccess) { (void)hipFree(p->dmem); delete p; return hip_error(e, "hipMemcpy(plan tables)"); }
   P.coef32 = (const float *)base;
   P.coef64 = (const double *)(base + o64);
   P.T = (const double *)(base + oT);
   P.kcount = (const int *)(base + ok);
+  P.rtab = brt > 0 ? (const float4 *)(base + ort) : nullptr;
   p->tuning.chunk_pairs = 2048;
   p->tuning.bin_divisor = 2;
   p->tuning.blocks_per_cu = 0;

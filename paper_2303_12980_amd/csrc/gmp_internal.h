@@ -104,6 +104,9 @@ struct PlanDev {
   int S, E, n_orders, lmax, order_mask, kmax, kb, nf, ncomp_total;  // kb: primitive stride of the tables (4/8/16)
   int n_sig, dens_slot, dens_order;  // sigmas, density slot, index of order -1 in orders (-1: none)
   int screen;                        // per-primitive screening (radius^2 in column 7 of the tables, FP32 value)
+  int tab_n;                         // tabulated radial factors: intervals per (slot, element) (0: exact)
+  float tab_inv_h[kMaxSigmas];       // 1 / interval width (in r = sqrt(q)) of every slot's table
+  const float4 *rtab;                // [S][E][tab_n][5]: cubic coefficients in t of c_l, l = 0..4
   int orders[kMaxOrders];
   int comp_off[kMaxOrders];       // offset of order o's (sigma, component) block in one centre's components
   int feat_off[kMaxOrders];       // first feature of order o (n_sig features per order, 1 for order -1)

@@ -155,7 +155,23 @@ template <int MODE, int NM> __device__ inline double acc_value(const Acc<MODE, N
 // The coefficient table [sigma][element][KB][8] (exponent scale, A_0..A_4,
 // -gamma) is copied into LDS once per workgroup when it fits; lanes read
 // the row of their own neighbour's species.
-template <int LMAX, int KB, int MODE, bool LDS, bool DENS, bool SCREEN>
+// Radial factors c_0..c_L of slot s and element e at squared distance q from
+// the plan's table: cubic in t = r/h - k on interval k of r = sqrt(q).
+template <int L>
+__device__ inline void radial_from_table(const PlanDev &P, int s, int e, float q, float (&cl)[L + 1]) {
+  const float x = __builtin_sqrtf(q) * P.tab_inv_h[s];
+  int k = (int)x;
+  k = k < P.tab_n - 1 ? k : P.tab_n - 1;
+  const float t = x - (float)k;
+  const float4 *c = P.rtab + (((size_t)s * P.E + e) * P.tab_n + k) * 5;
+#pragma unroll
+  for (int l = 0; l <= L; ++l) {
+    const float4 a = c[l];
+    cl[l] = fmaf(fmaf(fmaf(a.w, t, a.z), t, a.y), t, a.x);
+  }
+}
+
+template <int LMAX, int KB, int MODE, bool LDS, bool DENS, bool SCREEN, bool TAB = false>
 __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
                                                  const int32_t *astruct, double *partial, const int64_t *chunk_off,
                                                  int kc, unsigned long long *counter, const void *tab_global) {
@@ -263,9 +279,14 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         const double q = (dx * dx + dy * dy) + dz * dz;
         const TR qv = (TR)q;
         const int e = shift_species(w);
-        const int K = lds_k[e];
+        const int K = TAB ? 0 : lds_k[e];
         const size_t roff = ((size_t)(sgm * E + e) * KB) * kCoefStride;
         TR c0 = (TR)0;
+        if constexpr (TAB && !F64) {
+          float ct[1];
+          radial_from_table<0>(P, sgm, e, qv, ct);
+          c0 = ct[0];
+        }
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
           if (k < K) {
@@ -296,7 +317,9 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
         TR cl[LMAX + 1];
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) cl[l] = (TR)0;
-        if constexpr (!SCREEN && !F64) {
+        if constexpr (TAB && !F64) {
+          radial_from_table<LMAX>(P, sgm, e, qv, cl);
+        } else if constexpr (!SCREEN && !F64) {
           // FP32 table rows past an element's own primitive count are zero
           // (they add exact zeros), so every lane runs the plan's largest
           // count with wavefront-uniform control flow, and the LDS read of
@@ -480,6 +503,21 @@ template <bool LDS, bool DENS, bool SCREEN> OverlapFn pick_d(gmp_precision prec,
   return pick_l<ACC_TWOSUM, LDS, DENS, SCREEN>(lmax, kb);
 }
 
+// tabulated radial factors (FP32 modes): no coefficient table, no primitive loop
+template <int MODE, bool DENS> OverlapFn pick_tab_l(int lmax) {
+  switch (lmax) {
+    case 0: return k_overlap<0, 4, MODE, false, DENS, false, true>;
+    case 1: return k_overlap<1, 4, MODE, false, DENS, false, true>;
+    case 2: return k_overlap<2, 4, MODE, false, DENS, false, true>;
+    case 3: return k_overlap<3, 4, MODE, false, DENS, false, true>;
+    default: return k_overlap<4, 4, MODE, false, DENS, false, true>;
+  }
+}
+OverlapFn pick_tab(gmp_precision prec, int lmax, bool dens) {
+  if (prec == GMP_FP32_WIDE) return dens ? pick_tab_l<ACC_WIDE, true>(lmax) : pick_tab_l<ACC_WIDE, false>(lmax);
+  return dens ? pick_tab_l<ACC_TWOSUM, true>(lmax) : pick_tab_l<ACC_TWOSUM, false>(lmax);
+}
+
 template <bool LDS> OverlapFn pick_m(gmp_precision prec, int lmax, int kb, bool dens, bool screen) {
   if (screen) return dens ? pick_d<LDS, true, true>(prec, lmax, kb) : pick_d<LDS, false, true>(prec, lmax, kb);
   return dens ? pick_d<LDS, true, false>(prec, lmax, kb) : pick_d<LDS, false, false>(prec, lmax, kb);
@@ -562,13 +600,15 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
   scan_i64(nch, chunk_off, N, scan_aux, s);
   const bool f64 = p->prec == GMP_FP64;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
-  const bool use_lds = tab_bytes <= 48 * 1024;
+  const bool tabulated = p->dev.tab_n > 0 && !f64;
+  const bool use_lds = tab_bytes <= 48 * 1024 && !tabulated;
   const size_t smem = use_lds ? tab_bytes : 0;
   const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
   const bool dens = p->dev.dens_slot >= 0;
   const bool screen = p->dev.screen != 0;
-  OverlapFn fn = use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb, dens, screen)
-                         : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb, dens, screen);
+  OverlapFn fn = tabulated ? pick_tab(p->prec, p->dev.lmax, dens)
+                 : use_lds ? pick_m<true>(p->prec, p->dev.lmax, p->dev.kb, dens, screen)
+                           : pick_m<false>(p->prec, p->dev.lmax, p->dev.kb, dens, screen);
   const int64_t items_bound = max_chunks(p, N, pairs_bound);
   int64_t blocks = persistent_blocks((const void *)fn, smem, p->tuning.blocks_per_cu);
   const int64_t need = (items_bound + 3) / 4;

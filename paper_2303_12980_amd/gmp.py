@@ -54,7 +54,10 @@ class GMPPlan:
     """Probe set + density primitives + precision (wraps gmp_plan)."""
 
     def __init__(self, orders, sigmas, prim_offsets, B, beta, overlap_threshold, precision="fp32c",
-                 screening=False):
+                 screening=False, radial_intervals=0):
+        """radial_intervals > 0 (FP32 precisions): the forward reads the radial
+        factors from per-(slot, element, order) cubic tables in r = sqrt(q)
+        with that many intervals (see gmp_probe_desc.radial_intervals)."""
         L = _lib.load()
         self._orders = np.ascontiguousarray(orders, dtype=np.int32)
         self._sigmas = np.ascontiguousarray(sigmas, dtype=np.float64)
@@ -68,8 +71,9 @@ class GMPPlan:
                            len(self._sigmas), self._sigmas.ctypes.data_as(_lib.P_dbl),
                            len(self._poff) - 1, self._poff.ctypes.data_as(_lib.P_i32),
                            self._B.ctypes.data_as(_lib.P_dbl), self._beta.ctypes.data_as(_lib.P_dbl),
-                           self.tau, 1 if screening else 0)
+                           self.tau, 1 if screening else 0, int(radial_intervals))
         self.screening = bool(screening)
+        self.radial_intervals = int(radial_intervals)
         h = ctypes.c_void_p(0)
         check(L.gmp_plan_create(ctypes.byref(d), prec, ctypes.byref(h)))
         self._h = h
@@ -85,7 +89,7 @@ class GMPPlan:
     @classmethod
     def from_probes(cls, probes, precision="fp32c"):
         return cls(probes.orders, probes.sigmas, probes.prim_offsets, probes.B, probes.beta, probes.tau,
-                   precision, getattr(probes, "screening", False))
+                   precision, getattr(probes, "screening", False), getattr(probes, "radial_intervals", 0))
 
     @property
     def orders(self):
