@@ -167,8 +167,9 @@ typedef struct {
                                     points: the pair indices ordered by neighbour atom (stable), the
                                     order in which the backward gathers each atom's pairs */
   int64_t max_list;              /* [host] longest list of the last synchronous build (set by it); a
-                                    no-sync build sizes its in-LDS sort for this many entries (0: the
-                                    largest supported) and flags a longer list in the status word */
+                                    no-sync build sizes its in-LDS sort for this many entries plus 1/8
+                                    (0: as many as the LDS holds); longer lists are filled range by
+                                    range of buckets, a longer single bucket is flagged (GMP_E_STALE) */
 } gmp_neighbors;
 
 /* Plan: validates the probe set, infers rc(sigma)^2 from the overlap
@@ -218,6 +219,10 @@ gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n
 
 /* Lattice wrap, cell-list binning, neighbour count, fill and canonical
  * sort; also the reverse-pair index when nbrs->reverse is not NULL.
+ * Every (shell, species) bucket of a list is sorted in LDS: a list longer
+ * than the sort (up to the workgroup LDS of the device, 160 KB on gfx950,
+ * about 18,900 entries) is filled one range of buckets at a time, and a
+ * single bucket longer than that returns GMP_E_UNSUPPORTED.
  * Sync mode (n_pairs != NULL): syncs `stream` once after counting; if the
  * count exceeds nbrs->capacity it returns GMP_E_CAPACITY with *n_pairs set
  * to the required count (offsets are valid; call again with a larger
@@ -225,9 +230,10 @@ gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n
  * never syncs; an overflow is flagged in the workspace status word (see
  * gmp_check_status): lists that would end past the capacity are not written
  * and gmp_features / gmp_features_backward treat them as empty (zero
- * features and gradients for those centres), and a list longer than the
- * in-LDS sort sized from nbrs->max_list is replaced by placeholder entries;
- * every kernel stays inside the caller's arrays. */
+ * features and gradients for those centres), and a list with a bucket
+ * longer than the in-LDS sort sized from nbrs->max_list is replaced by
+ * placeholder entries (GMP_E_STALE); every kernel stays inside the caller's
+ * arrays. */
 gmp_status gmp_build_neighbors(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs,
                                int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream);
 

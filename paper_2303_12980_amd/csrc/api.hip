@@ -653,8 +653,8 @@ gmp_status status_to_error(uint32_t st) {
   if (st & ST_OVERFLOW) return set_error(GMP_E_CAPACITY, "neighbour capacity exceeded (no-sync mode)");
   if (st & ST_SORT_SIZE)
     return set_error(GMP_E_STALE,
-                     "a list outgrew the in-LDS sort sized by the last synchronous build (max_list); "
-                     "rebuild synchronously");
+                     "a (shell, species) bucket outgrew the in-LDS sort sized from max_list of the last "
+                     "synchronous build; rebuild synchronously");
   if (st & ST_INTERNAL) return set_error(GMP_E_INVALID, "inconsistent neighbour lists (internal check)");
   return set_error(GMP_E_INVALID, "device status " + std::to_string(st));
 }
@@ -667,12 +667,28 @@ int64_t nosync_sort_size(int64_t max_list) {
   return max_list + extra;
 }
 
+// LDS a workgroup may hold on this device (160 KB on gfx950)
+static int64_t lds_per_block() {
+  static int64_t bytes = 0;
+  if (bytes == 0) {
+    int dev = 0, v = 65536;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v < 65536)
+      v = 65536;
+    bytes = v;
+  }
+  return bytes;
+}
+
+// Keys of the fill kernel's in-LDS sort for lists of up to maxcnt entries
+// (<= 0: the most the LDS holds); the kernel's static LDS (candidate
+// staging, bucket counters) takes up to kFillStaticLds bytes.
+constexpr int64_t kFillStaticLds = 12 * 1024;
 int lds_keys_for(const gmp_plan *p, int64_t maxcnt) {
   const int nbk = p->dev.E * p->dev.S;
-  const int64_t avail = (65536 - 4 * (2 * nbk + 2)) / 8;
-  int64_t want = maxcnt <= 0 ? 64 : ((maxcnt + 63) / 64) * 64;
+  const int64_t avail = (lds_per_block() - kFillStaticLds - 4 * (2 * nbk + 2)) / 8;
+  int64_t want = maxcnt <= 0 ? avail : ((maxcnt + 63) / 64) * 64;
   if (want > avail) want = avail;
-  if (want > kSortMax) want = kSortMax;
   return (int)want;
 }
 
@@ -721,18 +737,17 @@ gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, i
     if (total > n->capacity)
       return set_error(GMP_E_CAPACITY, "neighbour capacity " + std::to_string(n->capacity) + " < required " +
                                            std::to_string(total));
-    if ((int64_t)stw[4] > kSortMax)
-      return set_error(GMP_E_UNSUPPORTED, "a centre has " + std::to_string(stw[4]) +
-                                              " neighbours; the in-LDS sort holds " + std::to_string(kSortMax));
     n->max_list = stw[4];
     lds_keys = lds_keys_for(p, stw[4]);
-    if ((int64_t)stw[4] > lds_keys)
-      return set_error(GMP_E_UNSUPPORTED, "a centre's neighbour list exceeds the in-LDS sort for this probe set");
+    if ((int64_t)stw[5] > lds_keys)
+      return set_error(GMP_E_UNSUPPORTED, "a centre has " + std::to_string(stw[5]) +
+                                              " neighbours of one species in one cutoff shell; the in-LDS sort "
+                                              "holds " + std::to_string(lds_keys));
   } else {
     // the pair count is known on the device only: every later call bounds
     // its pair range by the capacity and the device-side list ends
     n->n_pairs = 0;
-    lds_keys = lds_keys_for(p, n->max_list > 0 ? nosync_sort_size(n->max_list) : kSortMax);
+    lds_keys = lds_keys_for(p, n->max_list > 0 ? nosync_sort_size(n->max_list) : 0);
   }
   launch_fill(p, bt, nb, L, lds_keys, s);
   // the reverse index pairs mirror entries of atom-centred lists; with

@@ -22,7 +22,6 @@ constexpr int kMaxElements = 64;
 constexpr int kMaxL = 4;
 constexpr int kCoefStride = 8;    // per (slot, element, primitive): -g', A0..A4, -gamma, screening radius^2
 constexpr int kMaxPrims = 16;
-constexpr int kSortMax = 8192;    // largest per-centre list sorted in LDS
 constexpr int kWave = 64;
 
 // status-word bits (device side)
@@ -296,7 +295,7 @@ struct Carver {
 };
 
 struct WsLayout {
-  uint32_t *status;       // [64] words: [0] flags, [2..3] total pairs, [4] max count
+  uint32_t *status;       // [64] words: [0] flags, [2..3] total pairs, [4] longest list, [5] longest bucket
   StructInfo *sinfo;
   int32_t *bin_of;
   int32_t *astruct;       // [N] structure of every atom (written by the per-atom kernel of each stage)

@@ -357,10 +357,13 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
                      });
   __syncthreads();
   int64_t tot = 0;
+  int32_t bmax = 0;  // longest (shell, species) bucket of this centre
   for (int t = threadIdx.x; t < nbk; t += blockDim.x) {
     cnt[i * nbk + t] = c[t];
     tot += c[t];
+    bmax = c[t] > bmax ? c[t] : bmax;
   }
+  if (bmax > 0) atomicMax(status + 5, (uint32_t)bmax);
   for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, kWave);
   if (lane == 0) lds_tot[w] = tot;
   __syncthreads();
@@ -473,6 +476,9 @@ __device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3, int shell
 // One workgroup per centre (centres in cell-list order): fill its buckets
 // (shell h, species e), in bucket order h * E + e, in LDS; sort every bucket
 // by (j, n); write j / shift, the bucket starts and the sigma-prefix ends.
+// A list longer than the LDS sort (lds_keys entries) is filled range by range
+// of consecutive buckets that fit, enumerating the candidates once per range;
+// a single bucket longer than the sort leaves placeholders and is reported.
 __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                               const double *fw, const int64_t *bin_start,
                                               const double *sx, const double *sy, const double *sz,
@@ -495,12 +501,13 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   const int64_t base = nb.offsets[i];
   const int64_t total = nb.offsets[i + 1] - base;
   const bool overflow = nb.offsets[i + 1] > nb.capacity;
-  const bool too_big = total > lds_keys;
+  __shared__ int32_t lds_bmax;
   if (w == 0) {  // bucket starts: exclusive scan of the centre's bucket counts
-    int32_t carry = 0;
+    int32_t carry = 0, vmax = 0;
     for (int b0 = 0; b0 < nbk; b0 += kWave) {
       const int b = b0 + lane;
       const int32_t v = b < nbk ? cnt[i * nbk + b] : 0;
+      vmax = v > vmax ? v : vmax;
       int32_t incl = v;
 #pragma unroll
       for (int o = 1; o < kWave; o <<= 1) {
@@ -510,14 +517,23 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       if (b < nbk) bstart[b] = carry + incl - v;
       carry += __shfl(incl, kWave - 1, kWave);
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const int32_t y = __shfl_xor(vmax, o, kWave);
+      vmax = y > vmax ? y : vmax;
+    }
     if (lane == 0) {
       bstart[nbk] = carry;
+      lds_bmax = vmax;
       if (overflow) atomicOr(status, ST_OVERFLOW);
-      if (too_big) atomicOr(status, ST_SORT_SIZE);
+      if (vmax > lds_keys) atomicOr(status, ST_SORT_SIZE);
       if ((int64_t)carry != total) atomicOr(status, ST_INTERNAL);
     }
   }
   __syncthreads();
+  // a list longer than the sort is filled one range of buckets at a time;
+  // only a single bucket longer than the sort cannot be sorted here
+  const bool too_big = lds_bmax > lds_keys;
   for (int b = tid; b <= nbk; b += blockDim.x) {
     nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
     if (pair_key) abs_bstart[i * (nbk + 1) + b] = base + bstart[b];
@@ -544,48 +560,60 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
     }
     return;
   }
-  for (int b = tid; b < nbk; b += blockDim.x) cursor[b] = bstart[b];
-  __syncthreads();
   const int s = astruct[g];
   Cand C;
   cand_setup(C, info, bt, s, fw, g);
   const double rix = nb.rw[g], riy = nb.rw[N + g], riz = nb.rw[2 * N + g];
-  for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
-                     [&](int t, const int *n, double shx, double shy, double shz) {
-                       const double dx = (sx[t] - rix) + shx;
-                       const double dy = (sy[t] - riy) + shy;
-                       const double dz = (sz[t] - riz) + shz;
-                       const double q = (dx * dx + dy * dy) + dz * dz;
-                       if (q <= P.rcmax2) {
-                         const int sh = shell_of(P, q);
-                         const int bk = sh * P.E + ssp[t];
-                         const int pos = atomicAdd(&cursor[bk], 1);
-                         if (pos < bstart[bk + 1]) keys[pos] = make_key(sid[t], n[0], n[1], n[2], sh);
-                         else atomicOr(status, ST_INTERNAL);
-                       }
-                     });
-  __syncthreads();
-  for (int b = w; b < nbk; b += nw) {
-    const int b0 = bstart[b], bn = bstart[b + 1] - b0;
-    if (bn == 0) continue;
-    wave_sort(keys + b0, bn);
-    const int e = b % P.E;
-    for (int t = lane; t < bn; t += kWave) {
-      uint64_t k = keys[b0 + t];
-      int32_t jj = (int32_t)((k >> 24) & 0x7fffffffull);
-      uint32_t n1 = (uint32_t)(((k >> 16) & 0xff) - 128) & 0xffu;
-      uint32_t n2 = (uint32_t)(((k >> 8) & 0xff) - 128) & 0xffu;
-      uint32_t n3 = (uint32_t)((k & 0xff) - 128) & 0xffu;
-      nb.j[base + b0 + t] = jj;
-      nb.shift[base + b0 + t] = (int32_t)(n1 | (n2 << 8) | (n3 << 16) | ((uint32_t)e << 24));
-      if (pair_key) {  // inputs of the reverse-index kernel; the index starts unresolved
-        const int64_t gp = base + b0 + t;
-        pair_key[gp] = k;
-        if ((gp & 15) == 0) pair_sum[gp >> 4] = k;
-        pair_centre[gp] = (int32_t)i;
-        nb.reverse[gp] = -1;
+  // buckets [b_lo, b_hi) whose entries fit the sort together: one range for
+  // lists up to lds_keys entries, several (one candidate pass each) beyond
+  for (int b_lo = 0; b_lo < nbk;) {
+    int b_hi = b_lo + 1;
+    while (b_hi < nbk && bstart[b_hi + 1] - bstart[b_lo] <= lds_keys) ++b_hi;
+    const int key0 = bstart[b_lo];
+    for (int b = b_lo + tid; b < b_hi; b += blockDim.x) cursor[b] = bstart[b] - key0;
+    __syncthreads();
+    for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
+                       [&](int t, const int *n, double shx, double shy, double shz) {
+                         const double dx = (sx[t] - rix) + shx;
+                         const double dy = (sy[t] - riy) + shy;
+                         const double dz = (sz[t] - riz) + shz;
+                         const double q = (dx * dx + dy * dy) + dz * dz;
+                         if (q <= P.rcmax2) {
+                           const int sh = shell_of(P, q);
+                           const int bk = sh * P.E + ssp[t];
+                           if (bk >= b_lo && bk < b_hi) {
+                             const int pos = atomicAdd(&cursor[bk], 1);
+                             if (pos < bstart[bk + 1] - key0) keys[pos] = make_key(sid[t], n[0], n[1], n[2], sh);
+                             else atomicOr(status, ST_INTERNAL);
+                           }
+                         }
+                       });
+    __syncthreads();
+    for (int b = b_lo + w; b < b_hi; b += nw) {
+      const int b0 = bstart[b], bn = bstart[b + 1] - b0;
+      if (bn == 0) continue;
+      uint64_t *kb = keys + (b0 - key0);
+      wave_sort(kb, bn);
+      const int e = b % P.E;
+      for (int t = lane; t < bn; t += kWave) {
+        uint64_t k = kb[t];
+        int32_t jj = (int32_t)((k >> 24) & 0x7fffffffull);
+        uint32_t n1 = (uint32_t)(((k >> 16) & 0xff) - 128) & 0xffu;
+        uint32_t n2 = (uint32_t)(((k >> 8) & 0xff) - 128) & 0xffu;
+        uint32_t n3 = (uint32_t)((k & 0xff) - 128) & 0xffu;
+        nb.j[base + b0 + t] = jj;
+        nb.shift[base + b0 + t] = (int32_t)(n1 | (n2 << 8) | (n3 << 16) | ((uint32_t)e << 24));
+        if (pair_key) {  // inputs of the reverse-index kernel; the index starts unresolved
+          const int64_t gp = base + b0 + t;
+          pair_key[gp] = k;
+          if ((gp & 15) == 0) pair_sum[gp >> 4] = k;
+          pair_centre[gp] = (int32_t)i;
+          nb.reverse[gp] = -1;
+        }
       }
     }
+    __syncthreads();  // the next range reuses the keys and cursors
+    b_lo = b_hi;
   }
 }
 

@@ -181,14 +181,51 @@ def test_singular_cell_is_rejected(g):
         g.build_neighbors(plan, g.DeviceBatch.from_batch(b), g.Workspace())
 
 
-def test_list_longer_than_the_sort_is_unsupported(g):
-    """One atom in a 1.8 A cubic cell with a ~26 A cutoff has ~12,000 images
-    inside the cutoff, more than one centre's in-LDS sort holds."""
-    say("[list longer than the in-LDS sort]")
-    p = gs.Probes(np.array([0], np.int32), np.array([3.0]), np.array([0, 1], np.int32), np.array([5.0]),
-                  np.array([0.3]), 1e-14)
+def _lattice_probes(tau, n_elements=1):
+    return gs.Probes(np.array([0, 1, 2], np.int32), np.array([3.0]), np.arange(n_elements + 1, dtype=np.int32),
+                     np.full(n_elements, 5.0), np.full(n_elements, 0.3), tau)
+
+
+@pytest.mark.parametrize("n_atoms,tau", [(1, 1e-14), (2, 1e-17)])
+def test_lists_longer_than_8192(g, n_atoms, tau):
+    """Atoms in a 1.8 A cubic cell with 26-29 A cutoffs: one atom (one
+    bucket of ~12,600 images, sorted in the enlarged LDS sort) and two atoms
+    of two species (~33,000 neighbours per centre in two buckets of ~16,500,
+    more than the sort holds: filled one bucket range at a time).  Lists
+    bit-exact against the oracle, features within 1e-11 (FP64) where they
+    are not the cancelled remainder of symmetric images."""
+    p = _lattice_probes(tau, n_atoms)
+    pos = np.array([[0.0, 0.0, 0.0], [0.9, 0.8, 0.7]])[:n_atoms]
+    b = gs.make_batch([(pos, np.arange(n_atoms, dtype=np.int32), np.eye(3) * 1.8, 7)])
+    plan = g.GMPPlan.from_probes(p, "fp64")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    F, _ = g.features(plan, db, nb, ws)
+    torch.cuda.synchronize()
+    sizes = np.diff(nb.offsets.cpu().numpy())
+    say(f"[long lists] {n_atoms} atoms: list lengths {sizes.tolist()}")
+    assert sizes.min() > 12000
+    from gpu_helpers import check_lists_many
+    assert check_lists_many(nb, b, p, 0) == n_atoms
+    # features that vanish by the lattice's symmetry are rounding residuals
+    # of ~1e4 cancelling images on both sides (kappa = F_abs / F ~ 1e13): the
+    # bar there is the FP64 rounding of the terms, 64 * 2^-53 * F_abs
+    Fref = oracle.features_batch(b, p)
+    Fabs = oracle.features_abs(b.structure(0), p)
+    err = np.abs(F.cpu().numpy() - Fref)
+    ok = (err <= 1e-11 * Fref) | (err <= 64 * 2.0 ** -53 * Fabs) | ((Fref <= p.tau) & (err <= p.tau))
+    assert ok.all(), float(err.max())
+    good = Fref > 1e-8 * Fabs
+    assert good.any() and np.all(err[good] <= 1e-11 * Fref[good])
+
+
+def test_bucket_longer_than_the_sort_is_unsupported(g):
+    """One atom in the 1.8 A cell with a ~35 A cutoff: a single bucket of
+    ~30,000 images, more than the 160 KB LDS sort holds."""
+    p = _lattice_probes(1e-25)
     rc = float(np.sqrt(oracle.cutoffs(p).max()))
-    assert 24.0 < rc < 30.0
+    assert 33.0 < rc < 37.0
     b = gs.make_batch([(np.zeros((1, 3)), np.zeros(1, np.int32), np.eye(3) * 1.8, 7)])
     plan = g.GMPPlan.from_probes(p, "fp64")
     with pytest.raises(g.GMPError, match="UNSUPPORTED"):

@@ -231,11 +231,12 @@ def test_graph_replay_growing_pair_count(g, points, split):
     assert _same(step.gpos, gp1) and _same(step.gcell, gc1)
 
 
-def test_nosync_list_outgrowing_the_sort_is_reported(g):
+def test_nosync_list_outgrowing_the_sort_is_filled_by_ranges(g):
     """A no-sync rebuild sizes its in-LDS sort from the longest list of the
-    last synchronous build plus headroom (1/8, at least 64 entries).  A list
-    that grows beyond that is reported as GMP_E_STALE by the captured step's
-    own status word, and a synchronous rebuild then gives the exact lists."""
+    last synchronous build plus headroom (1/8, at least 64 entries).  Lists
+    that grow past it are filled range by range of (shell, species) buckets,
+    so replays of a strongly compressed geometry still equal a fresh
+    synchronous build bit for bit."""
     b, probes = _batch(29)
     plan = g.GMPPlan.from_probes(probes, "fp64")
     db = g.DeviceBatch.from_batch(b)
@@ -245,13 +246,33 @@ def test_nosync_list_outgrowing_the_sort_is_reported(g):
     step = g.CapturedStep(plan, db, ws, nbc, backward=False)
     step.replay()
     step.check_status()
-    # a small growth stays within the headroom
-    _scale_geometry(db, 0.99)
+    _scale_geometry(db, 0.8)
     step.replay()
     step.check_status()
-    nb1 = g.build_neighbors(plan, db, g.Workspace())
-    assert nb1.max_list > nb0.max_list
-    # a large one does not: reported, not silently wrong
+    nb2 = g.build_neighbors(plan, db, g.Workspace())
+    assert nb2.max_list > nb0.max_list + max(64, nb0.max_list // 8)
+    F2, mu2 = g.features(plan, db, nb2, g.Workspace())
+    torch.cuda.synchronize()
+    assert _same(step.F, F2) and _same(step.mu, mu2)
+
+
+def test_nosync_bucket_outgrowing_the_sort_is_reported(g):
+    """With one element and one sigma a centre's list is a single bucket;
+    when it outgrows the sort sized by the last synchronous build the
+    captured step's own status word reports GMP_E_STALE, and a synchronous
+    rebuild then gives the exact lists."""
+    rng = np.random.default_rng(31)
+    b = gs.make_batch([gs.small_periodic(rng, n_atoms=30, n_elements=1, density=0.06, dmin=1.3)])
+    probes = gs.Probes(np.array([0, 1], np.int32), np.array([0.6]), np.array([0, 1], np.int32), np.array([1.0]),
+                       np.array([0.3]), 1e-12)
+    plan = g.GMPPlan.from_probes(probes, "fp64")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb0 = g.build_neighbors(plan, db, ws)
+    nbc = g.build_neighbors(plan, db, ws, capacity=6 * nb0.n_pairs + 4096)
+    step = g.CapturedStep(plan, db, ws, nbc, backward=False)
+    step.replay()
+    step.check_status()
     _scale_geometry(db, 0.8)
     nb2 = g.build_neighbors(plan, db, g.Workspace())
     assert nb2.max_list > nb0.max_list + max(64, nb0.max_list // 8)
@@ -260,7 +281,6 @@ def test_nosync_list_outgrowing_the_sort_is_reported(g):
     with pytest.raises(g.GMPError) as ei:
         step.check_status()
     assert ei.value.status == 8  # GMP_E_STALE
-    # the synchronous build re-sizes the sort: features equal a fresh build's
     nbs = g.build_neighbors(plan, db, ws, out=nbc)
     F, _ = g.features(plan, db, nbs, ws)
     F2, _ = g.features(plan, db, nb2, g.Workspace())
