@@ -56,9 +56,10 @@ typedef enum {
   GMP_E_NONFINITE = 5,    /* non-finite coordinate or lattice entry */
   GMP_E_HIP = 6,          /* a HIP runtime call failed */
   GMP_E_NOMEM = 7,        /* host allocation or workspace too small */
-  GMP_E_STALE = 8,        /* a no-sync rebuild met a list longer than the sort sized from max_list of the
-                             last synchronous build: that centre holds placeholder entries; call the
-                             synchronous build (which re-sizes) */
+  GMP_E_STALE = 8,        /* a no-sync rebuild met a single (shell, species) bucket longer than the
+                             largest in-LDS sort (the device's workgroup LDS): that centre holds
+                             placeholder entries; a synchronous build reports such a list as
+                             GMP_E_UNSUPPORTED */
 } gmp_status;
 
 /* Arithmetic of the overlap kernels.
@@ -167,9 +168,9 @@ typedef struct {
                                     points: the pair indices ordered by neighbour atom (stable), the
                                     order in which the backward gathers each atom's pairs */
   int64_t max_list;              /* [host] longest list of the last synchronous build (set by it); a
-                                    no-sync build sizes its in-LDS sort for this many entries plus 1/8
-                                    (0: as many as the LDS holds); longer lists are filled range by
-                                    range of buckets, a longer single bucket is flagged (GMP_E_STALE) */
+                                    no-sync build sizes its short-list sort for this many entries plus
+                                    1/8 (0: 8,192 entries); lists that outgrow it are filled by the
+                                    long-list kernel, whose sort takes the device's workgroup LDS */
 } gmp_neighbors;
 
 /* Plan: validates the probe set, infers rc(sigma)^2 from the overlap
@@ -219,10 +220,12 @@ gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n
 
 /* Lattice wrap, cell-list binning, neighbour count, fill and canonical
  * sort; also the reverse-pair index when nbrs->reverse is not NULL.
- * Every (shell, species) bucket of a list is sorted in LDS: a list longer
- * than the sort (up to the workgroup LDS of the device, 160 KB on gfx950,
- * about 18,900 entries) is filled one range of buckets at a time, and a
- * single bucket longer than that returns GMP_E_UNSUPPORTED.
+ * Every (shell, species) bucket of a list is sorted in LDS.  Lists of up to
+ * 8,192 entries are filled by a workgroup per centre with a sort sized for
+ * the longest list; longer ones by a second, persistent kernel whose sort
+ * takes the workgroup LDS of the device (160 KB on gfx950, about 18,900
+ * entries): a list longer than that is filled one range of buckets at a
+ * time, and a single bucket longer than that returns GMP_E_UNSUPPORTED.
  * Sync mode (n_pairs != NULL): syncs `stream` once after counting; if the
  * count exceeds nbrs->capacity it returns GMP_E_CAPACITY with *n_pairs set
  * to the required count (offsets are valid; call again with a larger
@@ -231,9 +234,8 @@ gmp_status gmp_workspace_size(const gmp_plan *plan, int32_t n_structs, int64_t n
  * gmp_check_status): lists that would end past the capacity are not written
  * and gmp_features / gmp_features_backward treat them as empty (zero
  * features and gradients for those centres), and a list with a bucket
- * longer than the in-LDS sort sized from nbrs->max_list is replaced by
- * placeholder entries (GMP_E_STALE); every kernel stays inside the caller's
- * arrays. */
+ * longer than the long-list sort is replaced by placeholder entries
+ * (GMP_E_STALE); every kernel stays inside the caller's arrays. */
 gmp_status gmp_build_neighbors(const gmp_plan *plan, const gmp_batch *batch, gmp_neighbors *nbrs,
                                int64_t *n_pairs, void *ws, size_t ws_bytes, void *stream);
 

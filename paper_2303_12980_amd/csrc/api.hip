@@ -17,8 +17,9 @@ void launch_struct_setup(const gmp_plan *p, const BatchDev &bt, const WsLayout &
 void launch_wrap(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_elements, hipStream_t s);
 void launch_scatter(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_elements, hipStream_t s);
 void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, hipStream_t s);
+void launch_list_stats(const gmp_plan *p, const BatchDev &bt, const WsLayout &L, hipStream_t s);
 void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int lds_keys,
-                 hipStream_t s);
+                 int long_keys, hipStream_t s);
 void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,
                     hipStream_t s);
 int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs);
@@ -119,6 +120,7 @@ WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t M, int64_t c
   L.ssp = c.take<int32_t>(N);
   L.cnt = c.take<int32_t>((size_t)NC * p->dev.E * p->dev.S);
   L.ptotal = c.take<int64_t>(NC);
+  L.long_q = c.take<int32_t>(NC);
   L.scan_aux = c.take<int64_t>(scan_aux_size(scan_n));
   L.partial = c.take<double>(partial_slots(p, NC, capacity));
   L.nch = c.take<int64_t>(NC);
@@ -653,8 +655,8 @@ gmp_status status_to_error(uint32_t st) {
   if (st & ST_OVERFLOW) return set_error(GMP_E_CAPACITY, "neighbour capacity exceeded (no-sync mode)");
   if (st & ST_SORT_SIZE)
     return set_error(GMP_E_STALE,
-                     "a (shell, species) bucket outgrew the in-LDS sort sized from max_list of the last "
-                     "synchronous build; rebuild synchronously");
+                     "a (shell, species) bucket is longer than the largest in-LDS sort of this device; the "
+                     "centre holds placeholder entries");
   if (st & ST_INTERNAL) return set_error(GMP_E_INVALID, "inconsistent neighbour lists (internal check)");
   return set_error(GMP_E_INVALID, "device status " + std::to_string(st));
 }
@@ -680,16 +682,23 @@ static int64_t lds_per_block() {
   return bytes;
 }
 
-// Keys of the fill kernel's in-LDS sort for lists of up to maxcnt entries
-// (<= 0: the most the LDS holds); the kernel's static LDS (candidate
-// staging, bucket counters) takes up to kFillStaticLds bytes.
+// Keys of the fill kernels' in-LDS sorts.  The short-list kernel sorts
+// lists of up to maxcnt entries (rounded up to 64; <= 0: its cap), capped at
+// kShortSortMax so that several of its workgroups share a CU; longer lists go
+// to the long-list kernel, which sorts with the most LDS a workgroup may hold
+// (its static LDS, candidate staging and bucket counters, takes up to
+// kFillStaticLds bytes).
 constexpr int64_t kFillStaticLds = 12 * 1024;
-int lds_keys_for(const gmp_plan *p, int64_t maxcnt) {
+constexpr int64_t kShortSortMax = 8192;
+int long_keys_for(const gmp_plan *p) {
   const int nbk = p->dev.E * p->dev.S;
-  const int64_t avail = (lds_per_block() - kFillStaticLds - 4 * (2 * nbk + 2)) / 8;
-  int64_t want = maxcnt <= 0 ? avail : ((maxcnt + 63) / 64) * 64;
-  if (want > avail) want = avail;
-  return (int)want;
+  return (int)((lds_per_block() - kFillStaticLds - 4 * (2 * nbk + 2)) / 8);
+}
+int lds_keys_for(const gmp_plan *p, int64_t maxcnt) {
+  int64_t want = maxcnt <= 0 ? kShortSortMax : ((maxcnt + 63) / 64) * 64;
+  if (want > kShortSortMax) want = kShortSortMax;
+  const int64_t avail = long_keys_for(p);
+  return (int)(want < avail ? want : avail);
 }
 
 // The neighbour build; the reverse-pair search is launched only when
@@ -722,10 +731,11 @@ gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, i
   launch_scatter(bt, nb, L, p->dev.E, s);
   launch_count(p, bt, nb, L, s);
   scan_i64(L.ptotal, n->offsets, NC, L.scan_aux, s);
-  int lds_keys;
+  int lds_keys, long_keys = long_keys_for(p);
   if (n_pairs) {
     int64_t total = 0;
     uint32_t stw[8];
+    launch_list_stats(p, bt, L, s);
     hipError_t e = hipMemcpyAsync(&total, n->offsets + NC, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(stw, L.status, sizeof(stw), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -739,17 +749,19 @@ gmp_status build_impl(const gmp_plan *p, const gmp_batch *b, gmp_neighbors *n, i
                                            std::to_string(total));
     n->max_list = stw[4];
     lds_keys = lds_keys_for(p, stw[4]);
-    if ((int64_t)stw[5] > lds_keys)
+    if ((int64_t)stw[5] > long_keys)
       return set_error(GMP_E_UNSUPPORTED, "a centre has " + std::to_string(stw[5]) +
                                               " neighbours of one species in one cutoff shell; the in-LDS sort "
-                                              "holds " + std::to_string(lds_keys));
+                                              "holds " + std::to_string(long_keys));
+    if ((int64_t)stw[4] <= lds_keys) long_keys = 0;  // no list for the long-list kernel
   } else {
     // the pair count is known on the device only: every later call bounds
-    // its pair range by the capacity and the device-side list ends
+    // its pair range by the capacity and the device-side list ends; the
+    // long-list kernel takes whatever outgrew the short-list sort
     n->n_pairs = 0;
     lds_keys = lds_keys_for(p, n->max_list > 0 ? nosync_sort_size(n->max_list) : 0);
   }
-  launch_fill(p, bt, nb, L, lds_keys, s);
+  launch_fill(p, bt, nb, L, lds_keys, long_keys, s);
   // the reverse index pairs mirror entries of atom-centred lists; with
   // reference points the backward orders pairs by neighbour itself
   if (n->reverse && with_reverse && !b->point_offsets)

@@ -295,7 +295,8 @@ struct Carver {
 };
 
 struct WsLayout {
-  uint32_t *status;       // [64] words: [0] flags, [2..3] total pairs, [4] longest list, [5] longest bucket
+  uint32_t *status;       // [64] words: [0] flags, [2..3] total pairs, [4] longest list, [5] longest bucket,
+                          // [6] long-list queue length, [7] next queue entry
   StructInfo *sinfo;
   int32_t *bin_of;
   int32_t *astruct;       // [N] structure of every atom (written by the per-atom kernel of each stage)
@@ -307,6 +308,7 @@ struct WsLayout {
   int32_t *sid, *ssp;     // bin-sorted atom index and species
   int32_t *cnt;           // [N][S][E] neighbours per bucket (shell, species)
   int64_t *ptotal;        // [N]
+  int32_t *long_q;        // [N] centres whose lists the long-list fill kernel writes
   int64_t *scan_aux;      // scan block sums
   double *partial;        // overlap partial moments [chunk][sigma][monomial]
   int64_t *nch;           // [N] chunks per centre

@@ -357,13 +357,10 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
                      });
   __syncthreads();
   int64_t tot = 0;
-  int32_t bmax = 0;  // longest (shell, species) bucket of this centre
   for (int t = threadIdx.x; t < nbk; t += blockDim.x) {
     cnt[i * nbk + t] = c[t];
     tot += c[t];
-    bmax = c[t] > bmax ? c[t] : bmax;
   }
-  if (bmax > 0) atomicMax(status + 5, (uint32_t)bmax);
   for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, kWave);
   if (lane == 0) lds_tot[w] = tot;
   __syncthreads();
@@ -371,7 +368,33 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
     int64_t all = 0;
     for (int k = 0; k < nw; ++k) all += lds_tot[k];
     ptotal[i] = all;
-    atomicMax(status + 4, (uint32_t)(all > 0x7fffffff ? 0x7fffffff : all));
+  }
+}
+
+// Longest list (status word 4) and longest (shell, species) bucket (word 5)
+// of the counted lists, for the synchronous build's sort sizes: a grid-stride
+// maximum with one atomic per workgroup and word.
+__global__ __launch_bounds__(256) void k_list_stats(const int64_t *ptotal, int64_t n_centres, const int32_t *cnt,
+                                                    int64_t n_cnt, uint32_t *status) {
+  __shared__ int64_t lds_m[2][4];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t lmax = 0, bmax = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_centres; t += stride)
+    lmax = ptotal[t] > lmax ? ptotal[t] : lmax;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_cnt; t += stride)
+    bmax = cnt[t] > bmax ? cnt[t] : bmax;
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int64_t a = __shfl_xor(lmax, o, kWave), b = __shfl_xor(bmax, o, kWave);
+    lmax = a > lmax ? a : lmax;
+    bmax = b > bmax ? b : bmax;
+  }
+  if (lane == 0) { lds_m[0][w] = lmax; lds_m[1][w] = bmax; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    int64_t m = 0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) m = lds_m[threadIdx.x][k] > m ? lds_m[threadIdx.x][k] : m;
+    if (m > 0) atomicMax(status + 4 + threadIdx.x, (uint32_t)(m > 0x7fffffff ? 0x7fffffff : m));
   }
 }
 
@@ -473,35 +496,30 @@ __device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3, int shell
          ((uint64_t)(n2 + 128) << 8) | (uint64_t)(n3 + 128);
 }
 
-// One workgroup per centre (centres in cell-list order): fill its buckets
-// (shell h, species e), in bucket order h * E + e, in LDS; sort every bucket
-// by (j, n); write j / shift, the bucket starts and the sigma-prefix ends.
-// A list longer than the LDS sort (lds_keys entries) is filled range by range
-// of consecutive buckets that fit, enumerating the candidates once per range;
-// a single bucket longer than the sort leaves placeholders and is reported.
-__global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
-                                              const double *fw, const int64_t *bin_start,
-                                              const double *sx, const double *sy, const double *sz,
-                                              const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
-                                              const int32_t *cnt, int lds_keys, uint64_t *pair_key,
-                                              int32_t *pair_centre, uint64_t *pair_sum, int64_t *abs_bstart,
-                                              uint32_t *status) {
-  extern __shared__ uint64_t lds_u64[];
-  __shared__ CandLds lds_cand[4];
+// Fill of one centre's list by one workgroup: its buckets (shell h,
+// species e), in bucket order h * E + e, in LDS; every bucket sorted by
+// (j, n); j / shift, the bucket starts and the sigma-prefix ends written.
+// The in-LDS sort holds lds_keys entries.  RANGED = false (the short-list
+// kernel) takes lists that fit in one candidate pass and hands longer ones
+// to the long-list queue; RANGED = true fills range by range of consecutive
+// buckets that fit, enumerating the candidates once per range; a single
+// bucket longer than the sort leaves placeholders and is reported.
+template <bool RANGED>
+__device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const NbrDev &nb, const StructInfo *info,
+                                   const double *fw, const int64_t *bin_start, const double *sx, const double *sy,
+                                   const double *sz, const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
+                                   const int32_t *cnt, int lds_keys, uint64_t *pair_key, int32_t *pair_centre,
+                                   uint64_t *pair_sum, int64_t *abs_bstart, uint32_t *status, int32_t *long_q,
+                                   int64_t i, uint64_t *keys, CandLds *lds_cand, int32_t &lds_bmax) {
   const int nbk = P.E * P.S;
-  uint64_t *keys = lds_u64;
-  int32_t *bstart = (int32_t *)(lds_u64 + lds_keys);  // [nbk+1]
-  int32_t *cursor = bstart + nbk + 1;                 // [nbk]
-  // centre i (atoms: in cell-list order; reference points: in index order), index g
-  const int64_t kb = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int64_t i = point_mode(bt) ? kb : sid[kb];
+  int32_t *bstart = (int32_t *)(keys + lds_keys);  // [nbk+1]
+  int32_t *cursor = bstart + nbk + 1;              // [nbk]
   const int64_t g = centre_base(bt) + i;
   const int64_t N = n_total(bt);  // stride of rw
   const int tid = threadIdx.x, w = tid / kWave, nw = blockDim.x / kWave, lane = lane_id();
   const int64_t base = nb.offsets[i];
   const int64_t total = nb.offsets[i + 1] - base;
   const bool overflow = nb.offsets[i + 1] > nb.capacity;
-  __shared__ int32_t lds_bmax;
   if (w == 0) {  // bucket starts: exclusive scan of the centre's bucket counts
     int32_t carry = 0, vmax = 0;
     for (int b0 = 0; b0 < nbk; b0 += kWave) {
@@ -526,22 +544,22 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
       bstart[nbk] = carry;
       lds_bmax = vmax;
       if (overflow) atomicOr(status, ST_OVERFLOW);
-      if (vmax > lds_keys) atomicOr(status, ST_SORT_SIZE);
+      if (RANGED && vmax > lds_keys) atomicOr(status, ST_SORT_SIZE);
       if ((int64_t)carry != total) atomicOr(status, ST_INTERNAL);
+      // a list the short-list kernel cannot sort in one pass goes to the queue
+      if (!RANGED && !overflow && total > lds_keys) long_q[atomicAdd(status + 6, 1u)] = (int32_t)i;
     }
   }
   __syncthreads();
-  // a list longer than the sort is filled one range of buckets at a time;
-  // only a single bucket longer than the sort cannot be sorted here
-  const bool too_big = lds_bmax > lds_keys;
+  if (!RANGED && !overflow && total > lds_keys) return;  // the long-list kernel writes this centre
   for (int b = tid; b <= nbk; b += blockDim.x) {
     nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
     if (pair_key) abs_bstart[i * (nbk + 1) + b] = base + bstart[b];
   }
   for (int s = tid; s < P.S; s += blockDim.x) nb.sigma_end[i * P.S + s] = bstart[(P.rank_lt[s] + 1) * P.E];
   if (overflow) return;  // consumers skip centres whose list ends past the capacity
-  if (too_big) {
-    // the list does not fit the in-LDS sort: leave in-range placeholder
+  if (RANGED && lds_bmax > lds_keys) {
+    // a bucket does not fit the in-LDS sort: leave in-range placeholder
     // entries (the centre itself, or atom 0 for a reference point; no shift)
     // so no consumer reads outside its arrays; the status word reports it
     const int64_t jp = point_mode(bt) ? 0 : i;
@@ -564,12 +582,16 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   Cand C;
   cand_setup(C, info, bt, s, fw, g);
   const double rix = nb.rw[g], riy = nb.rw[N + g], riz = nb.rw[2 * N + g];
-  // buckets [b_lo, b_hi) whose entries fit the sort together: one range for
-  // lists up to lds_keys entries, several (one candidate pass each) beyond
+  // buckets [b_lo, b_hi) whose entries fit the sort together (all of them
+  // in the short-list kernel)
   for (int b_lo = 0; b_lo < nbk;) {
-    int b_hi = b_lo + 1;
-    while (b_hi < nbk && bstart[b_hi + 1] - bstart[b_lo] <= lds_keys) ++b_hi;
-    const int key0 = bstart[b_lo];
+    int b_hi = nbk;
+    if (RANGED) {
+      b_hi = b_lo + 1;
+      while (b_hi < nbk && bstart[b_hi + 1] - bstart[b_lo] <= lds_keys) ++b_hi;
+      b_hi = __builtin_amdgcn_readfirstlane(b_hi);  // the same for every thread
+    }
+    const int key0 = RANGED ? __builtin_amdgcn_readfirstlane(bstart[b_lo]) : 0;
     for (int b = b_lo + tid; b < b_hi; b += blockDim.x) cursor[b] = bstart[b] - key0;
     __syncthreads();
     for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
@@ -581,7 +603,7 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
                          if (q <= P.rcmax2) {
                            const int sh = shell_of(P, q);
                            const int bk = sh * P.E + ssp[t];
-                           if (bk >= b_lo && bk < b_hi) {
+                           if (!RANGED || (bk >= b_lo && bk < b_hi)) {
                              const int pos = atomicAdd(&cursor[bk], 1);
                              if (pos < bstart[bk + 1] - key0) keys[pos] = make_key(sid[t], n[0], n[1], n[2], sh);
                              else atomicOr(status, ST_INTERNAL);
@@ -612,8 +634,53 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
         }
       }
     }
+    if (!RANGED) break;
     __syncthreads();  // the next range reuses the keys and cursors
     b_lo = b_hi;
+  }
+}
+
+// Short-list fill: one workgroup per centre, centres in cell-list order
+// (reference points in index order).
+__global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
+                                              const double *fw, const int64_t *bin_start,
+                                              const double *sx, const double *sy, const double *sz,
+                                              const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
+                                              const int32_t *cnt, int lds_keys, uint64_t *pair_key,
+                                              int32_t *pair_centre, uint64_t *pair_sum, int64_t *abs_bstart,
+                                              uint32_t *status, int32_t *long_q) {
+  extern __shared__ uint64_t lds_u64[];
+  __shared__ CandLds lds_cand[4];
+  __shared__ int32_t lds_bmax;
+  const int64_t kb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t i = point_mode(bt) ? kb : sid[kb];
+  fill_centre<false>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
+                     pair_centre, pair_sum, abs_bstart, status, long_q, i, lds_u64, lds_cand, lds_bmax);
+}
+
+// Long-list fill: persistent workgroups take the queued centres one at a
+// time (status word 6 holds the queue length, word 7 the next entry); every
+// workgroup exits once the queue is drained, also when it is empty.
+__global__ __launch_bounds__(256) void k_fill_long(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
+                                                   const double *fw, const int64_t *bin_start,
+                                                   const double *sx, const double *sy, const double *sz,
+                                                   const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
+                                                   const int32_t *cnt, int lds_keys, uint64_t *pair_key,
+                                                   int32_t *pair_centre, uint64_t *pair_sum, int64_t *abs_bstart,
+                                                   uint32_t *status, int32_t *long_q) {
+  extern __shared__ uint64_t lds_u64[];
+  __shared__ CandLds lds_cand[4];
+  __shared__ int32_t lds_bmax;
+  __shared__ uint32_t lds_next;
+  const uint32_t nq = __atomic_load_n(status + 6, __ATOMIC_RELAXED);
+  for (;;) {
+    if (threadIdx.x == 0) lds_next = atomicAdd(status + 7, 1u);
+    __syncthreads();
+    const uint32_t q = lds_next;
+    if (q >= nq) break;
+    fill_centre<true>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
+                      pair_centre, pair_sum, abs_bstart, status, long_q, long_q[q], lds_u64, lds_cand, lds_bmax);
+    __syncthreads();  // lds_next, the keys and the bucket starts are reused
   }
 }
 
@@ -711,15 +778,31 @@ void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const
              L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, L.ptotal, L.status);
 }
 
+void launch_list_stats(const gmp_plan *p, const BatchDev &bt, const WsLayout &L, hipStream_t s) {
+  const int64_t nc = n_centres(bt), ncnt = nc * p->dev.E * p->dev.S;
+  int64_t blocks = (ncnt + 256 * 16 - 1) / (256 * 16);
+  blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
+  if (nc > 0)
+    GMP_LAUNCH("nbr_list_stats", k_list_stats, dim3((unsigned)blocks), dim3(256), 0, s, L.ptotal, nc, L.cnt, ncnt,
+               L.status);
+}
+
 void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int lds_keys,
-                 hipStream_t s) {
+                 int long_keys, hipStream_t s) {
   int nbk = p->dev.E * p->dev.S;
-  size_t smem = sizeof(uint64_t) * lds_keys + sizeof(int32_t) * (2 * nbk + 2);
   if (n_centres(bt) == 0) return;
+  uint64_t *pk = (nb.reverse && !point_mode(bt)) ? L.pair_key : (uint64_t *)nullptr;
+  size_t smem = sizeof(uint64_t) * lds_keys + sizeof(int32_t) * (2 * nbk + 2);
   GMP_LAUNCH("nbr_fill_sort", k_fill, dim3((unsigned)n_centres(bt)), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
-             L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, lds_keys,
-             (nb.reverse && !point_mode(bt)) ? L.pair_key : (uint64_t *)nullptr, L.pair_centre, L.pair_sum,
-             L.abs_bstart, L.status);
+             L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, lds_keys, pk, L.pair_centre,
+             L.pair_sum, L.abs_bstart, L.status, L.long_q);
+  if (long_keys > 0) {  // one workgroup per CU (its LDS takes most of the CU's), capped by the centre count
+    smem = sizeof(uint64_t) * long_keys + sizeof(int32_t) * (2 * nbk + 2);
+    const int64_t blocks = n_centres(bt) < 256 ? n_centres(bt) : 256;
+    GMP_LAUNCH("nbr_fill_long", k_fill_long, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
+               L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, long_keys, pk, L.pair_centre,
+               L.pair_sum, L.abs_bstart, L.status, L.long_q);
+  }
 }
 
 void launch_reverse(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int64_t n_pairs,

@@ -171,8 +171,11 @@ __device__ inline void radial_from_table(const PlanDev &P, int s, int e, float q
   }
 }
 
+// The wide mode's 35 FP64 accumulators and FP64 monomials fit three
+// wavefronts per SIMD (<= 168 VGPRs) once each monomial is accumulated as it
+// is formed; the bound keeps the compiler at that occupancy.
 template <int LMAX, int KB, int MODE, bool LDS, bool DENS, bool SCREEN, bool TAB = false>
-__global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
+__global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
                                                  const int32_t *astruct, double *partial, const int64_t *chunk_off,
                                                  int kc, unsigned long long *counter, const void *tab_global) {
   constexpr bool F64 = MODE == ACC_F64;
@@ -367,25 +370,25 @@ __global__ __launch_bounds__(256) void k_overlap(PlanDev P, BatchDev bt, NbrDev 
           }
         }
         }
-        TM mono[NM];
-        {
-          const TM xv = (TM)dx, yv = (TM)dy, zv = (TM)dz;
-          mono[0] = (TM)occj;  // the occupancy scales every monomial of the pair
+        // monomials degree by degree from their parents, each accumulated as
+        // soon as it is formed (only the previous degree's stay live)
+        double cd[LMAX + 1];
+        if constexpr (MODE != ACC_TWOSUM) {
 #pragma unroll
-          for (int m = 1; m < NM; ++m) {
+          for (int l = 0; l <= LMAX; ++l) cd[l] = (double)cl[l];
+        }
+        TM mono[NM];
+        const TM xv = (TM)dx, yv = (TM)dy, zv = (TM)dz;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          if (m == 0) {
+            mono[0] = (TM)occj;  // the occupancy scales every monomial of the pair
+          } else {
             const TM v = kMT.var[m] == 0 ? xv : (kMT.var[m] == 1 ? yv : zv);
             mono[m] = v * mono[kMT.parent[m]];
           }
-        }
-        if constexpr (MODE == ACC_TWOSUM) {
-#pragma unroll
-          for (int m = 0; m < NM; ++m) acc.add(m, cl[kMT.deg[m]] * mono[m]);
-        } else {
-          double cd[LMAX + 1];
-#pragma unroll
-          for (int l = 0; l <= LMAX; ++l) cd[l] = (double)cl[l];
-#pragma unroll
-          for (int m = 0; m < NM; ++m) acc.v[m] = fma(cd[kMT.deg[m]], mono[m], acc.v[m]);
+          if constexpr (MODE == ACC_TWOSUM) acc.add(m, cl[kMT.deg[m]] * mono[m]);
+          else acc.v[m] = fma(cd[kMT.deg[m]], mono[m], acc.v[m]);
         }
       }
       if (tb != ta) {  // the pass of slot sgm is complete: FP64 cross-lane reduction, store, restart

@@ -230,3 +230,30 @@ def test_bucket_longer_than_the_sort_is_unsupported(g):
     plan = g.GMPPlan.from_probes(p, "fp64")
     with pytest.raises(g.GMPError, match="UNSUPPORTED"):
         g.build_neighbors(plan, g.DeviceBatch.from_batch(b), g.Workspace())
+
+
+def test_nosync_bucket_longer_than_the_long_sort_is_stale(g):
+    """One atom in the 1.8 A cell with a ~27 A cutoff: one bucket of ~12,600
+    images, which the long-list sort holds.  Shrunk by 20% in place, the
+    no-sync rebuild of a captured step meets a bucket of ~24,000 images,
+    more than the 160 KB LDS sort holds: the captured step's status word
+    reports GMP_E_STALE, and a synchronous build GMP_E_UNSUPPORTED."""
+    p = _lattice_probes(1e-14)
+    b = gs.make_batch([(np.zeros((1, 3)), np.zeros(1, np.int32), np.eye(3) * 1.8, 7)])
+    plan = g.GMPPlan.from_probes(p, "fp64")
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb0 = g.build_neighbors(plan, db, ws)
+    assert 12000 < nb0.n_pairs < 14000
+    nbc = g.build_neighbors(plan, db, ws, capacity=3 * nb0.n_pairs)
+    step = g.CapturedStep(plan, db, ws, nbc, backward=False)
+    step.replay()
+    step.check_status()
+    db.xyz.mul_(0.8)
+    db.cell.mul_(0.8)
+    step.replay()
+    with pytest.raises(g.GMPError) as ei:
+        step.check_status()
+    assert ei.value.status == 8  # GMP_E_STALE
+    with pytest.raises(g.GMPError, match="UNSUPPORTED"):
+        g.build_neighbors(plan, db, g.Workspace())
