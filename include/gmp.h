@@ -141,11 +141,17 @@ typedef struct {
 } gmp_batch;
 
 /* Neighbour lists in canonical order; n_centres = n_atoms, or n_points
- * with reference points, and n_total = n_atoms (+ n_points).  For centre i, entries
- * [offsets[i], offsets[i+1]) are sorted by (shell, species of j, j, n1, n2, n3)
- * where shell(q) = number of cutoff slots with rc^2 < q, so the pairs each
+ * with reference points, and n_total = n_atoms (+ n_points).  The lists are
+ * stored in list-slot order: slot k holds the list of centre order[k] and
+ * slot[i] is the slot of centre i.  Atom centres are ordered by the cell list
+ * (by spatial bin, by atom index within a bin), so the lists of atoms that
+ * are near in space are near in memory; reference points keep their own
+ * order.  The list of centre i, entries [offsets[k], offsets[k+1]) with
+ * k = slot[i], is sorted by (shell, species of j, j, n1, n2, n3) where
+ * shell(q) = number of cutoff slots with rc^2 < q, so the pairs each cutoff
  * slot uses (q <= its rc^2) are a prefix of the list.  Bucket
- * b = shell * n_elements + species holds the entries of one (shell, species). */
+ * b = shell * n_elements + species holds the entries of one (shell, species).
+ * Neighbour indices j, wrap and rw are by atom (and point) index. */
 typedef struct {
   int64_t capacity;              /* [host] entries allocated in j, shift, reverse */
   int64_t n_pairs;               /* [host] total pairs, set by a synchronous build; a no-sync build sets
@@ -153,24 +159,28 @@ typedef struct {
                                     range by the capacity and the list ends on the device.  Callers
                                     that copy this struct must not pass a count from an earlier
                                     build after a no-sync rebuild */
-  int64_t *offsets;              /* [n_centres+1] */
+  int64_t *offsets;              /* [n_centres+1] per list slot */
   int32_t *j;                    /* [capacity] neighbour atom (global index) */
   int32_t *shift;                /* [capacity] bytes (n1, n2, n3, species_j), n_k signed, little endian;
                                     d = (Rw_j - Rw_i) + n1 a1 + n2 a2 + n3 a3 with wrapped positions */
-  int32_t *bucket_start;         /* [n_centres*(n_slots*n_elements+1)] bucket starts, local to
-                                    offsets[i]; the last entry is the list length */
-  int32_t *sigma_end;            /* [n_centres*n_slots] length of the prefix cutoff slot s uses, local */
+  int32_t *bucket_start;         /* [n_centres*(n_slots*n_elements+1)] per list slot k: bucket starts,
+                                    local to offsets[k]; the last entry is the list length */
+  int32_t *sigma_end;            /* [n_centres*n_slots] per list slot: length of the prefix cutoff
+                                    slot s uses, local */
   int32_t *wrap;                 /* [n_total*3] m_i: Rw_i = R_i - (m1 a1 + m2 a2 + m3 a3); atoms, then
                                     points */
   double *rw;                    /* [3*n_total] wrapped positions, SoA (x block, y block, z block) */
   int32_t *reverse;              /* [capacity] or NULL; required by gmp_features_backward.  Atoms as
-                                    centres: local index of (j, i, -n) in j's list.  Reference
+                                    centres: pair index (into j / shift) of the mirror (j, i, -n);
+                                    capacity must then stay below 2^31.  Reference
                                     points: the pair indices ordered by neighbour atom (stable), the
                                     order in which the backward gathers each atom's pairs */
   int64_t max_list;              /* [host] longest list of the last synchronous build (set by it); a
                                     no-sync build sizes its short-list sort for this many entries plus
                                     1/8 (0: 8,192 entries); lists that outgrow it are filled by the
                                     long-list kernel, whose sort takes the device's workgroup LDS */
+  int32_t *order;                /* [n_centres] centre whose list list-slot k holds (set by the build) */
+  int32_t *slot;                 /* [n_centres] list slot of centre i (set by the build) */
 } gmp_neighbors;
 
 /* Plan: validates the probe set, infers rc(sigma)^2 from the overlap

@@ -7,5 +7,5 @@ back to any CPU implementation.
 """
 from .gmp import (GMPPlan, DeviceBatch, Neighbors, Workspace, build_neighbors, features,  # noqa: F401
                   features_backward, GMPFunction, feature_labels, profile, GMPError, rebuild_neighbors_nosync,
-                  check_status, CapturedStep, build_reverse, feature_jacobian, pair_centres)
+                  check_status, CapturedStep, build_reverse, feature_jacobian, pair_centres, pairs_by_centre)
 from ._lib import LIB_PATH, EXPORTS, load  # noqa: F401

@@ -42,7 +42,7 @@ class BatchDesc(ctypes.Structure):
 class NbrDesc(ctypes.Structure):
     _fields_ = [("capacity", c_i64), ("n_pairs", c_i64), ("offsets", c_vp), ("j", c_vp), ("shift", c_vp),
                 ("bucket_start", c_vp), ("sigma_end", c_vp), ("wrap", c_vp), ("rw", c_vp), ("reverse", c_vp),
-                ("max_list", c_i64)]
+                ("max_list", c_i64), ("order", c_vp), ("slot", c_vp)]
 
 
 class Tuning(ctypes.Structure):

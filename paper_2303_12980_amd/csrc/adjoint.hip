@@ -156,9 +156,10 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
   for (;;) {
     const int64_t item = next_item(counter);
     if (item >= n_items) break;
-    const int64_t i = item / C;
-    const int c = (int)(item - i * C);
-    if (nb.offsets[i + 1] > nb.capacity) continue;  // list not written (overflowed no-sync build)
+    const int64_t k = item / C;   // list slot
+    const int c = (int)(item - k * C);
+    if (nb.offsets[k + 1] > nb.capacity) continue;  // list not written (overflowed no-sync build)
+    const int64_t i = nb.order[k];  // its centre
     {
       const T *src = (const T *)bcoef_ + (size_t)i * S * NB;
       for (int t = lane; t < S * NB; t += kWave) bcoef[t] = src[t];
@@ -170,11 +171,11 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
     const int pbc = bt.pbc[st] & 7;
     const double4 ri4 = rw4[g];
     const double rix = ri4.x, riy = ri4.y, riz = ri4.z;
-    const int64_t base = nb.offsets[i];
-    const int cnt = (int)(nb.offsets[i + 1] - base);
+    const int64_t base = nb.offsets[k];
+    const int cnt = (int)(nb.offsets[k + 1] - base);
     const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
     // sigma prefix ends, one per lane (lane s <-> sigma s)
-    const int end_lane = lane < S ? nb.sigma_end[i * S + lane] : 0;
+    const int end_lane = lane < S ? nb.sigma_end[k * S + lane] : 0;
     // pipeline: (jb, wb, rb) current step, (jc, wc) the step after
     const int32_t ii = (int32_t)g;  // idle lanes read the centre's own packed position
     int32_t jb = ii, wb = 0, jc = ii, wc = 0;
@@ -359,20 +360,23 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BatchDev bt, NbrDev nb, cons
   const int64_t a = xcd_contiguous(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int64_t N = bt.n_atoms;
   if (a >= N) return;
-  const int64_t base = nb.offsets[a];
-  // a list that ends past the capacity was not written (overflowed no-sync build)
-  const int64_t end = nb.offsets[a + 1] > nb.capacity ? base : nb.offsets[a + 1];
+  const int64_t k = nb.slot[a];  // the atom's list slot
+  const int64_t base = nb.offsets[k];
+  // a list that ends past the capacity was not written (overflowed no-sync
+  // build); mirrors lie in the written lists, below the capacity
+  const int64_t end = nb.offsets[k + 1] > nb.capacity ? base : nb.offsets[k + 1];
+  const int64_t total = nb.capacity;
   const int ma0 = nb.wrap[3 * a], ma1 = nb.wrap[3 * a + 1], ma2 = nb.wrap[3 * a + 2];
   double g[3] = {0.0, 0.0, 0.0};
   double cp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t p = base + lane; p < end; p += kWave) {
     const int32_t j = nb.j[p];
     const int32_t w = nb.shift[p];
-    const int32_t rv = nb.reverse[p];
+    const int32_t rv = nb.reverse[p];  // the mirror's pair index
     // a missing mirror is flagged by the neighbour build; never for a consistent list
-    if (rv < 0 || (int64_t)rv >= nb.offsets[j + 1] - nb.offsets[j] || nb.offsets[j + 1] > nb.capacity) continue;
+    if (rv < 0 || (int64_t)rv >= total) continue;
     const T *va = vbuf + (size_t)p * 4;
-    const T *vr = vbuf + (size_t)(nb.offsets[j] + rv) * 4;
+    const T *vr = vbuf + (size_t)rv * 4;
     const double v0 = (double)va[0], v1 = (double)va[1], v2 = (double)va[2];
     g[0] += (double)vr[0] - v0;
     g[1] += (double)vr[1] - v1;

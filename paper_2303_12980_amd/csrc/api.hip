@@ -26,7 +26,8 @@ int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs);
 void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, double *partial, int64_t *nch,
                     int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
                     int32_t *astruct, int64_t pairs_bound, hipStream_t s);
-void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off, void *features,
+void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off,
+                   const int32_t *order, void *features,
                    double *components, hipStream_t s);
 void *noalloc_scratch(size_t *bytes, hipError_t *err);
 size_t bwd_coef_elems(const gmp_plan *p, int64_t n_atoms);
@@ -121,6 +122,7 @@ WsLayout carve(const gmp_plan *p, int n_structs, int64_t N, int64_t M, int64_t c
   L.cnt = c.take<int32_t>((size_t)NC * p->dev.E * p->dev.S);
   L.ptotal = c.take<int64_t>(NC);
   L.long_q = c.take<int32_t>(NC);
+  L.sid_tmp = c.take<int32_t>(N);
   L.scan_aux = c.take<int64_t>(scan_aux_size(scan_n));
   L.partial = c.take<double>(partial_slots(p, NC, capacity));
   L.nch = c.take<int64_t>(NC);
@@ -609,9 +611,11 @@ gmp_status check_nbrs(const gmp_plan *p, const gmp_batch *b, const gmp_neighbors
   if (n->capacity < 0) return set_error(GMP_E_INVALID, "negative capacity");
   if (n->max_list < 0) return set_error(GMP_E_INVALID, "negative max_list");
   if (!n->offsets) return set_error(GMP_E_INVALID, "null neighbour offsets");
-  if (batch_centres(b) > 0 && (!n->bucket_start || !n->sigma_end || !n->wrap || !n->rw))
+  if (batch_centres(b) > 0 && (!n->bucket_start || !n->sigma_end || !n->wrap || !n->rw || !n->order || !n->slot))
     return set_error(GMP_E_INVALID, "null neighbour arrays");
   if (need_lists && n->capacity > 0 && (!n->j || !n->shift)) return set_error(GMP_E_INVALID, "null j/shift");
+  if (n->reverse && n->capacity > INT32_MAX)
+    return set_error(GMP_E_UNSUPPORTED, "the reverse-pair index holds 32-bit pair indices: capacity < 2^31");
   (void)p;
   return GMP_OK;
 }
@@ -643,6 +647,8 @@ NbrDev to_dev(const gmp_neighbors *n) {
   d.wrap = n->wrap;
   d.rw = n->rw;
   d.reverse = n->reverse;
+  d.order = n->order;
+  d.slot = n->slot;
   return d;
 }
 
@@ -831,7 +837,7 @@ gmp_status gmp_features(const gmp_plan *p, const gmp_batch *b, const gmp_neighbo
   NbrDev nb = to_dev(n);
   const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
   launch_overlap(p, bt, nb, L.partial, L.nch, L.chunk_off, L.scan_aux, L.counter, L.rw4, L.astruct, pairs, s);
-  launch_finish(p, N, L.partial, L.chunk_off, features, components, s);
+  launch_finish(p, N, L.partial, L.chunk_off, n->order, features, components, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "feature kernels");
   return GMP_OK;
@@ -868,7 +874,7 @@ gmp_status gmp_features_noalloc(const gmp_plan *p, const gmp_batch *b, const gmp
                                       " bytes of scratch; its fixed array holds " + std::to_string(cap));
   hipStream_t s = (hipStream_t)stream;
   launch_overlap(p, to_dev(b), to_dev(n), partial, nch, chunk_off, scan_aux, counter, rw4, astruct, pairs, s);
-  launch_finish(p, N, partial, chunk_off, features, components, s);
+  launch_finish(p, N, partial, chunk_off, n->order, features, components, s);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "feature kernels");
   return GMP_OK;

@@ -146,16 +146,20 @@ __host__ __device__ inline int64_t n_total(const BatchDev &b) { return b.n_atoms
 __host__ __device__ inline int64_t n_centres(const BatchDev &b) { return point_mode(b) ? b.n_points : b.n_atoms; }
 __host__ __device__ inline int64_t centre_base(const BatchDev &b) { return point_mode(b) ? b.n_atoms : 0; }
 
+// Lists are stored per slot: slot k holds the list of centre order[k], and
+// slot[i] is the slot of centre i (atoms: cell-list order, points: their own).
 struct NbrDev {
   int64_t capacity;
-  int64_t *offsets;
+  int64_t *offsets;        // [N+1] per slot
   int32_t *j;
   int32_t *shift;
-  int32_t *bucket_start;   // [N][S*E+1] local starts of buckets (shell h, species e) = h*E + e (S slots)
-  int32_t *sigma_end;      // [N][S] end of each cutoff slot's prefix
+  int32_t *bucket_start;   // [N][S*E+1] per slot: local starts of buckets (shell h, species e) = h*E + e
+  int32_t *sigma_end;      // [N][S] per slot: end of each cutoff slot's prefix
   int32_t *wrap;
   double *rw;
   int32_t *reverse;
+  int32_t *order;          // [N] centre of every slot
+  int32_t *slot;           // [N] slot of every centre
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -308,7 +312,8 @@ struct WsLayout {
   int32_t *sid, *ssp;     // bin-sorted atom index and species
   int32_t *cnt;           // [N][S][E] neighbours per bucket (shell, species)
   int64_t *ptotal;        // [N]
-  int32_t *long_q;        // [N] centres whose lists the long-list fill kernel writes
+  int32_t *long_q;        // [N] slots whose lists the long-list fill kernel writes
+  int32_t *sid_tmp;       // [N] atoms placed in their bins in arrival order (before the in-bin ordering)
   int64_t *scan_aux;      // scan block sums
   double *partial;        // overlap partial moments [chunk][sigma][monomial]
   int64_t *nch;           // [N] chunks per centre

@@ -52,9 +52,10 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
   for (;;) {
     const int64_t item = next_item(counter);
     if (item >= n_items) break;
-    const int64_t i = item / C;
-    const int c = (int)(item - i * C);
-    if (nb.offsets[i + 1] > nb.capacity) continue;  // list not written (overflowed no-sync build)
+    const int64_t k = item / C;  // list slot
+    const int c = (int)(item - k * C);
+    if (nb.offsets[k + 1] > nb.capacity) continue;  // list not written (overflowed no-sync build)
+    const int64_t i = nb.order[k];  // its centre
     {
       const T *src = (const T *)bcoef_ + (size_t)i * S * NB;
       for (int t = lane; t < S * NB; t += kWave) bcoef[t] = src[t];
@@ -65,10 +66,10 @@ __global__ __launch_bounds__(256) void k_jac_pairs(PlanDev P, BatchDev bt, NbrDe
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
     const double4 ri4 = rw4[g];
-    const int64_t base = nb.offsets[i];
-    const int cnt = (int)(nb.offsets[i + 1] - base);
+    const int64_t base = nb.offsets[k];
+    const int cnt = (int)(nb.offsets[k + 1] - base);
     const int clo = (int)((int64_t)cnt * c / C), chi = (int)((int64_t)cnt * (c + 1) / C);
-    const int end_lane = lane < S ? nb.sigma_end[i * S + lane] : 0;
+    const int end_lane = lane < S ? nb.sigma_end[k * S + lane] : 0;
     for (int p0 = clo; p0 < chi; p0 += kWave) {
       const int p = p0 + lane;
       const bool act = p < chi && base + p < ld;

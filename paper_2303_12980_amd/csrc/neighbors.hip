@@ -162,26 +162,54 @@ __global__ void k_wrap(BatchDev bt, const StructInfo *info, NbrDev nb, double *f
   fw[i] = f3[0];
   fw[N + i] = f3[1];
   fw[2 * N + i] = f3[2];
-  if (!atom) return;
+  if (!atom) {  // reference points keep their own list order
+    nb.order[k] = (int32_t)k;
+    nb.slot[k] = (int32_t)k;
+    return;
+  }
   int64_t bin = I.bin_base + ((int64_t)b[0] * I.nb[1] + b[1]) * I.nb[2] + b[2];
   bin_of[i] = (int32_t)bin;
   atomicAdd(&bin_count[bin], 1);
 }
 
-__global__ void k_scatter(BatchDev bt, NbrDev nb, const int32_t *bin_of, const int64_t *bin_start,
-                          int32_t *bin_fill, double *sx, double *sy, double *sz, int32_t *sid,
-                          int32_t *ssp, int n_elements) {
+// Atoms into their bins, in arrival order (the slot within a bin comes
+// from an atomic counter); k_bin_order then orders every bin by atom index.
+__global__ void k_scatter(BatchDev bt, const int32_t *bin_of, const int64_t *bin_start, int32_t *bin_fill,
+                          int32_t *sid_tmp) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= bt.n_atoms) return;
-  const int64_t N = n_total(bt);  // stride of rw
   int32_t b = bin_of[i];
   int64_t p = bin_start[b] + atomicAdd(&bin_fill[b], 1);
-  sx[p] = nb.rw[i];
-  sy[p] = nb.rw[N + i];
-  sz[p] = nb.rw[2 * N + i];
-  sid[p] = (int32_t)i;
-  int sp = bt.species[i];
-  ssp[p] = sp < 0 ? 0 : (sp >= n_elements ? n_elements - 1 : sp);  // out-of-range species are flagged in k_wrap
+  sid_tmp[p] = (int32_t)i;
+}
+
+// Deterministic cell-list order: the atom at arrival slot p of bin b goes to
+// position bin_start[b] + (number of atoms of b with a smaller index); the
+// bin-sorted SoA copies (wrapped positions, atom index, species) are written
+// there, and with atoms as centres the list-slot order follows it.  One
+// thread per arrival slot; the threads of one bin read the same members.
+__global__ void k_bin_order(BatchDev bt, NbrDev nb, const int32_t *bin_of, const int64_t *bin_start,
+                            const int32_t *sid_tmp, double *sx, double *sy, double *sz, int32_t *sid, int32_t *ssp,
+                            int n_elements) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= bt.n_atoms) return;
+  const int64_t N = n_total(bt);  // stride of rw
+  const int32_t i = sid_tmp[p];
+  const int32_t b = bin_of[i];
+  const int64_t lo = bin_start[b], hi = bin_start[b + 1];
+  int64_t r = 0;
+  for (int64_t q = lo; q < hi; ++q) r += sid_tmp[q] < i ? 1 : 0;
+  const int64_t k = lo + r;
+  sx[k] = nb.rw[i];
+  sy[k] = nb.rw[N + i];
+  sz[k] = nb.rw[2 * N + i];
+  sid[k] = i;
+  const int sp = bt.species[i];
+  ssp[k] = sp < 0 ? 0 : (sp >= n_elements ? n_elements - 1 : sp);  // out-of-range species are flagged in k_wrap
+  if (!point_mode(bt)) {
+    nb.order[k] = i;
+    nb.slot[i] = (int32_t)k;
+  }
 }
 
 // Range of virtual bins along axis k for a centre at fractional f.
@@ -337,7 +365,7 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
   const int nbk = P.E * P.S;
   int32_t *c = lds_cnt;
   const int64_t N = n_total(bt);  // stride of rw
-  // centre ci (atoms: in cell-list order; reference points: in index order), index g
+  // list slot k (atoms: cell-list order, each XCD one contiguous range), centre i, index g
   const int64_t k = xcd_contiguous(blockIdx.x, gridDim.x);
   const int64_t i = point_mode(bt) ? k : sid[k];
   const int64_t g = centre_base(bt) + i;
@@ -358,7 +386,7 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
   __syncthreads();
   int64_t tot = 0;
   for (int t = threadIdx.x; t < nbk; t += blockDim.x) {
-    cnt[i * nbk + t] = c[t];
+    cnt[k * nbk + t] = c[t];
     tot += c[t];
   }
   for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, kWave);
@@ -366,8 +394,8 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t all = 0;
-    for (int k = 0; k < nw; ++k) all += lds_tot[k];
-    ptotal[i] = all;
+    for (int u = 0; u < nw; ++u) all += lds_tot[u];
+    ptotal[k] = all;
   }
 }
 
@@ -510,21 +538,21 @@ __device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const N
                                    const double *sz, const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
                                    const int32_t *cnt, int lds_keys, uint64_t *pair_key, int32_t *pair_centre,
                                    uint64_t *pair_sum, int64_t *abs_bstart, uint32_t *status, int32_t *long_q,
-                                   int64_t i, uint64_t *keys, CandLds *lds_cand, int32_t &lds_bmax) {
+                                   int64_t k, int64_t i, uint64_t *keys, CandLds *lds_cand, int32_t &lds_bmax) {
   const int nbk = P.E * P.S;
   int32_t *bstart = (int32_t *)(keys + lds_keys);  // [nbk+1]
   int32_t *cursor = bstart + nbk + 1;              // [nbk]
   const int64_t g = centre_base(bt) + i;
   const int64_t N = n_total(bt);  // stride of rw
   const int tid = threadIdx.x, w = tid / kWave, nw = blockDim.x / kWave, lane = lane_id();
-  const int64_t base = nb.offsets[i];
-  const int64_t total = nb.offsets[i + 1] - base;
-  const bool overflow = nb.offsets[i + 1] > nb.capacity;
+  const int64_t base = nb.offsets[k];
+  const int64_t total = nb.offsets[k + 1] - base;
+  const bool overflow = nb.offsets[k + 1] > nb.capacity;
   if (w == 0) {  // bucket starts: exclusive scan of the centre's bucket counts
     int32_t carry = 0, vmax = 0;
     for (int b0 = 0; b0 < nbk; b0 += kWave) {
       const int b = b0 + lane;
-      const int32_t v = b < nbk ? cnt[i * nbk + b] : 0;
+      const int32_t v = b < nbk ? cnt[k * nbk + b] : 0;
       vmax = v > vmax ? v : vmax;
       int32_t incl = v;
 #pragma unroll
@@ -547,16 +575,16 @@ __device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const N
       if (RANGED && vmax > lds_keys) atomicOr(status, ST_SORT_SIZE);
       if ((int64_t)carry != total) atomicOr(status, ST_INTERNAL);
       // a list the short-list kernel cannot sort in one pass goes to the queue
-      if (!RANGED && !overflow && total > lds_keys) long_q[atomicAdd(status + 6, 1u)] = (int32_t)i;
+      if (!RANGED && !overflow && total > lds_keys) long_q[atomicAdd(status + 6, 1u)] = (int32_t)k;
     }
   }
   __syncthreads();
   if (!RANGED && !overflow && total > lds_keys) return;  // the long-list kernel writes this centre
   for (int b = tid; b <= nbk; b += blockDim.x) {
-    nb.bucket_start[i * (nbk + 1) + b] = bstart[b];
-    if (pair_key) abs_bstart[i * (nbk + 1) + b] = base + bstart[b];
+    nb.bucket_start[k * (nbk + 1) + b] = bstart[b];
+    if (pair_key) abs_bstart[k * (nbk + 1) + b] = base + bstart[b];
   }
-  for (int s = tid; s < P.S; s += blockDim.x) nb.sigma_end[i * P.S + s] = bstart[(P.rank_lt[s] + 1) * P.E];
+  for (int s = tid; s < P.S; s += blockDim.x) nb.sigma_end[k * P.S + s] = bstart[(P.rank_lt[s] + 1) * P.E];
   if (overflow) return;  // consumers skip centres whose list ends past the capacity
   if (RANGED && lds_bmax > lds_keys) {
     // a bucket does not fit the in-LDS sort: leave in-range placeholder
@@ -652,10 +680,10 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   extern __shared__ uint64_t lds_u64[];
   __shared__ CandLds lds_cand[4];
   __shared__ int32_t lds_bmax;
-  const int64_t kb = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int64_t i = point_mode(bt) ? kb : sid[kb];
+  const int64_t k = xcd_contiguous(blockIdx.x, gridDim.x);  // list slot
+  const int64_t i = point_mode(bt) ? k : sid[k];
   fill_centre<false>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
-                     pair_centre, pair_sum, abs_bstart, status, long_q, i, lds_u64, lds_cand, lds_bmax);
+                     pair_centre, pair_sum, abs_bstart, status, long_q, k, i, lds_u64, lds_cand, lds_bmax);
 }
 
 // Long-list fill: persistent workgroups take the queued centres one at a
@@ -678,8 +706,10 @@ __global__ __launch_bounds__(256) void k_fill_long(PlanDev P, BatchDev bt, NbrDe
     __syncthreads();
     const uint32_t q = lds_next;
     if (q >= nq) break;
+    const int64_t k = long_q[q];
     fill_centre<true>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
-                      pair_centre, pair_sum, abs_bstart, status, long_q, long_q[q], lds_u64, lds_cand, lds_bmax);
+                      pair_centre, pair_sum, abs_bstart, status, long_q, k, point_mode(bt) ? k : sid[k], lds_u64,
+                      lds_cand, lds_bmax);
     __syncthreads();  // lds_next, the keys and the bucket starts are reused
   }
 }
@@ -714,10 +744,9 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
   int ei = bt.species[i];
   ei = ei < 0 ? 0 : (ei >= P.E ? P.E - 1 : ei);
   const int b = h * P.E + ei;  // the mirror has the same q, hence the same shell
-  const int64_t *ab = abs_bstart + (int64_t)j * (nbk + 1);
+  const int64_t *ab = abs_bstart + (int64_t)nb.slot[j] * (nbk + 1);  // j's list slot
   const int64_t A = ab[b], Z = ab[b + 1];  // the bucket as global pair indices
   const uint64_t key = make_key(i, -n1, -n2, -n3, h);
-  const int64_t jb = nb.offsets[j];
   // two levels: the every-16th keys that fall inside the bucket (one or two
   // cache lines) select a 16-key window (one line), searched in turn
   int64_t lo = A, hi = Z;
@@ -742,8 +771,8 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
     atomicOr(status, ST_INTERNAL);
     return;
   }
-  nb.reverse[p] = (int32_t)(found - jb);
-  nb.reverse[found] = (int32_t)(p - nb.offsets[i]);
+  nb.reverse[p] = (int32_t)found;
+  nb.reverse[found] = (int32_t)p;
 }
 
 }  // namespace
@@ -766,8 +795,10 @@ void launch_wrap(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_
 void launch_scatter(const BatchDev &bt, const NbrDev &nb, const WsLayout &L, int n_elements, hipStream_t s) {
   int64_t blocks = (bt.n_atoms + 255) / 256;
   if (blocks == 0) return;
-  GMP_LAUNCH("nbr_scatter", k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, L.bin_of,
-             L.bin_start, L.bin_fill, L.sx, L.sy, L.sz, L.sid, L.ssp, n_elements);
+  GMP_LAUNCH("nbr_scatter", k_scatter, dim3((unsigned)blocks), dim3(256), 0, s, bt, L.bin_of, L.bin_start,
+             L.bin_fill, L.sid_tmp);
+  GMP_LAUNCH("nbr_bin_order", k_bin_order, dim3((unsigned)blocks), dim3(256), 0, s, bt, nb, L.bin_of, L.bin_start,
+             L.sid_tmp, L.sx, L.sy, L.sz, L.sid, L.ssp, n_elements);
 }
 
 void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const WsLayout &L, hipStream_t s) {

@@ -48,7 +48,7 @@ __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c
 // Chunks of one centre's list: fixed-size pieces of kc pairs (kc = 0: whole
 // list), so the decomposition of a centre depends on its own list only and
 // a batched launch sums in the same order as a launch over one structure.
-// Per atom: the number of chunks of its list (fixed-size pieces of kc pairs,
+// Per list slot: the number of chunks of its list (fixed-size pieces of kc pairs,
 // kc = 0: whole list, so the decomposition of a centre depends on its own
 // list only and a batched launch sums in the same order as a launch over one
 // structure), its structure, and its wrapped position as an AoS double4 (one
@@ -202,22 +202,23 @@ __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanD
   for (;;) {
     const int64_t qc = next_item(counter);
     if (qc >= n_items) break;
-    const int64_t i = centre_of_chunk(chunk_off, N, qc);
-    const int c = (int)(qc - chunk_off[i]);
+    const int64_t k = centre_of_chunk(chunk_off, N, qc);  // list slot
+    const int64_t i = nb.order[k];                         // its centre
+    const int c = (int)(qc - chunk_off[k]);
     const int st = astruct[cb + i];
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
     const double4 ri4 = rw4[cb + i];
     const double rix = ri4.x, riy = ri4.y, riz = ri4.z;
-    const int64_t base = nb.offsets[i];
-    const int cnt = (int)(nb.offsets[i + 1] - base);
+    const int64_t base = nb.offsets[k];
+    const int cnt = (int)(nb.offsets[k + 1] - base);
     const int clo = kc > 0 ? c * kc : 0;
     const int chi = kc > 0 ? (clo + kc < cnt ? clo + kc : cnt) : cnt;
     // per-item pass ends and sigma order, one per lane (lane t <-> t-th sigma by cutoff)
     int end_lane = clo, so_lane = 0;
     if (lane < S) {
       so_lane = P.sig_order[lane];
-      const int en = nb.sigma_end[i * S + so_lane];
+      const int en = nb.sigma_end[k * S + so_lane];
       end_lane = en < chi ? en : chi;
     }
     auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
@@ -408,7 +409,8 @@ __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanD
 // moment of the density slot as its component rho and |rho| as its feature.
 template <int LMAX, bool F64OUT>
 __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const double *partial,
-                                                const int64_t *chunk_off, void *features, double *components) {
+                                                const int64_t *chunk_off, const int32_t *order, void *features,
+                                                double *components) {
   extern __shared__ double lds_f[];
   // moment -> component maps of all orders and the multinomial weights,
   // staged in LDS once per workgroup (read with lane-varying indices)
@@ -418,12 +420,13 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
   for (int t = threadIdx.x; t < nmono(kMaxL); t += blockDim.x) lds_w[t] = P.weight[t];
   __syncthreads();
   const int w = threadIdx.x / kWave, lane = lane_id();
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;  // list slot
   constexpr int NM = nmono(LMAX);  // compile-time: the index splits below are not divisions
   const int S = P.S;
   double *mom = lds_f + (size_t)w * (S * NM + P.ncomp_total);
   double *mu = mom + S * NM;
   const bool live = i < N;
+  const int64_t row = live ? order[i] : 0;  // the slot's centre: its row of the outputs
   if (live) {
     for (int t = lane; t < S * NM; t += kWave) {
       const int s = t / NM, m = t - s * NM;
@@ -453,7 +456,7 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
         for (int mm = 0; mm < nc; ++mm) v += Tl[mm] * ms[mm];
       }
       mu[t] = v;
-      if (components) components[(size_t)i * P.ncomp_total + t] = v;
+      if (components) components[(size_t)row * P.ncomp_total + t] = v;
     }
   }
   wave_lds_sync();
@@ -472,8 +475,8 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
         for (int cc = 0; cc < nc; ++cc) a += lds_w[doff(l) + cc] * mv[cc] * mv[cc];
         F = sqrt(a);
       }
-      if (F64OUT) ((double *)features)[(size_t)i * P.nf + t] = F;
-      else ((float *)features)[(size_t)i * P.nf + t] = (float)F;
+      if (F64OUT) ((double *)features)[(size_t)row * P.nf + t] = F;
+      else ((float *)features)[(size_t)row * P.nf + t] = (float)F;
     }
   }
 }
@@ -621,19 +624,19 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
              (const int32_t *)astruct, partial, chunk_off, kc, counter, tab);
 }
 
-void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off, void *features,
-                   double *components, hipStream_t s) {
+void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off,
+                   const int32_t *order, void *features, double *components, hipStream_t s) {
   if (N == 0) return;
   const int NM = nmono(p->dev.lmax);
   size_t smem = sizeof(double) * 4 * (size_t)(p->dev.S * NM + p->dev.ncomp_total);
   int64_t blocks = (N + 3) / 4;
-  using FinishFn = void (*)(PlanDev, int64_t, const double *, const int64_t *, void *, double *);
+  using FinishFn = void (*)(PlanDev, int64_t, const double *, const int64_t *, const int32_t *, void *, double *);
   static const FinishFn fns[2][kMaxL + 1] = {
       {k_finish<0, false>, k_finish<1, false>, k_finish<2, false>, k_finish<3, false>, k_finish<4, false>},
       {k_finish<0, true>, k_finish<1, true>, k_finish<2, true>, k_finish<3, true>, k_finish<4, true>}};
   const int lm = p->dev.lmax < 0 ? 0 : (p->dev.lmax > kMaxL ? kMaxL : p->dev.lmax);
   GMP_LAUNCH("norm", fns[p->prec == GMP_FP64 ? 1 : 0][lm], dim3((unsigned)blocks), dim3(256), smem, s, p->dev, N,
-             partial, chunk_off, features, components);
+             partial, chunk_off, order, features, components);
 }
 
 }  // namespace gmp

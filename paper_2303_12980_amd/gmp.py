@@ -22,7 +22,8 @@ from ._lib import GMPError, check
 
 __all__ = ["GMPPlan", "DeviceBatch", "Neighbors", "Workspace", "build_neighbors", "rebuild_neighbors_nosync",
            "build_reverse",
-           "check_status", "features", "features_backward", "feature_jacobian", "pair_centres", "GMPFunction",
+           "check_status", "features", "features_backward", "feature_jacobian", "pair_centres", "pairs_by_centre",
+           "GMPFunction",
            "CapturedStep", "feature_labels",
            "profile", "GMPError"]
 
@@ -249,6 +250,9 @@ class Neighbors:
         self.sigma_end = torch.empty(N * S, dtype=torch.int32, device=dev)
         self.wrap = torch.empty(NT * 3, dtype=torch.int32, device=dev)
         self.rw = torch.empty(3 * NT, dtype=torch.float64, device=dev)
+        # list slots: slot k holds the list of centre order[k]; slot[i] is the slot of centre i
+        self.order = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
+        self.slot = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
         # reference points need no reverse index (the backward orders pairs by neighbour itself)
         reverse = reverse and batch.point_offsets is None
         self.reverse = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev) if reverse else None
@@ -260,7 +264,13 @@ class Neighbors:
         return _lib.NbrDesc(self.capacity, self.n_pairs if self.synced else 0, self.offsets.data_ptr(), self.j.data_ptr(),
                             self.shift.data_ptr(), self.bucket_start.data_ptr(), self.sigma_end.data_ptr(),
                             self.wrap.data_ptr(), self.rw.data_ptr(),
-                            self.reverse.data_ptr() if self.reverse is not None else 0, self.max_list)
+                            self.reverse.data_ptr() if self.reverse is not None else 0, self.max_list,
+                            self.order.data_ptr(), self.slot.data_ptr())
+
+    def list_range(self, i):
+        """[lo, hi) of centre i's list in j / shift (host read)."""
+        k = int(self.slot[i])
+        return int(self.offsets[k]), int(self.offsets[k + 1])
 
     # host-side views for tests
     def shifts_numpy(self):
@@ -387,10 +397,24 @@ def feature_jacobian(plan: GMPPlan, batch: DeviceBatch, nb: Neighbors, ws: Works
 
 
 def pair_centres(nb: Neighbors):
-    """Centre index of every pair of the lists (int64 [n_pairs])."""
+    """Centre index of every pair of the lists (int64 [n_pairs]; the lists
+    are stored per list slot, slot k holding centre order[k]'s)."""
     offs = nb.offsets
     cnt = offs[1:] - offs[:-1]
-    return torch.repeat_interleave(torch.arange(len(cnt), device=offs.device, dtype=torch.int64), cnt)
+    slots = torch.repeat_interleave(torch.arange(len(cnt), device=offs.device, dtype=torch.int64), cnt)
+    return nb.order[: len(cnt)].long()[slots]
+
+
+def pairs_by_centre(nb: Neighbors, centres=None):
+    """Pair indices of the given centres' lists (default: all), centre after
+    centre in the given order, each list in its own order (int64, device)."""
+    offs = nb.offsets
+    N = offs.numel() - 1
+    c = torch.arange(N, device=offs.device) if centres is None else torch.as_tensor(centres, device=offs.device)
+    k = nb.slot[:N].long()[c.long()]
+    lo, cnt = offs[k], offs[k + 1] - offs[k]
+    start = torch.repeat_interleave(lo - (torch.cumsum(cnt, 0) - cnt), cnt)
+    return start + torch.arange(int(cnt.sum()), device=offs.device)
 
 
 class GMPFunction(torch.autograd.Function):

@@ -25,16 +25,20 @@ def run_path(g, batch_np, probes, precision, ws, reverse=True, tuning=None):
 
 
 def check_reverse(nb):
-    """Every pair's reverse entry is its mirror (j, i, -n) -- checked on the GPU."""
+    """Every pair's reverse entry is its mirror (j, i, -n) -- checked on the GPU.
+    Lists are stored per list slot: slot k holds the list of centre order[k]."""
     import torch
     P = nb.n_pairs
     offs = nb.offsets
     cnt = offs[1:] - offs[:-1]
-    centre = torch.repeat_interleave(torch.arange(len(cnt), device=offs.device, dtype=torch.int64), cnt)
+    N = len(cnt)
+    order, slot = nb.order[:N].long(), nb.slot[:N].long()
+    assert torch.equal(order[slot], torch.arange(N, device=offs.device)), "order and slot are not inverse"
+    centre = order[torch.repeat_interleave(torch.arange(N, device=offs.device, dtype=torch.int64), cnt)]
     J = nb.j[:P].long()
-    rev = nb.reverse[:P].long()
-    assert bool((rev >= 0).all()) and bool((rev < cnt[J]).all())
-    tgt = offs[J] + rev
+    tgt = nb.reverse[:P].long()  # pair index of the mirror
+    kj = slot[J]
+    assert bool((tgt >= offs[kj]).all()) and bool((tgt < offs[kj + 1]).all()), "mirror outside j's list"
     assert bool((J[tgt] == centre).all())
     w = nb.shift[:P]
     nk = [((w >> (8 * k)) & 0xff).to(torch.int8) for k in range(3)]
@@ -56,6 +60,7 @@ def check_neighbors(nb, batch_np, probes, centres=None):
         check_reverse(nb)
     wrap_all = nb.wrap.view(-1, 3)
     rw_all = nb.rw.view(3, -1)
+    slot = nb.slot.cpu().numpy()
     checked = 0
     for s in range(batch_np.n_structs):
         loc = None if centres is None else centres.get(s, [])
@@ -71,7 +76,8 @@ def check_neighbors(nb, batch_np, probes, centres=None):
         for li in loc:
             gi = a0 + li
             ref = oracle.neighbors(struct, rc2, li)
-            lo, hi = int(offs[gi]), int(offs[gi + 1])
+            ki = int(slot[gi])  # list slot of atom gi
+            lo, hi = int(offs[ki]), int(offs[ki + 1])
             assert hi - lo == len(ref["j"]), (s, li, hi - lo, len(ref["j"]))
             J = nb.j[lo:hi].cpu().numpy()
             w = nb.shift[lo:hi].cpu().numpy().view(np.uint8).reshape(-1, 4)
@@ -80,8 +86,8 @@ def check_neighbors(nb, batch_np, probes, centres=None):
             assert np.array_equal(J, ref["j"] + a0)
             assert np.array_equal(n, ref["n"])
             assert np.array_equal(e, ref["e"])
-            bs = nb.bucket_start[gi * (S * E + 1):(gi + 1) * (S * E + 1)].cpu().numpy()
-            se = nb.sigma_end[gi * S:(gi + 1) * S].cpu().numpy()
+            bs = nb.bucket_start[ki * (S * E + 1):(ki + 1) * (S * E + 1)].cpu().numpy()
+            se = nb.sigma_end[ki * S:(ki + 1) * S].cpu().numpy()
             bucket = ref["shell"] * E + ref["e"]
             assert np.array_equal(bs, np.searchsorted(np.sort(bucket), np.arange(S * E + 1), side="left"))
             assert np.array_equal(se, np.array([int(np.sum(ref["q"] <= rc2[t])) for t in range(S)]))
@@ -123,7 +129,7 @@ def check_lists_many(nb, batch_np, probes, s, local=None):
     assert nb.rw.view(3, -1)[:, a0:a1].t().contiguous().cpu().numpy().tobytes() == orw.tobytes()
     ref = oracle.neighbors_many(struct, rc2, loc)
     offs = nb.offsets.cpu().numpy()
-    gi = a0 + loc.astype(np.int64)
+    gi = nb.slot.cpu().numpy()[a0 + loc.astype(np.int64)].astype(np.int64)  # list slots of the centres
     lo, hi = offs[gi], offs[gi + 1]
     cnt = hi - lo
     assert np.array_equal(cnt, np.diff(ref["offs"])), "list lengths differ"

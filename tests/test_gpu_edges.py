@@ -93,7 +93,7 @@ def test_nosync_overflow_is_reported(g):
     g.check_status(ws)
     Fref, _ = g.features(plan, db, nb, ws)
     offs = small.offsets.cpu().numpy()
-    fits = offs[1:] <= small.capacity
+    fits = (offs[1:] <= small.capacity)[small.slot.cpu().numpy()]  # per list slot -> per centre
     assert fits.any() and not fits.all()
     Fh, Fr = F.cpu().numpy(), Fref.cpu().numpy()
     assert np.array_equal(Fh[fits], Fr[fits])
@@ -125,7 +125,7 @@ def test_nosync_overflow_with_points(g):
         g.check_status(ws)
     Fref, _ = g.features(plan, db, nb, ws)
     offs = small.offsets.cpu().numpy()
-    fits = offs[1:] <= small.capacity
+    fits = (offs[1:] <= small.capacity)[small.slot.cpu().numpy()]  # per list slot -> per centre
     assert fits.any() and not fits.all()
     Fh, Fr = F.cpu().numpy(), Fref.cpu().numpy()
     assert np.array_equal(Fh[fits], Fr[fits])
