@@ -34,6 +34,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# autotuner choices of this run (a fresh box searches; the file is a scratch cache)
+TUNE_CACHE = os.path.join(ROOT, "gpurun_out", "tune_cache.json")
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed issue)
 # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz (this build issues no packed FP32)
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -92,6 +94,7 @@ def _median_ms(fn, reps, torch):
 
 
 def other_workloads(g, gs, torch, steps=5, warmup=2):
+    from paper_2303_12980_amd import autotune
     """Graph-replayed fwd+bwd step (FP32 compensated, neighbour build
     included) on the differentiation workload (512 periodic triclinic
     structures of 32-200 atoms, l=0..3 x 6 sigma) and on the large single
@@ -105,6 +108,8 @@ def other_workloads(g, gs, torch, steps=5, warmup=2):
         db = g.DeviceBatch.from_batch(batch)
         plan = g.GMPPlan.from_probes(probes, "fp32c")
         ws = g.Workspace()
+        tune = autotune.autotune(plan, db, ws, candidates=autotune.STEP_CANDIDATES, backward=True, reps=2,
+                                 cache_path=TUNE_CACHE)
         nb = g.build_neighbors(plan, db, ws)
         G = torch.as_tensor(np.random.default_rng(7).standard_normal((batch.n_atoms, probes.n_features)),
                             device="cuda")
@@ -119,10 +124,11 @@ def other_workloads(g, gs, torch, steps=5, warmup=2):
         g.check_status(ws)
         af = batch.n_atoms * probes.n_features
         out[name] = {"workload": label, "atoms": batch.n_atoms, "features_per_atom": probes.n_features,
-                     "pairs": int(nb.n_pairs), "fwd_bwd_ms": t_fb, "fwd_ms": t_fo,
+                     "pairs": int(nb.n_pairs), "tuning": dict(tune["tuning"], searched=not tune["cached"]),
+                     "fwd_bwd_ms": t_fb, "fwd_ms": t_fo,
                      "atoms_features_per_s_fwd_bwd": af / (t_fb * 1e-3), "atoms_features_per_s_fwd": af / (t_fo * 1e-3)}
-        print(f"[bench] {name}: {batch.n_atoms} atoms, {nb.n_pairs} pairs (generated in {gen_s:.1f}s): "
-              f"fwd+bwd {t_fb:.2f} ms, fwd {t_fo:.2f} ms", file=sys.stderr, flush=True)
+        print(f"[bench] {name}: {batch.n_atoms} atoms, {nb.n_pairs} pairs (generated in {gen_s:.1f}s), tuning "
+              f"{tune['tuning']}: fwd+bwd {t_fb:.2f} ms, fwd {t_fo:.2f} ms", file=sys.stderr, flush=True)
         del fb, fo, nb, nbf, ws, db, G
         torch.cuda.empty_cache()
     return out
@@ -391,7 +397,7 @@ def batched_vs_per_structure(g, gs, torch):
     ws = g.Workspace()
     tune = autotune.autotune(plan, db, ws, backward=False, reps=2, candidates=[
         dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0) for c in (1024, 2048, 4096) for b in (2, 3)],
-        cache_path=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
+        cache_path=TUNE_CACHE)
     print(f"[bench] autotuned {tune['tuning']} ({'cached' if tune['cached'] else 'searched'})",
           file=sys.stderr, flush=True)
     nb = g.build_neighbors(plan, db, ws, reverse=False)
@@ -574,9 +580,17 @@ def main():
     db = g.DeviceBatch.from_batch(batch, dev)
     G = torch.as_tensor(np.random.default_rng(7).standard_normal((N, nf)), device=dev)
 
+    from paper_2303_12980_amd import autotune
+    tunings = {}
+
     def make(prec):
         plan = g.GMPPlan.from_probes(probes, prec)
         w = g.Workspace(dev)
+        tune = autotune.autotune(plan, db, w, candidates=autotune.STEP_CANDIDATES, backward=True, reps=3,
+                                 cache_path=TUNE_CACHE)
+        tunings[prec] = dict(tune["tuning"], searched=not tune["cached"], step_ms=tune["ms"])
+        print(f"[bench] {prec} autotuned {tune['tuning']} ({'cached' if tune['cached'] else 'searched'})",
+              file=sys.stderr, flush=True)
         nb = g.build_neighbors(plan, db, w)
         return plan, w, nb
 
@@ -716,6 +730,7 @@ def main():
             "fp32c_fwd_kernels_only": atoms_feat / (1e-3 * (kern_f["overlap"]["avg_ms"] + kern_f["norm"]["avg_ms"])),
         },
         "timings_ms": results,
+        "tuning": tunings,
         "accuracy": acc,
         "kernels_fp32c_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in kern.items()},
     }

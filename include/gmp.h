@@ -212,13 +212,16 @@ gmp_status gmp_plan_info(const gmp_plan *plan, int32_t *n_features, int32_t *n_c
  *  bin_divisor:   cell-list bin edge is about rc_max / bin_divisor (1..4).
  *  blocks_per_cu: workgroups per compute unit of the persistent kernels
  *                 (0 = as many as fit).
+ *  adj_items:     work items per centre of the adjoint and Jacobian pair
+ *                 kernels (equal pieces of the list; 0 = automatic: about
+ *                 8,192 items over the batch, none shorter than chunk_pairs).
  * The workspace size depends on the tuning.  Changing the tuning is not
  * thread-safe with concurrent calls on the plan. */
 typedef struct {
   int32_t chunk_pairs;
   int32_t bin_divisor;
   int32_t blocks_per_cu;
-  int32_t reserved;              /* must be 0 */
+  int32_t adj_items;             /* 0..64 */
 } gmp_tuning;
 gmp_status gmp_plan_get_tuning(const gmp_plan *plan, gmp_tuning *out);
 gmp_status gmp_plan_set_tuning(gmp_plan *plan, const gmp_tuning *t);

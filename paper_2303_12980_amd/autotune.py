@@ -1,5 +1,6 @@
 """Autotuner of the library's tuning knobs (chunk size of the per-centre
-work items, cell-list bin size, persistent grid size).
+work items of the forward, cell-list bin size, persistent grid size, work
+items per centre of the adjoint).
 
 Candidates are timed with the HIP events the library records around its
 own launches on the current stream (neighbour build + forward, optionally
@@ -23,9 +24,23 @@ import torch
 from . import gmp as _g
 
 DEFAULT_CANDIDATES = [
-    dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0)
+    dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0, adj_items=0)
     for c in (0, 512, 1024, 2048, 4096) for b in (2, 3, 4)
-] + [dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=k) for k in (1, 2)]
+] + [dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=k, adj_items=0) for k in (1, 2)]
+
+# a whole forward + backward step: the forward's chunking and the cell-list
+# bins crossed with the adjoint's items per centre
+STEP_CANDIDATES = [
+    dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0, adj_items=a)
+    for c in (1024, 2048, 0) for b in (2, 3) for a in (0, 2)
+]
+
+_DEFAULT = dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=0, adj_items=0)
+
+
+def _full(cand: Dict) -> Dict:
+    """A candidate with every knob set (unnamed knobs at their defaults)."""
+    return dict(_DEFAULT, **cand)
 
 
 def _cache_path():
@@ -36,15 +51,16 @@ def _bucket(x: float) -> int:
     return int(math.floor(math.log2(max(1.0, x))))
 
 
-def tuning_key(plan, batch, nb) -> str:
+def tuning_key(plan, batch, nb, backward: bool = True) -> str:
     """Device, precision, l_max, sigma count, species count, largest
-    primitive count per element, and log2 buckets of the atom count and of
-    the mean neighbour-list length."""
+    primitive count per element, log2 buckets of the atom count and of the
+    mean neighbour-list length, and whether the adjoint is part of the
+    timed step."""
     dev = torch.cuda.get_device_name(batch.species.device)
     avg = nb.n_pairs / max(1, batch.n_atoms)
     kmax = int(max(int(b) - int(a) for a, b in zip(plan._poff[:-1], plan._poff[1:])))
     return (f"{dev}|{plan.precision}|L{int(max(plan.orders))}|S{plan.n_slots}|E{plan.n_elements}|K{kmax}"
-            f"|N{_bucket(batch.n_atoms)}|avg{_bucket(avg)}")
+            f"|N{_bucket(batch.n_atoms)}|avg{_bucket(avg)}|{'step' if backward else 'fwd'}")
 
 
 def _load(path):
@@ -79,10 +95,10 @@ def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backw
     Returns {"tuning": ..., "ms": ..., "key": ..., "cached": bool, "tried": [...]}."""
     path = cache_path or _cache_path()
     nb = _g.build_neighbors(plan, batch, ws)
-    key = tuning_key(plan, batch, nb)
+    key = tuning_key(plan, batch, nb, backward)
     cache = _load(path)
     if not force and key in cache:
-        plan.set_tuning(**cache[key]["tuning"])
+        plan.set_tuning(**_full(cache[key]["tuning"]))
         return dict(cache[key], key=key, cached=True)
     if os.environ.get("GMP_AUTOTUNE", "1") == "0":
         return dict(tuning=plan.get_tuning(), ms=None, key=key, cached=False, tried=[])
@@ -91,11 +107,12 @@ def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backw
     best = None
     t0 = time.time()
     for cand in (candidates or DEFAULT_CANDIDATES):
+        cand = _full(cand)
         plan.set_tuning(**cand)
         ms = _time_config(plan, batch, ws, G, reps, backward)
-        tried.append(dict(tuning=dict(cand), ms=ms))
+        tried.append(dict(tuning=cand, ms=ms))
         if best is None or ms < best[1]:
-            best = (dict(cand), ms)
+            best = (cand, ms)
     plan.set_tuning(**best[0])
     entry = dict(tuning=best[0], ms=best[1], search_s=time.time() - t0)
     cache[key] = entry

@@ -534,7 +534,7 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   p->tuning.chunk_pairs = 2048;
   p->tuning.bin_divisor = 2;
   p->tuning.blocks_per_cu = 0;
-  p->tuning.reserved = 0;
+  p->tuning.adj_items = 0;
   *out = p;
   return GMP_OK;
 }
@@ -566,7 +566,7 @@ gmp_status gmp_plan_set_tuning(gmp_plan *p, const gmp_tuning *t) {
   if (t->chunk_pairs < 0) return set_error(GMP_E_INVALID, "chunk_pairs must be >= 0");
   if (t->bin_divisor < 1 || t->bin_divisor > 4) return set_error(GMP_E_INVALID, "bin_divisor must be 1..4");
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return set_error(GMP_E_INVALID, "blocks_per_cu must be 0..64");
-  if (t->reserved != 0) return set_error(GMP_E_INVALID, "reserved tuning field must be 0");
+  if (t->adj_items < 0 || t->adj_items > 64) return set_error(GMP_E_INVALID, "adj_items must be 0..64");
   p->tuning = *t;
   return GMP_OK;
 }
@@ -673,6 +673,19 @@ gmp_status status_to_error(uint32_t st) {
 int64_t nosync_sort_size(int64_t max_list) {
   const int64_t extra = max_list / 8 > 64 ? max_list / 8 : 64;
   return max_list + extra;
+}
+
+// Work items per centre of the adjoint and Jacobian pair kernels: the
+// tuning's adj_items, else about 8,192 items over the batch with none
+// shorter than chunk_pairs (256 when unsplit) on average.
+int64_t adjoint_items(const gmp_plan *p, int64_t pairs, int64_t N) {
+  if (p->tuning.adj_items > 0) return p->tuning.adj_items;
+  const int64_t chunk = p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 256;
+  int64_t by_pairs = (pairs / N) / chunk;
+  if (by_pairs < 1) by_pairs = 1;
+  const int64_t want = (8192 + N - 1) / N;
+  const int64_t C = want < by_pairs ? want : by_pairs;
+  return C < 1 ? 1 : C;
 }
 
 // LDS a workgroup may hold on this device (160 KB on gfx950)
@@ -906,12 +919,7 @@ gmp_status gmp_features_backward(const gmp_plan *p, const gmp_batch *b, const gm
   const int64_t pairs = n->n_pairs > 0 && n->n_pairs <= n->capacity ? n->n_pairs : n->capacity;
   if (b->point_offsets && pairs > 0xffffffffLL)
     return set_error(GMP_E_UNSUPPORTED, "at most 2^32-1 pairs in the backward of reference points");
-  int64_t chunk = p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 256;
-  int64_t by_pairs = (pairs / N) / chunk;
-  if (by_pairs < 1) by_pairs = 1;
-  int64_t want = (8192 + N - 1) / N;
-  int64_t C = want < by_pairs ? want : by_pairs;
-  if (C < 1) C = 1;
+  const int64_t C = adjoint_items(p, pairs, N);
   launch_backward(p, bt, nb, components, grad_features, grad_pos, grad_cell, L, (int)C, pairs, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "adjoint kernels");
@@ -936,12 +944,7 @@ gmp_status gmp_feature_jacobian(const gmp_plan *p, const gmp_batch *b, const gmp
   if (L.bytes > ws_bytes) return set_error(GMP_E_NOMEM, "workspace too small");
   BatchDev bt = to_dev(b);
   NbrDev nb = to_dev(n);
-  int64_t chunk = p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 256;
-  int64_t by_pairs = (pairs / N) / chunk;
-  if (by_pairs < 1) by_pairs = 1;
-  int64_t want = (8192 + N - 1) / N;
-  int64_t C = want < by_pairs ? want : by_pairs;
-  if (C < 1) C = 1;
+  const int64_t C = adjoint_items(p, pairs, N);
   launch_jacobian(p, bt, nb, components, jac, ld, L, (int)C, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "jacobian kernels");

@@ -110,12 +110,13 @@ class GMPPlan:
     def get_tuning(self) -> dict:
         t = _lib.Tuning()
         check(_lib.load().gmp_plan_get_tuning(self._h, ctypes.byref(t)))
-        return dict(chunk_pairs=t.chunk_pairs, bin_divisor=t.bin_divisor, blocks_per_cu=t.blocks_per_cu)
+        return dict(chunk_pairs=t.chunk_pairs, bin_divisor=t.bin_divisor, blocks_per_cu=t.blocks_per_cu,
+                    adj_items=t.adj_items)
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
         cur.update(kw)
-        t = _lib.Tuning(cur["chunk_pairs"], cur["bin_divisor"], cur["blocks_per_cu"], 0)
+        t = _lib.Tuning(cur["chunk_pairs"], cur["bin_divisor"], cur["blocks_per_cu"], cur["adj_items"])
         check(_lib.load().gmp_plan_set_tuning(self._h, ctypes.byref(t)))
 
     def workspace_bytes(self, n_structs, n_atoms, capacity, n_points=0) -> int:

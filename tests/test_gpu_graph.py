@@ -103,8 +103,9 @@ def test_autotune_choice_and_cache(g, tmp_path):
     db = g.DeviceBatch.from_batch(b)
     ws = g.Workspace()
     cache = str(tmp_path / "tune.json")
-    cands = [dict(chunk_pairs=0, bin_divisor=2, blocks_per_cu=0), dict(chunk_pairs=256, bin_divisor=3, blocks_per_cu=0),
-             dict(chunk_pairs=1024, bin_divisor=2, blocks_per_cu=2)]
+    cands = [dict(chunk_pairs=0, bin_divisor=2, blocks_per_cu=0, adj_items=0),
+             dict(chunk_pairs=256, bin_divisor=3, blocks_per_cu=0, adj_items=2),
+             dict(chunk_pairs=1024, bin_divisor=2, blocks_per_cu=2, adj_items=0)]
     r = autotune.autotune(plan, db, ws, candidates=cands, reps=2, cache_path=cache)
     assert not r["cached"] and len(r["tried"]) == 3
     assert r["tuning"] in cands and plan.get_tuning() == r["tuning"]
