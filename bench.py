@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--sample-centres", type=int, default=48)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-per-structure comparison")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the eager steps whose reverse search runs on a second stream (kernel traces "
+                         "then hold no launches slowed by a concurrent kernel)")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads (512 structures, 1e5 atoms)")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the order -1 (local density), occupancy (disordered), reference-point, Jacobian and "
@@ -588,9 +591,10 @@ def main():
         w = g.Workspace(dev)
         tune = autotune.autotune(plan, db, w, candidates=autotune.STEP_CANDIDATES, backward=True, reps=3,
                                  cache_path=TUNE_CACHE)
-        tunings[prec] = dict(tune["tuning"], searched=not tune["cached"], step_ms=tune["ms"])
-        print(f"[bench] {prec} autotuned {tune['tuning']} ({'cached' if tune['cached'] else 'searched'})",
-              file=sys.stderr, flush=True)
+        tunings[prec] = dict(tune["tuning"], step_ms=tune["ms"])
+        how = "cached" if tune["cached"] else ("search off: defaults" if tune["ms"] is None else "searched")
+        tunings[prec]["how"] = how
+        print(f"[bench] {prec} autotuned {tune['tuning']} ({how})", file=sys.stderr, flush=True)
         nb = g.build_neighbors(plan, db, w)
         return plan, w, nb
 
@@ -631,7 +635,8 @@ def main():
         r = {}
         r["eager_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True), args.steps, args.warmup)
         r["eager_fwd_ms"] = wall_ms(lambda: eager_step(plan, w, nbf, False), args.steps, args.warmup)
-        r["eager_split_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True, True), args.steps, args.warmup)
+        if not args.no_split:
+            r["eager_split_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True, True), args.steps, args.warmup)
         fb = g.CapturedStep(plan, db, w, nb, backward=True, G=G)
         r["graph_fwd_bwd_ms"] = wall_ms(fb.replay, args.steps, args.warmup)
         fo = g.CapturedStep(plan, db, w, nbf, backward=False)
@@ -641,7 +646,7 @@ def main():
         graphs[prec] = (plan, w, nb, fb, nbf)
         print(f"[bench] {prec}: graph fwd+bwd {r['graph_fwd_bwd_ms']:.3f} ms, fwd {r['graph_fwd_ms']:.3f} ms; "
               f"eager fwd+bwd {r['eager_fwd_bwd_ms']:.3f} ms (reverse on a second stream: "
-              f"{r['eager_split_fwd_bwd_ms']:.3f} ms)", file=sys.stderr, flush=True)
+              f"{r.get('eager_split_fwd_bwd_ms', float('nan')):.3f} ms)", file=sys.stderr, flush=True)
 
     def kernel_profile(prec, backward, steps=5):
         plan, w, nb, _, nbf = graphs[prec]
