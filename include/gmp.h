@@ -215,6 +215,11 @@ gmp_status gmp_plan_info(const gmp_plan *plan, int32_t *n_features, int32_t *n_c
  *  adj_items:     work items per centre of the adjoint and Jacobian pair
  *                 kernels (equal pieces of the list; 0 = automatic: about
  *                 8,192 items over the batch, none shorter than chunk_pairs).
+ *  sigma_groups:  each forward work item (a chunk of a list) is split into
+ *                 this many work items, each taking one group of the cutoff
+ *                 slots in cutoff order (1..16, capped at the slot count;
+ *                 0 = 1); finer items for the persistent grid, the same
+ *                 features bit for bit.
  * The workspace size depends on the tuning.  Changing the tuning is not
  * thread-safe with concurrent calls on the plan. */
 typedef struct {
@@ -222,6 +227,7 @@ typedef struct {
   int32_t bin_divisor;
   int32_t blocks_per_cu;
   int32_t adj_items;             /* 0..64 */
+  int32_t sigma_groups;          /* 0..16 */
 } gmp_tuning;
 gmp_status gmp_plan_get_tuning(const gmp_plan *plan, gmp_tuning *out);
 gmp_status gmp_plan_set_tuning(gmp_plan *plan, const gmp_tuning *t);

@@ -46,7 +46,8 @@ class NbrDesc(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("chunk_pairs", c_i32), ("bin_divisor", c_i32), ("blocks_per_cu", c_i32), ("adj_items", c_i32)]
+    _fields_ = [("chunk_pairs", c_i32), ("bin_divisor", c_i32), ("blocks_per_cu", c_i32), ("adj_items", c_i32),
+                ("sigma_groups", c_i32)]
 
 
 class GMPError(RuntimeError):

@@ -1,6 +1,6 @@
-"""Autotuner of the library's tuning knobs (chunk size of the per-centre
-work items of the forward, cell-list bin size, persistent grid size, work
-items per centre of the adjoint).
+"""Autotuner of the library's tuning knobs (chunk size and cutoff-slot groups
+of the per-centre work items of the forward, cell-list bin size,
+persistent grid size, work items per centre of the adjoint).
 
 Candidates are timed with the HIP events the library records around its
 own launches on the current stream (neighbour build + forward, optionally
@@ -28,14 +28,14 @@ DEFAULT_CANDIDATES = [
     for c in (0, 512, 1024, 2048, 4096) for b in (2, 3, 4)
 ] + [dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=k, adj_items=0) for k in (1, 2)]
 
-# a whole forward + backward step: the forward's chunking and the cell-list
-# bins crossed with the adjoint's items per centre
+# a whole forward + backward step: the forward's chunking and slot groups
+# and the cell-list bins crossed with the adjoint's items per centre
 STEP_CANDIDATES = [
-    dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0, adj_items=a)
-    for c in (1024, 2048, 0) for b in (2, 3) for a in (0, 2)
-]
+    dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0, adj_items=a, sigma_groups=1)
+    for c in (2048, 0) for b in (2, 3) for a in (0, 2)
+] + [dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0, adj_items=0, sigma_groups=2) for c, b in ((2048, 2), (0, 3))]
 
-_DEFAULT = dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=0, adj_items=0)
+_DEFAULT = dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=0, adj_items=0, sigma_groups=1)
 
 
 def _full(cand: Dict) -> Dict:

@@ -535,6 +535,7 @@ gmp_status gmp_plan_create(const gmp_probe_desc *d, gmp_precision precision, gmp
   p->tuning.bin_divisor = 2;
   p->tuning.blocks_per_cu = 0;
   p->tuning.adj_items = 0;
+  p->tuning.sigma_groups = 1;
   *out = p;
   return GMP_OK;
 }
@@ -567,6 +568,7 @@ gmp_status gmp_plan_set_tuning(gmp_plan *p, const gmp_tuning *t) {
   if (t->bin_divisor < 1 || t->bin_divisor > 4) return set_error(GMP_E_INVALID, "bin_divisor must be 1..4");
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return set_error(GMP_E_INVALID, "blocks_per_cu must be 0..64");
   if (t->adj_items < 0 || t->adj_items > 64) return set_error(GMP_E_INVALID, "adj_items must be 0..64");
+  if (t->sigma_groups < 0 || t->sigma_groups > 16) return set_error(GMP_E_INVALID, "sigma_groups must be 0..16");
   p->tuning = *t;
   return GMP_OK;
 }

@@ -48,15 +48,15 @@ __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c
 // Chunks of one centre's list: fixed-size pieces of kc pairs (kc = 0: whole
 // list), so the decomposition of a centre depends on its own list only and
 // a batched launch sums in the same order as a launch over one structure.
-// Per list slot: the number of chunks of its list (fixed-size pieces of kc pairs,
-// kc = 0: whole list, so the decomposition of a centre depends on its own
-// list only and a batched launch sums in the same order as a launch over one
-// structure), its structure, and its wrapped position as an AoS double4 (one
-// 32-byte gather per neighbour).  The first thread also clears the work-item
-// counter.
+// Per list slot: the number of work items of its list (fixed-size pieces
+// of kc pairs, kc = 0: whole list, each split into ng groups of cutoff
+// slots, so the decomposition of a centre depends on its own list only and
+// a batched launch sums in the same order as a launch over one structure),
+// its structure, and its wrapped position as an AoS double4 (one 32-byte
+// gather per neighbour).  The first thread also clears the work-item counter.
 // Indices g < n_total get their structure and packed position; centres
 // c < n_centres their chunk count.
-__global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int kc, int64_t *nch, double4 *rw4,
+__global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int kc, int ng, int64_t *nch, double4 *rw4,
                                int32_t *astruct, unsigned long long *counter) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *counter = 0ull;
@@ -64,7 +64,7 @@ __global__ void k_overlap_prep(BatchDev bt, NbrDev nb, int kc, int64_t *nch, dou
     const int64_t cnt = nb.offsets[i + 1] - nb.offsets[i];
     // a list that ends past the capacity was not written (overflowed no-sync
     // build, reported in the status word): no work items, zero moments
-    nch[i] = nb.offsets[i + 1] > nb.capacity ? 0 : (kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1);
+    nch[i] = nb.offsets[i + 1] > nb.capacity ? 0 : ng * (kc > 0 ? (cnt > kc ? (cnt + kc - 1) / kc : 1) : 1);
   }
   if (i < n_total(bt)) {
     const int st = struct_of_index(bt, i);
@@ -177,7 +177,8 @@ __device__ inline void radial_from_table(const PlanDev &P, int s, int e, float q
 template <int LMAX, int KB, int MODE, bool LDS, bool DENS, bool SCREEN, bool TAB = false>
 __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanDev P, BatchDev bt, NbrDev nb, const double4 *rw4,
                                                  const int32_t *astruct, double *partial, const int64_t *chunk_off,
-                                                 int kc, unsigned long long *counter, const void *tab_global) {
+                                                 int kc, int ng, unsigned long long *counter,
+                                                 const void *tab_global) {
   constexpr bool F64 = MODE == ACC_F64;
   using TR = typename std::conditional<F64, double, float>::type;                 // radial arithmetic
   using TM = typename std::conditional<MODE == ACC_TWOSUM, float, double>::type;  // monomials
@@ -204,7 +205,12 @@ __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanD
     if (qc >= n_items) break;
     const int64_t k = centre_of_chunk(chunk_off, N, qc);  // list slot
     const int64_t i = nb.order[k];                         // its centre
-    const int c = (int)(qc - chunk_off[k]);
+    // item = (chunk c of the list, group g of the cutoff slots in cutoff
+    // order: passes [t0, t1)); every item writes all slots' moments, zero
+    // for the slots outside its group, so a centre's sum is the same for any ng
+    const int cg = (int)(qc - chunk_off[k]);
+    const int c = cg / ng, g = cg - c * ng;
+    const int t0 = g * S / ng, t1 = (g + 1) * S / ng;
     const int st = astruct[cb + i];
     const Cell9 cell = load_cell(bt.cell + 9 * (int64_t)st);
     const int pbc = bt.pbc[st] & 7;
@@ -224,22 +230,23 @@ __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanD
     auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
     auto pass_end = [&](int t) { return __builtin_amdgcn_readlane(end_lane, t); };
     double *dst_item = partial + (size_t)qc * S * NM;
-    // sigmas whose prefix misses this chunk contribute zero moments
+    // sigmas outside the item's group, or whose prefix misses this chunk,
+    // contribute zero moments
     for (int t = 0; t < S; ++t)
-      if (pass_end(t) <= clo)
+      if (t < t0 || t >= t1 || pass_end(t) <= clo)
         for (int m = lane; m < NM; m += kWave)
           dst_item[(size_t)__builtin_amdgcn_readlane(so_lane, t) * NM + m] = 0.0;
     // step iterator over (sigma pass t, pair block p0); pass ends are non-decreasing in t
-    int tb = 0, pb = clo;
-    while (tb < S && pass_end(tb) <= clo) ++tb;
-    if (tb >= S) continue;
+    int tb = t0, pb = clo;
+    while (tb < t1 && pass_end(tb) <= clo) ++tb;
+    if (tb >= t1) continue;
     int tc = tb, pc = pb;
     auto advance = [&](int &t, int &p) {
       p += kWave;
       if (p >= pass_end(t)) {
         ++t;
         p = clo;
-        while (t < S && pass_end(t) <= clo) ++t;
+        while (t < t1 && pass_end(t) <= clo) ++t;
       }
       t = uni(t);
       p = uni(p);
@@ -253,12 +260,12 @@ __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanD
       int32_t jb = ii;
       const int p = pb + lane;
       if (p < pass_end(tb)) { jb = nb.j[base + p]; wb = nb.shift[base + p]; }
-      if (tc < S && pc + lane < pass_end(tc)) { jc = nb.j[base + pc + lane]; wc = nb.shift[base + pc + lane]; }
+      if (tc < t1 && pc + lane < pass_end(tc)) { jc = nb.j[base + pc + lane]; wc = nb.shift[base + pc + lane]; }
       rb = rw4[jb];
     }
     Acc<MODE, NM> acc;
     acc.zero();
-    while (tb < S) {
+    while (tb < t1) {
       const int ta = tb, pa = pb;
       const int32_t w = wb;
       const double rjx = rb.x, rjy = rb.y, rjz = rb.z, occj = rb.w;  // w: occupancy of j
@@ -266,9 +273,9 @@ __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanD
       tb = tc; pb = pc; wb = wc;
       rb = rw4[jc];
       jc = ii; wc = 0;
-      if (tc < S) {
+      if (tc < t1) {
         advance(tc, pc);
-        if (tc < S && pc + lane < pass_end(tc)) { jc = nb.j[base + pc + lane]; wc = nb.shift[base + pc + lane]; }
+        if (tc < t1 && pc + lane < pass_end(tc)) { jc = nb.j[base + pc + lane]; wc = nb.shift[base + pc + lane]; }
       }
       // current step: slot sig_order[ta], pairs pa + lane
       const int sgm = __builtin_amdgcn_readlane(so_lane, ta);
@@ -482,7 +489,7 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
 }
 
 using OverlapFn = void (*)(PlanDev, BatchDev, NbrDev, const double4 *, const int32_t *, double *, const int64_t *,
-                           int, unsigned long long *, const void *);
+                           int, int, unsigned long long *, const void *);
 
 // DENS: the plan has the density slot of order -1; SCREEN: per-primitive
 // screening (separate instantiations keep both branches out of the loop of
@@ -561,10 +568,16 @@ void *noalloc_scratch(size_t *bytes, hipError_t *err) {
 
 int chunk_size(const gmp_plan *p) { return p->tuning.chunk_pairs > 0 ? p->tuning.chunk_pairs : 0; }
 
-// upper bound on the number of chunks of a batch with at most `pairs` pairs
+// groups of cutoff slots per chunk (each a work item of its own)
+int slot_groups(const gmp_plan *p) {
+  const int g = p->tuning.sigma_groups > 0 ? p->tuning.sigma_groups : 1;
+  return g < p->dev.S ? g : (p->dev.S > 0 ? p->dev.S : 1);
+}
+
+// upper bound on the number of work items of a batch with at most `pairs` pairs
 int64_t max_chunks(const gmp_plan *p, int64_t n_atoms, int64_t pairs) {
   const int kc = chunk_size(p);
-  return n_atoms + (kc > 0 ? pairs / kc + 1 : 0);
+  return (n_atoms + (kc > 0 ? pairs / kc + 1 : 0)) * slot_groups(p);
 }
 
 static int cus_cached() {
@@ -600,9 +613,9 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
                     int64_t *chunk_off, int64_t *scan_aux, unsigned long long *counter, double4 *rw4,
                     int32_t *astruct, int64_t pairs_bound, hipStream_t s) {
   const int64_t N = n_centres(bt), NT = n_total(bt);  // NT >= N
-  const int kc = chunk_size(p);
-  GMP_LAUNCH("overlap_prep", k_overlap_prep, dim3((unsigned)((NT + 255) / 256)), dim3(256), 0, s, bt, nb, kc, nch,
-             rw4, astruct, counter);
+  const int kc = chunk_size(p), ng = slot_groups(p);
+  GMP_LAUNCH("overlap_prep", k_overlap_prep, dim3((unsigned)((NT + 255) / 256)), dim3(256), 0, s, bt, nb, kc, ng,
+             nch, rw4, astruct, counter);
   scan_i64(nch, chunk_off, N, scan_aux, s);
   const bool f64 = p->prec == GMP_FP64;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
@@ -621,7 +634,7 @@ void launch_overlap(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, dou
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
   GMP_LAUNCH("overlap", fn, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, (const double4 *)rw4,
-             (const int32_t *)astruct, partial, chunk_off, kc, counter, tab);
+             (const int32_t *)astruct, partial, chunk_off, kc, ng, counter, tab);
 }
 
 void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const int64_t *chunk_off,

@@ -111,12 +111,13 @@ class GMPPlan:
         t = _lib.Tuning()
         check(_lib.load().gmp_plan_get_tuning(self._h, ctypes.byref(t)))
         return dict(chunk_pairs=t.chunk_pairs, bin_divisor=t.bin_divisor, blocks_per_cu=t.blocks_per_cu,
-                    adj_items=t.adj_items)
+                    adj_items=t.adj_items, sigma_groups=t.sigma_groups)
 
     def set_tuning(self, **kw):
         cur = self.get_tuning()
         cur.update(kw)
-        t = _lib.Tuning(cur["chunk_pairs"], cur["bin_divisor"], cur["blocks_per_cu"], cur["adj_items"])
+        t = _lib.Tuning(cur["chunk_pairs"], cur["bin_divisor"], cur["blocks_per_cu"], cur["adj_items"],
+                        cur["sigma_groups"])
         check(_lib.load().gmp_plan_set_tuning(self._h, ctypes.byref(t)))
 
     def workspace_bytes(self, n_structs, n_atoms, capacity, n_points=0) -> int:

@@ -95,6 +95,39 @@ def test_graph_replay_matches_eager(g, precision, split):
     assert not _same(F1, F0)
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_work_item_splits_give_the_same_features(g, prec):
+    """Splitting every forward work item into groups of cutoff slots
+    (sigma_groups) adds only exact zeros to a centre's sums: features and
+    components equal the unsplit ones bit for bit; a different adjoint split
+    (adj_items) keeps the gradients within the FP64 rounding of the order."""
+    b, probes = _batch(33)
+    plan = g.GMPPlan.from_probes(probes, prec)
+    db = g.DeviceBatch.from_batch(b)
+    ws = g.Workspace()
+    nb = g.build_neighbors(plan, db, ws)
+    G = torch.as_tensor(np.random.default_rng(34).standard_normal((b.n_atoms, probes.n_features)),
+                        device="cuda", dtype=plan.dtype)
+    F0, mu0 = g.features(plan, db, nb, ws)
+    gp0, gc0 = g.features_backward(plan, db, nb, ws, mu0, F0, G)
+    F0, mu0, gp0, gc0 = F0.clone(), mu0.clone(), gp0.clone(), gc0.clone()
+    for sg, chunk, adj in ((2, 2048, 0), (4, 64, 3), (16, 0, 1)):
+        plan.set_tuning(sigma_groups=sg, chunk_pairs=chunk, adj_items=adj)
+        F1, mu1 = g.features(plan, db, nb, ws)
+        if chunk == 2048:
+            assert _same(F1, F0) and _same(mu1, mu0)
+        gp1, gc1 = g.features_backward(plan, db, nb, ws, mu0, F0, G)
+        scale = max(gp0.abs().max().item(), gc0.abs().max().item())
+        tol = 1e-12 if prec == "fp64" else 1e-6
+        assert (gp1 - gp0).abs().max().item() <= tol * scale and (gc1 - gc0).abs().max().item() <= tol * scale
+    plan.set_tuning(sigma_groups=1, chunk_pairs=64, adj_items=0)
+    F2, mu2 = g.features(plan, db, nb, ws)
+    plan.set_tuning(sigma_groups=3)
+    F3, mu3 = g.features(plan, db, nb, ws)
+    torch.cuda.synchronize()
+    assert _same(F3, F2) and _same(mu3, mu2)
+
+
 def test_autotune_choice_and_cache(g, tmp_path):
     say("[autotune]")
     from paper_2303_12980_amd import autotune
@@ -103,9 +136,9 @@ def test_autotune_choice_and_cache(g, tmp_path):
     db = g.DeviceBatch.from_batch(b)
     ws = g.Workspace()
     cache = str(tmp_path / "tune.json")
-    cands = [dict(chunk_pairs=0, bin_divisor=2, blocks_per_cu=0, adj_items=0),
-             dict(chunk_pairs=256, bin_divisor=3, blocks_per_cu=0, adj_items=2),
-             dict(chunk_pairs=1024, bin_divisor=2, blocks_per_cu=2, adj_items=0)]
+    cands = [dict(chunk_pairs=0, bin_divisor=2, blocks_per_cu=0, adj_items=0, sigma_groups=1),
+             dict(chunk_pairs=256, bin_divisor=3, blocks_per_cu=0, adj_items=2, sigma_groups=2),
+             dict(chunk_pairs=1024, bin_divisor=2, blocks_per_cu=2, adj_items=0, sigma_groups=1)]
     r = autotune.autotune(plan, db, ws, candidates=cands, reps=2, cache_path=cache)
     assert not r["cached"] and len(r["tried"]) == 3
     assert r["tuning"] in cands and plan.get_tuning() == r["tuning"]
