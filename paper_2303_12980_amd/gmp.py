@@ -487,7 +487,7 @@ class CapturedStep:
         # later by a larger eager call on the same Workspace)
         self.ws_buf = ws.buf
         self._held = (ws.buf, nb.offsets, nb.j, nb.shift, nb.bucket_start, nb.sigma_end, nb.wrap, nb.rw,
-                      nb.reverse, batch.xyz, batch.cell, batch.species, batch.atom_offsets, batch.pbc,
+                      nb.reverse, nb.order, nb.slot, batch.xyz, batch.cell, batch.species, batch.atom_offsets, batch.pbc,
                       batch.occupancy, batch.point_offsets, batch.pxyz)
 
     def _run(self):
