@@ -283,8 +283,7 @@ __device__ inline int64_t cand_bin(const Cand &C, int v, int n[3], double rcmax2
 
 // Per-wavefront LDS scratch of the candidate enumeration.
 struct CandLds {
-  int pre[kWave];
-  int start[kWave];
+  int delta[kWave];  // bin start minus the bin's first flattened position
   int npk[kWave];
   double sh[3][kWave];
 };
@@ -294,7 +293,11 @@ struct CandLds {
 // taken 64 at a time (one per lane); their atoms are then flattened so that
 // consecutive lanes read consecutive atoms.  With several wavefronts on one
 // centre (wave w of nw), each wavefront takes every nw-th block of 64
-// flattened candidates of every chunk.
+// flattened candidates of every chunk.  The bin of flattened position c is
+// the last lane whose exclusive prefix pre is <= c: the prefixes grow with the
+// lane, so for a block starting at c0 it is the count of lanes with pre <= c0
+// less one, moved on past every non-empty bin that starts inside the block
+// (one or two for bins of tens of atoms).
 template <typename F>
 __device__ inline void for_each_candidate(const Cand &C, const int64_t *bin_start, double rcmax2, int w, int nw,
                                           CandLds &L, F &&f) {
@@ -320,8 +323,8 @@ __device__ inline void for_each_candidate(const Cand &C, const int64_t *bin_star
       if (lane >= o) incl += y;
     }
     const int tot = __shfl(incl, kWave - 1, kWave);
-    L.pre[lane] = incl - cnt;
-    L.start[lane] = start;
+    const int pre = incl - cnt;  // lanes past the last bin image: pre = tot
+    L.delta[lane] = start - pre;
     L.npk[lane] = npk;
     L.sh[0][lane] = shx;
     L.sh[1][lane] = shy;
@@ -329,30 +332,43 @@ __device__ inline void for_each_candidate(const Cand &C, const int64_t *bin_star
     wave_lds_sync();
     for (int c0 = w * kWave; c0 < tot; c0 += nw * kWave) {
       const int c = c0 + lane;
+      int own = __popcll(__ballot(pre <= c0)) - 1;
+      for (uint64_t starts = __ballot(cnt > 0 && pre > c0 && pre - c0 < kWave); starts; starts &= starts - 1) {
+        const int l = __builtin_ctzll(starts);
+        if (c >= __builtin_amdgcn_readlane(pre, l)) own = l;
+      }
       if (c < tot) {
-        int lo = 0, hi = kWave;  // largest lane with pre <= c
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (L.pre[mid] <= c) lo = mid; else hi = mid;
-        }
-        const int t = L.start[lo] + (c - L.pre[lo]);
-        const int pk = L.npk[lo];
+        const int t = c + L.delta[own];
+        const int pk = L.npk[own];
         const int n[3] = {(int)(int8_t)(pk & 0xff), (int)(int8_t)((pk >> 8) & 0xff), (int)(int8_t)((pk >> 16) & 0xff)};
-        f(t, n, L.sh[0][lo], L.sh[1][lo], L.sh[2][lo]);
+        f(t, n, L.sh[0][own], L.sh[1][own], L.sh[2][own]);
       }
     }
     wave_lds_sync();
   }
 }
 
-__device__ inline int shell_of(const PlanDev &P, double q) {
-  int sh = 0;
-  for (int s = 0; s < P.S; ++s) sh += (P.rc2[s] < q) ? 1 : 0;
-  return sh;
-}
+// Shell of a squared distance q: the number of cutoffs rc2[s] < q.  The
+// cutoffs sit in registers, padded to SM with +infinity, so the count is a
+// fixed run of compares against uniform operands.
+template <int SM>
+struct Shells {
+  double r[SM];
+  __device__ explicit Shells(const PlanDev &P) {
+#pragma unroll
+    for (int s = 0; s < SM; ++s) r[s] = s < P.S ? P.rc2[s] : __builtin_huge_val();
+  }
+  __device__ int of(double q) const {
+    int sh = 0;
+#pragma unroll
+    for (int s = 0; s < SM; ++s) sh += r[s] < q ? 1 : 0;
+    return sh;
+  }
+};
 
 // One workgroup per centre (centres in cell-list order): count neighbours
 // per (shell, species) bucket; the wavefronts share the centre's candidates.
+template <int SM>
 __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                                const double *fw, const int64_t *bin_start,
                                                const double *sx, const double *sy, const double *sz,
@@ -374,6 +390,7 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
   const int s = astruct[g];
   Cand C;
   cand_setup(C, info, bt, s, fw, g);
+  const Shells<SM> shells(P);
   const double rix = nb.rw[g], riy = nb.rw[N + g], riz = nb.rw[2 * N + g];
   for_each_candidate(C, bin_start, P.rcmax2, w, nw, lds_cand[w],
                      [&](int t, const int *n, double shx, double shy, double shz) {
@@ -381,7 +398,7 @@ __global__ __launch_bounds__(256) void k_count(PlanDev P, BatchDev bt, NbrDev nb
                        const double dy = (sy[t] - riy) + shy;
                        const double dz = (sz[t] - riz) + shz;
                        const double q = (dx * dx + dy * dy) + dz * dz;
-                       if (q <= P.rcmax2) atomicAdd(&c[shell_of(P, q) * P.E + ssp[t]], 1);
+                       if (q <= P.rcmax2) atomicAdd(&c[shells.of(q) * P.E + ssp[t]], 1);
                      });
   __syncthreads();
   int64_t tot = 0;
@@ -532,7 +549,7 @@ __device__ inline uint64_t make_key(int64_t j, int n1, int n2, int n3, int shell
 // to the long-list queue; RANGED = true fills range by range of consecutive
 // buckets that fit, enumerating the candidates once per range; a single
 // bucket longer than the sort leaves placeholders and is reported.
-template <bool RANGED>
+template <bool RANGED, int SM>
 __device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const NbrDev &nb, const StructInfo *info,
                                    const double *fw, const int64_t *bin_start, const double *sx, const double *sy,
                                    const double *sz, const int32_t *sid, const int32_t *ssp, const int32_t *astruct,
@@ -609,6 +626,7 @@ __device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const N
   const int s = astruct[g];
   Cand C;
   cand_setup(C, info, bt, s, fw, g);
+  const Shells<SM> shells(P);
   const double rix = nb.rw[g], riy = nb.rw[N + g], riz = nb.rw[2 * N + g];
   // buckets [b_lo, b_hi) whose entries fit the sort together (all of them
   // in the short-list kernel)
@@ -629,7 +647,7 @@ __device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const N
                          const double dz = (sz[t] - riz) + shz;
                          const double q = (dx * dx + dy * dy) + dz * dz;
                          if (q <= P.rcmax2) {
-                           const int sh = shell_of(P, q);
+                           const int sh = shells.of(q);
                            const int bk = sh * P.E + ssp[t];
                            if (!RANGED || (bk >= b_lo && bk < b_hi)) {
                              const int pos = atomicAdd(&cursor[bk], 1);
@@ -670,6 +688,7 @@ __device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const N
 
 // Short-list fill: one workgroup per centre, centres in cell-list order
 // (reference points in index order).
+template <int SM>
 __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                               const double *fw, const int64_t *bin_start,
                                               const double *sx, const double *sy, const double *sz,
@@ -682,13 +701,14 @@ __global__ __launch_bounds__(256) void k_fill(PlanDev P, BatchDev bt, NbrDev nb,
   __shared__ int32_t lds_bmax;
   const int64_t k = xcd_contiguous(blockIdx.x, gridDim.x);  // list slot
   const int64_t i = point_mode(bt) ? k : sid[k];
-  fill_centre<false>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
+  fill_centre<false, SM>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
                      pair_centre, pair_sum, abs_bstart, status, long_q, k, i, lds_u64, lds_cand, lds_bmax);
 }
 
 // Long-list fill: persistent workgroups take the queued centres one at a
 // time (status word 6 holds the queue length, word 7 the next entry); every
 // workgroup exits once the queue is drained, also when it is empty.
+template <int SM>
 __global__ __launch_bounds__(256) void k_fill_long(PlanDev P, BatchDev bt, NbrDev nb, const StructInfo *info,
                                                    const double *fw, const int64_t *bin_start,
                                                    const double *sx, const double *sy, const double *sz,
@@ -707,7 +727,7 @@ __global__ __launch_bounds__(256) void k_fill_long(PlanDev P, BatchDev bt, NbrDe
     const uint32_t q = lds_next;
     if (q >= nq) break;
     const int64_t k = long_q[q];
-    fill_centre<true>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
+    fill_centre<true, SM>(P, bt, nb, info, fw, bin_start, sx, sy, sz, sid, ssp, astruct, cnt, lds_keys, pair_key,
                       pair_centre, pair_sum, abs_bstart, status, long_q, k, point_mode(bt) ? k : sid[k], lds_u64,
                       lds_cand, lds_bmax);
     __syncthreads();  // lds_next, the keys and the bucket starts are reused
@@ -805,7 +825,8 @@ void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const
   int64_t blocks = n_centres(bt);
   if (blocks == 0) return;
   size_t smem = sizeof(int32_t) * p->dev.E * p->dev.S;
-  GMP_LAUNCH("nbr_count", k_count, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo, L.fw,
+  auto kern = p->dev.S <= 8 ? k_count<8> : k_count<kMaxSigmas>;
+  GMP_LAUNCH("nbr_count", kern, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo, L.fw,
              L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, L.ptotal, L.status);
 }
 
@@ -824,13 +845,15 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
   if (n_centres(bt) == 0) return;
   uint64_t *pk = (nb.reverse && !point_mode(bt)) ? L.pair_key : (uint64_t *)nullptr;
   size_t smem = sizeof(uint64_t) * lds_keys + sizeof(int32_t) * (2 * nbk + 2);
-  GMP_LAUNCH("nbr_fill_sort", k_fill, dim3((unsigned)n_centres(bt)), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
+  auto kern = p->dev.S <= 8 ? k_fill<8> : k_fill<kMaxSigmas>;
+  GMP_LAUNCH("nbr_fill_sort", kern, dim3((unsigned)n_centres(bt)), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
              L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, lds_keys, pk, L.pair_centre,
              L.pair_sum, L.abs_bstart, L.status, L.long_q);
   if (long_keys > 0) {  // one workgroup per CU (its LDS takes most of the CU's), capped by the centre count
     smem = sizeof(uint64_t) * long_keys + sizeof(int32_t) * (2 * nbk + 2);
     const int64_t blocks = n_centres(bt) < 256 ? n_centres(bt) : 256;
-    GMP_LAUNCH("nbr_fill_long", k_fill_long, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
+    auto kern_long = p->dev.S <= 8 ? k_fill_long<8> : k_fill_long<kMaxSigmas>;
+    GMP_LAUNCH("nbr_fill_long", kern_long, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
                L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, long_keys, pk, L.pair_centre,
                L.pair_sum, L.abs_bstart, L.status, L.long_q);
   }
