@@ -116,7 +116,8 @@ def other_workloads(g, gs, torch, steps=5, warmup=2):
         nb = g.build_neighbors(plan, db, ws)
         G = torch.as_tensor(np.random.default_rng(7).standard_normal((batch.n_atoms, probes.n_features)),
                             device="cuda")
-        fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G)
+        split = bool(tune.get("concurrent_reverse", False))
+        fb = g.CapturedStep(plan, db, ws, nb, backward=True, G=G, concurrent_reverse=split)
         nbf = g.build_neighbors(plan, db, ws, reverse=False)
         fo = g.CapturedStep(plan, db, ws, nbf, backward=False)
         for _ in range(warmup):
@@ -127,11 +128,13 @@ def other_workloads(g, gs, torch, steps=5, warmup=2):
         g.check_status(ws)
         af = batch.n_atoms * probes.n_features
         out[name] = {"workload": label, "atoms": batch.n_atoms, "features_per_atom": probes.n_features,
-                     "pairs": int(nb.n_pairs), "tuning": dict(tune["tuning"], searched=not tune["cached"]),
+                     "pairs": int(nb.n_pairs),
+                     "tuning": dict(tune["tuning"], searched=not tune["cached"], concurrent_reverse=split),
                      "fwd_bwd_ms": t_fb, "fwd_ms": t_fo,
                      "atoms_features_per_s_fwd_bwd": af / (t_fb * 1e-3), "atoms_features_per_s_fwd": af / (t_fo * 1e-3)}
         print(f"[bench] {name}: {batch.n_atoms} atoms, {nb.n_pairs} pairs (generated in {gen_s:.1f}s), tuning "
-              f"{tune['tuning']}: fwd+bwd {t_fb:.2f} ms, fwd {t_fo:.2f} ms", file=sys.stderr, flush=True)
+              f"{tune['tuning']}, reverse search on a second stream: {split}: fwd+bwd {t_fb:.2f} ms, "
+              f"fwd {t_fo:.2f} ms", file=sys.stderr, flush=True)
         del fb, fo, nb, nbf, ws, db, G
         torch.cuda.empty_cache()
     return out
@@ -591,10 +594,15 @@ def main():
         w = g.Workspace(dev)
         tune = autotune.autotune(plan, db, w, candidates=autotune.STEP_CANDIDATES, backward=True, reps=3,
                                  cache_path=TUNE_CACHE)
-        tunings[prec] = dict(tune["tuning"], step_ms=tune["ms"])
+        tunings[prec] = dict(tune["tuning"], step_ms=tune["ms"],
+                             concurrent_reverse=bool(tune.get("concurrent_reverse", False)))
+        for k in ("graph_ms_one_stream", "graph_ms_two_streams"):
+            if k in tune:
+                tunings[prec][k] = tune[k]
         how = "cached" if tune["cached"] else ("search off: defaults" if tune["ms"] is None else "searched")
         tunings[prec]["how"] = how
-        print(f"[bench] {prec} autotuned {tune['tuning']} ({how})", file=sys.stderr, flush=True)
+        print(f"[bench] {prec} autotuned {tune['tuning']}, reverse search on a second stream: "
+              f"{tunings[prec]['concurrent_reverse']} ({how})", file=sys.stderr, flush=True)
         nb = g.build_neighbors(plan, db, w)
         return plan, w, nb
 
@@ -637,7 +645,8 @@ def main():
         r["eager_fwd_ms"] = wall_ms(lambda: eager_step(plan, w, nbf, False), args.steps, args.warmup)
         if not args.no_split:
             r["eager_split_fwd_bwd_ms"] = wall_ms(lambda: eager_step(plan, w, nb, True, True), args.steps, args.warmup)
-        fb = g.CapturedStep(plan, db, w, nb, backward=True, G=G)
+        fb = g.CapturedStep(plan, db, w, nb, backward=True, G=G,
+                            concurrent_reverse=tunings[prec]["concurrent_reverse"])
         r["graph_fwd_bwd_ms"] = wall_ms(fb.replay, args.steps, args.warmup)
         fo = g.CapturedStep(plan, db, w, nbf, backward=False)
         r["graph_fwd_ms"] = wall_ms(fo.replay, args.steps, args.warmup)

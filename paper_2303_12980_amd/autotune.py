@@ -1,6 +1,10 @@
 """Autotuner of the library's tuning knobs (chunk size and cutoff-slot groups
 of the per-centre work items of the forward, cell-list bin size,
-persistent grid size, work items per centre of the adjoint).
+persistent grid size, work items per centre of the adjoint), and, for a
+forward + backward step, whether a captured step runs the reverse-pair
+search on a second stream beside the forward (`concurrent_reverse` of
+CapturedStep: it pays where that search is long and bound by memory
+latency, as on the 100,000-atom cell, and costs where it is short).
 
 Candidates are timed with the HIP events the library records around its
 own launches on the current stream (neighbour build + forward, optionally
@@ -89,10 +93,41 @@ def _time_config(plan, batch, ws, G, reps: int, backward: bool) -> float:
     return sum(v[1] for v in pr.result.values()) / reps
 
 
+def _graph_ms(plan, batch, ws, G, split: bool, reps: int) -> float:
+    """Wall time of one replay of a captured forward + backward step."""
+    nb = _g.build_neighbors(plan, batch, ws)
+    st = _g.CapturedStep(plan, batch, ws, nb, backward=True, G=G, concurrent_reverse=split)
+    for _ in range(2):
+        st.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def choose_concurrent_reverse(plan, batch, ws, G, step_ms: float) -> Dict:
+    """Time captured fwd + bwd steps with the reverse-pair search on the
+    forward's stream and on a second stream (two rounds each, the faster
+    round counts); the second stream is chosen when it is at least 2%
+    faster."""
+    reps = int(min(50, max(3, 100.0 / max(step_ms, 1e-3))))
+    t = {False: [], True: []}
+    for _ in range(2):
+        for split in (False, True):
+            t[split].append(_graph_ms(plan, batch, ws, G, split, reps))
+    one, two = min(t[False]), min(t[True])
+    return dict(concurrent_reverse=bool(two < 0.98 * one), graph_ms_one_stream=one, graph_ms_two_streams=two)
+
+
 def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backward: bool = True,
-             reps: int = 3, cache_path: Optional[str] = None, force: bool = False) -> Dict:
-    """Pick and set the fastest tuning for this plan and batch shape.
-    Returns {"tuning": ..., "ms": ..., "key": ..., "cached": bool, "tried": [...]}."""
+             reps: int = 3, cache_path: Optional[str] = None, force: bool = False, streams: bool = True) -> Dict:
+    """Pick and set the fastest tuning for this plan and batch shape; with
+    backward and streams, also time the captured step on one and on two
+    streams (see choose_concurrent_reverse).
+    Returns {"tuning": ..., "ms": ..., "key": ..., "cached": bool, "tried": [...]}
+    plus "concurrent_reverse" (and the two graph times) when streams were timed."""
     path = cache_path or _cache_path()
     nb = _g.build_neighbors(plan, batch, ws)
     key = tuning_key(plan, batch, nb, backward)
@@ -114,7 +149,10 @@ def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backw
         if best is None or ms < best[1]:
             best = (cand, ms)
     plan.set_tuning(**best[0])
-    entry = dict(tuning=best[0], ms=best[1], search_s=time.time() - t0)
+    entry = dict(tuning=best[0], ms=best[1])
+    if backward and streams and batch.n_points == 0:  # reference points keep no reverse index
+        entry.update(choose_concurrent_reverse(plan, batch, ws, G, best[1]))
+    entry["search_s"] = time.time() - t0
     cache[key] = entry
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -143,11 +143,15 @@ def test_autotune_choice_and_cache(g, tmp_path):
     assert not r["cached"] and len(r["tried"]) == 3
     assert r["tuning"] in cands and plan.get_tuning() == r["tuning"]
     assert r["ms"] == min(t["ms"] for t in r["tried"])
+    # the captured step was timed on one and on two streams, and the choice follows the 2% rule
+    assert r["graph_ms_one_stream"] > 0 and r["graph_ms_two_streams"] > 0
+    assert r["concurrent_reverse"] == (r["graph_ms_two_streams"] < 0.98 * r["graph_ms_one_stream"])
     with open(cache) as f:
         assert r["key"] in json.load(f)
     plan2 = g.GMPPlan.from_probes(probes, "fp32c")
     r2 = autotune.autotune(plan2, db, ws, candidates=cands, cache_path=cache)
     assert r2["cached"] and plan2.get_tuning() == r["tuning"]
+    assert r2["concurrent_reverse"] == r["concurrent_reverse"]
     nb = g.build_neighbors(plan2, db, ws)
     F, _ = g.features(plan2, db, nb, ws)
     Fref = oracle.features_batch(b, probes)
