@@ -8,7 +8,9 @@ latency, as on the 100,000-atom cell, and costs where it is short).
 
 Candidates are timed with the HIP events the library records around its
 own launches on the current stream (neighbour build + forward, optionally
-the adjoint), the fastest is set on the plan, and the choice is cached in
+the adjoint); a candidate displaces the best so far only when it is more
+than 1% faster (the first candidate is the default: differences within
+run-to-run noise keep it), the choice is set on the plan and cached in
 a JSON file keyed by the device, the precision, the probe shape (l_max,
 sigmas, species, largest primitive count per element) and log2 buckets of
 the atom count and of the mean list length.
@@ -40,6 +42,7 @@ STEP_CANDIDATES = [
 ] + [dict(chunk_pairs=c, bin_divisor=b, blocks_per_cu=0, adj_items=0, sigma_groups=2) for c, b in ((2048, 2), (0, 3))]
 
 _DEFAULT = dict(chunk_pairs=2048, bin_divisor=2, blocks_per_cu=0, adj_items=0, sigma_groups=1)
+_MARGIN = 0.01  # a later candidate must be this much faster than the best so far
 
 
 def _full(cand: Dict) -> Dict:
@@ -146,7 +149,7 @@ def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backw
         plan.set_tuning(**cand)
         ms = _time_config(plan, batch, ws, G, reps, backward)
         tried.append(dict(tuning=cand, ms=ms))
-        if best is None or ms < best[1]:
+        if best is None or ms < (1.0 - _MARGIN) * best[1]:
             best = (cand, ms)
     plan.set_tuning(**best[0])
     entry = dict(tuning=best[0], ms=best[1])

@@ -142,7 +142,12 @@ def test_autotune_choice_and_cache(g, tmp_path):
     r = autotune.autotune(plan, db, ws, candidates=cands, reps=2, cache_path=cache)
     assert not r["cached"] and len(r["tried"]) == 3
     assert r["tuning"] in cands and plan.get_tuning() == r["tuning"]
-    assert r["ms"] == min(t["ms"] for t in r["tried"])
+    # the choice: a candidate displaces the best so far only when more than 1% faster
+    best = r["tried"][0]
+    for t in r["tried"][1:]:
+        if t["ms"] < 0.99 * best["ms"]:
+            best = t
+    assert r["tuning"] == best["tuning"] and r["ms"] == best["ms"]
     # the captured step was timed on one and on two streams, and the choice follows the 2% rule
     assert r["graph_ms_one_stream"] > 0 and r["graph_ms_two_streams"] > 0
     assert r["concurrent_reverse"] == (r["graph_ms_two_streams"] < 0.98 * r["graph_ms_one_stream"])
