@@ -144,9 +144,12 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
   const int S = P.S, E = P.E;
   const T *__restrict__ tabg = (const T *)tab_global;
   T *tabl = (T *)lds_dyn;
-  const int tab_n = LDS ? S * E * KB * kCoefStride : 0;
+  // LDS copy with a 16-byte gap after every (slot, element) block: lanes of
+  // different species then read their rows from different banks
+  constexpr int BLK = KB * kCoefStride, BLKL = BLK + 16 / (int)sizeof(T);
+  const int tab_n = LDS ? S * E * BLKL : 0;
   if (LDS)
-    for (int idx = threadIdx.x; idx < tab_n; idx += blockDim.x) tabl[idx] = tabg[idx];
+    for (int idx = threadIdx.x; idx < S * E * BLK; idx += blockDim.x) tabl[(idx / BLK) * BLKL + idx % BLK] = tabg[idx];
   for (int e = threadIdx.x; e < E; e += blockDim.x) lds_k[e] = P.kcount[e];
   __syncthreads();
   const int lane = lane_id();
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(PlanDev P, BatchDev bt, NbrDe
       for (int s = 0; s < S; ++s) {
         const int ends = __builtin_amdgcn_readlane(end_lane, s);
         if (!(act && p < ends)) continue;
-        const size_t roff = ((size_t)(s * E + e) * KB) * kCoefStride;
+        const size_t roff = (size_t)(s * E + e) * (LDS ? BLKL : BLK);
         const T *bc = (const T *)__builtin_assume_aligned(bcoef + (size_t)s * NB, 16);
         if (s == dens) {  // local density: v = 2 rho'(q) W d, rho'(q) = sum_k B (-beta) e_k
           T cp0 = (T)0;
@@ -584,7 +587,8 @@ void launch_backward(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
   const int64_t n_items = N * (int64_t)C;
   const size_t tab_bytes = (size_t)p->dev.S * p->dev.E * p->dev.kb * kCoefStride * (f64 ? 8 : 4);
   const bool use_lds = tab_bytes <= 48 * 1024;
-  const size_t tsm = (use_lds ? tab_bytes : 0) + 4 * (size_t)p->dev.S * coef_block(p->dev.lmax) * (f64 ? 8 : 4);
+  const size_t tsm = (use_lds ? tab_bytes + (size_t)p->dev.S * p->dev.E * 16 : 0) +  // table with its gaps
+                     4 * (size_t)p->dev.S * coef_block(p->dev.lmax) * (f64 ? 8 : 4);
   const void *tab = f64 ? (const void *)p->dev.coef64 : (const void *)p->dev.coef32;
   const bool scr = p->dev.screen != 0;
   PairsFn fn = f64 ? (use_lds ? pick_pairs<true, true>(p->dev.lmax, p->dev.kb, scr)
