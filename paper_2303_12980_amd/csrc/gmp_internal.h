@@ -323,7 +323,7 @@ struct WsLayout {
   uint64_t *pair_key;     // [capacity] packed (j, n) of every pair (reverse search)
   int32_t *pair_centre;   // [capacity] centre of every pair (reverse search)
   uint64_t *pair_sum;     // [capacity/16 + 1] every 16th packed key (first level of the reverse search)
-  int64_t *abs_bstart;    // [N][S*E+1] bucket starts as global pair indices (reverse search)
+  int64_t *abs_bstart;    // [N][S*E+1] bucket starts as global pair indices, a row per atom (reverse search)
   // reference points: pairs sorted by neighbour atom (adjoint gather order)
   uint32_t *tr_key_in, *tr_key_out, *tr_val_in, *tr_val_out;  // [capacity] radix-sort ping-pong buffers
   int32_t *tr_hist;       // [256 * tiles] per-tile digit counts

@@ -599,7 +599,7 @@ __device__ inline void fill_centre(const PlanDev &P, const BatchDev &bt, const N
   if (!RANGED && !overflow && total > lds_keys) return;  // the long-list kernel writes this centre
   for (int b = tid; b <= nbk; b += blockDim.x) {
     nb.bucket_start[k * (nbk + 1) + b] = bstart[b];
-    if (pair_key) abs_bstart[k * (nbk + 1) + b] = base + bstart[b];
+    if (pair_key) abs_bstart[i * (nbk + 1) + b] = base + bstart[b];  // row of the atom: one probe less
   }
   for (int s = tid; s < P.S; s += blockDim.x) nb.sigma_end[k * P.S + s] = bstart[(P.rank_lt[s] + 1) * P.E];
   if (overflow) return;  // consumers skip centres whose list ends past the capacity
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(256) void k_reverse(PlanDev P, BatchDev bt, NbrDev 
   int ei = bt.species[i];
   ei = ei < 0 ? 0 : (ei >= P.E ? P.E - 1 : ei);
   const int b = h * P.E + ei;  // the mirror has the same q, hence the same shell
-  const int64_t *ab = abs_bstart + (int64_t)nb.slot[j] * (nbk + 1);  // j's list slot
+  const int64_t *ab = abs_bstart + (int64_t)j * (nbk + 1);  // j's bucket starts (rows by atom)
   const int64_t A = ab[b], Z = ab[b + 1];  // the bucket as global pair indices
   const uint64_t key = make_key(i, -n1, -n2, -n3, h);
   // two levels: the every-16th keys that fall inside the bucket (one or two
