@@ -414,6 +414,10 @@ __global__ __launch_bounds__(256, MODE == ACC_WIDE ? 3 : 1) void k_overlap(PlanD
 // components with the exact integer matrices, then the weighted norm
 // F_{l,s} = sqrt(sum_abc l!/(a!b!c!) mu_abc^2).  Order -1 takes the degree-0
 // moment of the density slot as its component rho and |rho| as its feature.
+// Where every component and feature comes from (order, slot, position) is
+// decoded once per workgroup into LDS tables, so the per-centre loops are
+// table reads and dot products; the partials of a centre with one work item
+// (the common case) are read directly.
 template <int LMAX, bool F64OUT>
 __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const double *partial,
                                                 const int64_t *chunk_off, const int32_t *order, void *features,
@@ -423,67 +427,95 @@ __global__ __launch_bounds__(256) void k_finish(PlanDev P, int64_t N, const doub
   // staged in LDS once per workgroup (read with lane-varying indices)
   __shared__ double lds_T[kTmat];
   __shared__ double lds_w[nmono(kMaxL)];
+  constexpr int NM = nmono(LMAX);  // compile-time: the index splits below are not divisions
+  const int S = P.S, NC = P.ncomp_total, NF = P.nf;
+  // decode tables after the four wavefronts' moment and component buffers:
+  // component t: T row offset | moment offset << 10 | length << 22 (bit 31:
+  // the density component, moment offset only); feature t: component offset |
+  // weight offset << 12 | length << 20 (bit 31: the density feature)
+  int32_t *cdec = (int32_t *)(lds_f + (size_t)4 * (S * NM + NC));
+  int32_t *fdec = cdec + NC;
   for (int t = threadIdx.x; t < kTmat; t += blockDim.x) lds_T[t] = P.T[t];
   for (int t = threadIdx.x; t < nmono(kMaxL); t += blockDim.x) lds_w[t] = P.weight[t];
+  for (int t = threadIdx.x; t < NC; t += blockDim.x) {
+    int o = 0;
+    while (o + 1 < P.n_orders && P.comp_off[o + 1] <= t) ++o;
+    const int l = P.orders[o];
+    if (l < 0) {
+      cdec[t] = (int32_t)(0x80000000u | (uint32_t)((P.dens_slot * NM) << 10));
+    } else {
+      const int nc = ncomp(l), r = t - P.comp_off[o];
+      const int sl = r / nc, cc = r - sl * nc;
+      cdec[t] = (P.toff[l] + cc * nc) | ((sl * NM + doff(l)) << 10) | (nc << 22);
+    }
+  }
+  for (int t = threadIdx.x; t < NF; t += blockDim.x) {
+    int o = 0;
+    while (o + 1 < P.n_orders && P.feat_off[o + 1] <= t) ++o;
+    const int l = P.orders[o];
+    if (l < 0) {
+      fdec[t] = (int32_t)(0x80000000u | (uint32_t)P.comp_off[o]);
+    } else {
+      const int nc = ncomp(l);
+      fdec[t] = (P.comp_off[o] + (t - P.feat_off[o]) * nc) | (doff(l) << 12) | (nc << 20);
+    }
+  }
   __syncthreads();
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;  // list slot
-  constexpr int NM = nmono(LMAX);  // compile-time: the index splits below are not divisions
-  const int S = P.S;
-  double *mom = lds_f + (size_t)w * (S * NM + P.ncomp_total);
+  double *mom = lds_f + (size_t)w * (S * NM + NC);
   double *mu = mom + S * NM;
   const bool live = i < N;
   const int64_t row = live ? order[i] : 0;  // the slot's centre: its row of the outputs
   if (live) {
+    const int64_t q0 = chunk_off[i], q1 = chunk_off[i + 1];
     for (int t = lane; t < S * NM; t += kWave) {
       const int s = t / NM, m = t - s * NM;
       double a = 0.0;
       if (s == P.dens_slot ? m == 0 : ((P.order_mask >> kMT.deg[m]) & 1)) {
-        const int64_t q1 = chunk_off[i + 1];
-        for (int64_t q = chunk_off[i]; q < q1; ++q) a += partial[((size_t)q * S + s) * NM + m];
+        if (q1 - q0 == 1) {
+          a = partial[((size_t)q0 * S + s) * NM + m];
+        } else {
+          for (int64_t q = q0; q < q1; ++q) a += partial[((size_t)q * S + s) * NM + m];
+        }
       }
       mom[t] = a;
     }
   }
   wave_lds_sync();
   if (live) {
-    for (int t = lane; t < P.ncomp_total; t += kWave) {
-      int o = 0;
-      while (o + 1 < P.n_orders && P.comp_off[o + 1] <= t) ++o;
-      const int l = P.orders[o];
+    for (int t = lane; t < NC; t += kWave) {
+      const int32_t d = cdec[t];
       double v = 0.0;
-      if (l < 0) {
-        v = mom[P.dens_slot * NM];
+      if (d < 0) {
+        v = mom[(d >> 10) & 0xfff];
       } else {
-        const int nc = ncomp(l);
-        const int r = t - P.comp_off[o];
-        const int s = r / nc, cc = r - s * nc;
-        const double *Tl = lds_T + P.toff[l] + cc * nc;
-        const double *ms = mom + s * NM + doff(l);
+        const int nc = (d >> 22) & 0xf;
+        const double *Tl = lds_T + (d & 0x3ff);
+        const double *ms = mom + ((d >> 10) & 0xfff);
         for (int mm = 0; mm < nc; ++mm) v += Tl[mm] * ms[mm];
       }
       mu[t] = v;
-      if (components) components[(size_t)row * P.ncomp_total + t] = v;
+      if (components) components[(size_t)row * NC + t] = v;
     }
   }
   wave_lds_sync();
   if (live) {
-    for (int t = lane; t < P.nf; t += kWave) {
-      int o = 0;
-      while (o + 1 < P.n_orders && P.feat_off[o + 1] <= t) ++o;
-      const int l = P.orders[o];
+    for (int t = lane; t < NF; t += kWave) {
+      const int32_t d = fdec[t];
       double F;
-      if (l < 0) {
-        F = fabs(mu[P.comp_off[o]]);
+      if (d < 0) {
+        F = fabs(mu[d & 0xfff]);
       } else {
-        const int s = t - P.feat_off[o], nc = ncomp(l);
-        const double *mv = mu + P.comp_off[o] + s * nc;
+        const int nc = (d >> 20) & 0xf;
+        const double *mv = mu + (d & 0xfff);
+        const double *wl = lds_w + ((d >> 12) & 0xff);
         double a = 0.0;
-        for (int cc = 0; cc < nc; ++cc) a += lds_w[doff(l) + cc] * mv[cc] * mv[cc];
+        for (int cc = 0; cc < nc; ++cc) a += wl[cc] * mv[cc] * mv[cc];
         F = sqrt(a);
       }
-      if (F64OUT) ((double *)features)[(size_t)row * P.nf + t] = F;
-      else ((float *)features)[(size_t)row * P.nf + t] = (float)F;
+      if (F64OUT) ((double *)features)[(size_t)row * NF + t] = F;
+      else ((float *)features)[(size_t)row * NF + t] = (float)F;
     }
   }
 }
@@ -641,7 +673,8 @@ void launch_finish(const gmp_plan *p, int64_t N, const double *partial, const in
                    const int32_t *order, void *features, double *components, hipStream_t s) {
   if (N == 0) return;
   const int NM = nmono(p->dev.lmax);
-  size_t smem = sizeof(double) * 4 * (size_t)(p->dev.S * NM + p->dev.ncomp_total);
+  size_t smem = sizeof(double) * 4 * (size_t)(p->dev.S * NM + p->dev.ncomp_total) +
+                sizeof(int32_t) * (size_t)(p->dev.ncomp_total + p->dev.nf);  // + the decode tables
   int64_t blocks = (N + 3) / 4;
   using FinishFn = void (*)(PlanDev, int64_t, const double *, const int64_t *, const int32_t *, void *, double *);
   static const FinishFn fns[2][kMaxL + 1] = {
