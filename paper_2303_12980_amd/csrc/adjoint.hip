@@ -37,7 +37,10 @@ __device__ inline double fma_(double a, double b, double c) { return fma(a, b, c
 
 
 // One wavefront per index: centres get their coefficients, every index
-// (atoms, and reference points) its structure and packed position.
+// (atoms, and reference points) its structure and packed position.  The
+// centre's components are staged in LDS, and where every feature and every
+// (slot, monomial) coefficient comes from is decoded once per workgroup
+// into LDS tables.
 template <int LMAX, bool F64>
 __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev nb, const double *components,
                                                   const void *grad_features, void *bcoef, double4 *rw4,
@@ -49,17 +52,56 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   // staged in LDS once per workgroup (read with lane-varying indices)
   __shared__ double lds_T[kTmat];
   __shared__ double lds_w[nmono(kMaxL)];
-  for (int t = threadIdx.x; t < kTmat; t += blockDim.x) lds_T[t] = P.T[t];
-  for (int t = threadIdx.x; t < nmono(kMaxL); t += blockDim.x) lds_w[t] = P.weight[t];
-  __syncthreads();
-  const int w = threadIdx.x / kWave, lane = lane_id();
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
   // block sizes are compile-time constants (the index splits below are then
   // multiplications, not integer divisions)
   constexpr int NM = nmono(LMAX), NB = coef_block(LMAX);
-  const int S = P.S;
-  double *scale = lds_b + (size_t)w * (P.nf + S * NM);  // [nf]
-  double *M = scale + P.nf;                               // [S][NM]
+  const int S = P.S, NC = P.ncomp_total, NF = P.nf;
+  // decode tables after the four wavefronts' buffers.  Feature t: component
+  // offset | weight offset << 12 | length << 20 (bit 31: the density
+  // feature).  Coefficient (s, m): component offset | T column << 12 |
+  // length << 22, or bit 31 alone (zero: order not requested, or a density
+  // slot moment past degree 0), or bit 31 | bit 30 | component offset (the
+  // density coefficient); mfeat: its feature | weight offset << 12.
+  int32_t *fdec = (int32_t *)(lds_b + (size_t)4 * (NF + S * NM + NC));
+  int32_t *mdec = fdec + NF;
+  int32_t *mfeat = mdec + S * NM;
+  for (int t = threadIdx.x; t < kTmat; t += blockDim.x) lds_T[t] = P.T[t];
+  for (int t = threadIdx.x; t < nmono(kMaxL); t += blockDim.x) lds_w[t] = P.weight[t];
+  for (int t = threadIdx.x; t < NF; t += blockDim.x) {
+    int o = 0;
+    while (o + 1 < P.n_orders && P.feat_off[o + 1] <= t) ++o;
+    const int l = P.orders[o];
+    if (l < 0) {
+      fdec[t] = (int32_t)(0x80000000u | (uint32_t)P.comp_off[o]);
+    } else {
+      const int nc = ncomp(l);
+      fdec[t] = (P.comp_off[o] + (t - P.feat_off[o]) * nc) | (doff(l) << 12) | (nc << 20);
+    }
+  }
+  for (int t = threadIdx.x; t < S * NM; t += blockDim.x) {
+    const int sl = t / NM, m = t - sl * NM;
+    const int l = kMT.deg[m];
+    int32_t d = (int32_t)0x80000000u, f = 0;
+    if (sl == P.dens_slot) {
+      if (m == 0) {
+        const int o = P.dens_order;
+        d = (int32_t)(0xC0000000u | (uint32_t)P.comp_off[o]);
+        f = P.feat_off[o];
+      }
+    } else if (P.order_idx[l] >= 0) {
+      const int o = P.order_idx[l], nc = ncomp(l), mm = m - doff(l);
+      d = (P.comp_off[o] + sl * nc) | ((P.toff[l] + mm) << 12) | (nc << 22);
+      f = (P.feat_off[o] + sl) | (doff(l) << 12);
+    }
+    mdec[t] = d;
+    mfeat[t] = f;
+  }
+  __syncthreads();
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + w;
+  double *scale = lds_b + (size_t)w * (NF + S * NM + NC);  // [nf]
+  double *M = scale + NF;                                  // [S][NM]
+  double *mus = M + S * NM;                                // [ncomp_total] the centre's components
   const bool live = i < N;
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0ull;  // work items of the pair kernel
   // AoS wrapped position (one 32-byte gather per neighbour in the pair kernel)
@@ -68,24 +110,27 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
     astruct[i] = st;
     rw4[i] = wrapped_position(bt, nb, i, st);
   }
-  const double *mu = components + (size_t)i * P.ncomp_total;
   if (live) {
-    for (int t = lane; t < P.nf; t += kWave) {
-      int o = 0;
-      while (o + 1 < P.n_orders && P.feat_off[o + 1] <= t) ++o;
-      const int l = P.orders[o];
+    const double *mu = components + (size_t)i * NC;
+    for (int t = lane; t < NC; t += kWave) mus[t] = mu[t];
+  }
+  wave_lds_sync();
+  if (live) {
+    for (int t = lane; t < NF; t += kWave) {
+      const int32_t d = fdec[t];
       double F;
-      if (l < 0) {
-        F = fabs(mu[P.comp_off[o]]);
+      if (d < 0) {
+        F = fabs(mus[d & 0xfff]);
       } else {
-        const int s = t - P.feat_off[o], nc = ncomp(l);
-        const double *mv = mu + P.comp_off[o] + s * nc;
+        const int nc = (d >> 20) & 0xf;
+        const double *mv = mus + (d & 0xfff);
+        const double *wl = lds_w + ((d >> 12) & 0xff);
         double a = 0.0;
-        for (int cc = 0; cc < nc; ++cc) a += lds_w[doff(l) + cc] * mv[cc] * mv[cc];
+        for (int cc = 0; cc < nc; ++cc) a += wl[cc] * mv[cc] * mv[cc];
         F = sqrt(a);
       }
       // unit upstream gradient (grad_features null): the coefficients of dF/dd per feature
-      const double G = grad_features ? (double)((const T *)grad_features)[(size_t)i * P.nf + t] : 1.0;
+      const double G = grad_features ? (double)((const T *)grad_features)[(size_t)i * NF + t] : 1.0;
       scale[t] = F > 0.0 ? G / F : 0.0;
     }
   }
@@ -93,21 +138,18 @@ __global__ __launch_bounds__(256) void k_bwd_coef(PlanDev P, BatchDev bt, NbrDev
   if (live) {
     // M_{s,m} = sum_abc W_abc T_l[abc][m],  W_abc = scale w_abc mu_abc
     for (int t = lane; t < S * NM; t += kWave) {
-      const int s = t / NM, m = t - s * NM;
-      const int l = kMT.deg[m];
+      const int32_t d = mdec[t];
+      const int32_t f = mfeat[t];
       double v = 0.0;
-      if (s == P.dens_slot) {
-        const int o = P.dens_order;
-        if (m == 0) v = mu[P.comp_off[o]] * scale[P.feat_off[o]];
+      if (d < 0) {
+        if (d & 0x40000000) v = mus[d & 0xfff] * scale[f & 0xfff];  // density coefficient
       } else {
-        int o = -1;
-        for (int oo = 0; oo < P.n_orders; ++oo) if (P.orders[oo] == l) o = oo;
-        if (o >= 0) {
-          const int nc = ncomp(l), mm = m - doff(l);
-          const double *mv = mu + P.comp_off[o] + s * nc;
-          for (int cc = 0; cc < nc; ++cc) v += lds_w[doff(l) + cc] * mv[cc] * lds_T[P.toff[l] + cc * nc + mm];
-          v *= scale[P.feat_off[o] + s];
-        }
+        const int nc = (d >> 22) & 0xf;
+        const double *mv = mus + (d & 0xfff);
+        const double *Tc = lds_T + ((d >> 12) & 0x3ff);
+        const double *wl = lds_w + ((f >> 12) & 0xff);
+        for (int cc = 0; cc < nc; ++cc) v += wl[cc] * mv[cc] * Tc[cc * nc];
+        v *= scale[f & 0xfff];
       }
       M[t] = v;
     }
@@ -559,7 +601,9 @@ void launch_bwd_coef(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, co
                      const void *grad_features, const WsLayout &L, hipStream_t s) {
   const int64_t blocks_all = (n_total(bt) + 3) / 4;
   if (blocks_all == 0) return;
-  size_t smem = sizeof(double) * 4 * (size_t)(p->dev.nf + p->dev.S * nmono(p->dev.lmax));
+  const size_t sm = (size_t)p->dev.S * nmono(p->dev.lmax);
+  size_t smem = sizeof(double) * 4 * ((size_t)p->dev.nf + sm + p->dev.ncomp_total) +
+                sizeof(int32_t) * ((size_t)p->dev.nf + 2 * sm);  // + the decode tables
   using CoefFn = void (*)(PlanDev, BatchDev, NbrDev, const double *, const void *, void *, double4 *, int32_t *,
                           unsigned long long *);
   static const CoefFn fns[2][kMaxL + 1] = {
