@@ -451,12 +451,18 @@ def batched_vs_per_structure(g, gs, torch):
     per_structure()
     per_ms = _median_ms(per_structure, 3, torch)
     g.check_status(ws)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record()
-    step.replay()
-    ev[1].record()
-    torch.cuda.synchronize()
-    graph_event_ms = ev[0].elapsed_time(ev[1])
+    # HIP events around single replays (after two warm-up replays): median of 10
+    for _ in range(2):
+        step.replay()
+    ev_ms = []
+    for _ in range(10):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        step.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ev_ms.append(ev[0].elapsed_time(ev[1]))
+    graph_event_ms = float(np.median(ev_ms))
     bitwise = bool(torch.equal(Fp, Fb)) and bool(torch.equal(mup, mub))
     N, nf = batch.n_atoms, probes.n_features
     return {
