@@ -80,6 +80,19 @@ def _load(path):
         return {}
 
 
+def choose(tried, margin: float = None) -> int:
+    """Index of the chosen candidate among [{"ms": ...}, ...] in search
+    order: a candidate displaces the best so far only when it is faster by
+    more than `margin` (default 1%), so the first (the default tuning) keeps
+    its place against differences within run-to-run noise."""
+    margin = _MARGIN if margin is None else margin
+    best = None
+    for i, t in enumerate(tried):
+        if best is None or t["ms"] < (1.0 - margin) * tried[best]["ms"]:
+            best = i
+    return best
+
+
 def _time_config(plan, batch, ws, G, reps: int, backward: bool) -> float:
     nb = _g.build_neighbors(plan, batch, ws)
     for _ in range(2):  # warm: grows the workspace, fills occupancy caches
@@ -151,10 +164,8 @@ def autotune(plan, batch, ws, candidates: Optional[Iterable[Dict]] = None, backw
             plan.set_tuning(**cand)
             times[c].append(_time_config(plan, batch, ws, G, reps, backward))
     tried = [dict(tuning=cand, ms=min(t)) for cand, t in zip(cands, times)]
-    best = None
-    for t in tried:
-        if best is None or t["ms"] < (1.0 - _MARGIN) * best[1]:
-            best = (t["tuning"], t["ms"])
+    b = choose(tried)
+    best = (tried[b]["tuning"], tried[b]["ms"])
     plan.set_tuning(**best[0])
     entry = dict(tuning=best[0], ms=best[1])
     if backward and streams and batch.n_points == 0:  # reference points keep no reverse index
