@@ -349,8 +349,8 @@ __device__ inline void for_each_candidate(const Cand &C, const int64_t *bin_star
 }
 
 // Shell of a squared distance q: the number of cutoffs rc2[s] < q.  The
-// cutoffs sit in registers, padded to SM with +infinity, so the count is a
-// fixed run of compares against uniform operands.
+// cutoffs sit in registers, padded to SM (8, 12 or 16) with +infinity, so
+// the count is a fixed run of compares against uniform operands.
 template <int SM>
 struct Shells {
   double r[SM];
@@ -842,7 +842,7 @@ void launch_count(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const
   int64_t blocks = n_centres(bt);
   if (blocks == 0) return;
   size_t smem = sizeof(int32_t) * p->dev.E * p->dev.S;
-  auto kern = p->dev.S <= 8 ? k_count<8> : k_count<kMaxSigmas>;
+  auto kern = p->dev.S <= 8 ? k_count<8> : (p->dev.S <= 12 ? k_count<12> : k_count<kMaxSigmas>);
   GMP_LAUNCH("nbr_count", kern, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo, L.fw,
              L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, L.ptotal, L.status);
 }
@@ -862,14 +862,14 @@ void launch_fill(const gmp_plan *p, const BatchDev &bt, const NbrDev &nb, const 
   if (n_centres(bt) == 0) return;
   uint64_t *pk = (nb.reverse && !point_mode(bt)) ? L.pair_key : (uint64_t *)nullptr;
   size_t smem = sizeof(uint64_t) * lds_keys + sizeof(int32_t) * (2 * nbk + 2);
-  auto kern = p->dev.S <= 8 ? k_fill<8> : k_fill<kMaxSigmas>;
+  auto kern = p->dev.S <= 8 ? k_fill<8> : (p->dev.S <= 12 ? k_fill<12> : k_fill<kMaxSigmas>);
   GMP_LAUNCH("nbr_fill_sort", kern, dim3((unsigned)n_centres(bt)), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
              L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, lds_keys, pk, L.pair_centre,
              L.pair_sum, L.abs_bstart, L.status, L.long_q);
   if (long_keys > 0) {  // one workgroup per CU (its LDS takes most of the CU's), capped by the centre count
     smem = sizeof(uint64_t) * long_keys + sizeof(int32_t) * (2 * nbk + 2);
     const int64_t blocks = n_centres(bt) < 256 ? n_centres(bt) : 256;
-    auto kern_long = p->dev.S <= 8 ? k_fill_long<8> : k_fill_long<kMaxSigmas>;
+    auto kern_long = p->dev.S <= 8 ? k_fill_long<8> : (p->dev.S <= 12 ? k_fill_long<12> : k_fill_long<kMaxSigmas>);
     GMP_LAUNCH("nbr_fill_long", kern_long, dim3((unsigned)blocks), dim3(256), smem, s, p->dev, bt, nb, L.sinfo,
                L.fw, L.bin_start, L.sx, L.sy, L.sz, L.sid, L.ssp, L.astruct, L.cnt, long_keys, pk, L.pair_centre,
                L.pair_sum, L.abs_bstart, L.status, L.long_q);
