@@ -87,7 +87,13 @@ enum AccMode { ACC_F64 = 0, ACC_TWOSUM = 1, ACC_WIDE = 2 };
 
 // Per-lane accumulator of one sigma's moments.
 template <int MODE, int NM> struct Acc;
-// FP32 (hi, lo) pairs updated with Knuth's error-free two-sum.
+// FP32 (hi, lo) pairs updated with an error-free sum: Dekker's Fast2Sum
+// on the two addends ordered by magnitude (exact when the first is the
+// larger).  It yields the same exact rounding error, hence the same (hi,
+// lo), as Knuth's branch-free two-sum, in as many operations (a compare on
+// magnitudes, two selects, three additions), but reads the old sum only
+// before the new one is formed, so the new sum takes its register without a
+// copy back.
 template <int NM> struct Acc<ACC_TWOSUM, NM> {
   float hi[NM], lo[NM];
   __device__ void zero() {
@@ -95,10 +101,10 @@ template <int NM> struct Acc<ACC_TWOSUM, NM> {
     for (int m = 0; m < NM; ++m) { hi[m] = 0.f; lo[m] = 0.f; }
   }
   __device__ void add(int m, float p) {
-    const float s = hi[m] + p;
-    const float bp = s - hi[m];
-    const float ap = s - bp;
-    lo[m] += (hi[m] - ap) + (p - bp);
+    const bool ge = __builtin_fabsf(hi[m]) >= __builtin_fabsf(p);
+    const float big = ge ? hi[m] : p, small = ge ? p : hi[m];
+    const float s = big + small;
+    lo[m] += small - (s - big);
     hi[m] = s;
   }
   __device__ double value(int m) const { return (double)hi[m] + (double)lo[m]; }
